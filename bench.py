@@ -1,0 +1,261 @@
+#!/usr/bin/env python
+"""BSPAI-GMRES-IR on one MI355X: solves/s and bucketed M-apply bandwidth.
+
+A step is one full gmres_ir_solve (Algorithm 4 after the SPAI build: x_0,
+refinement residuals in double-double, left-preconditioned MGS-GMRES with the
+bucketed SPAI applied in FP32, updates) on the 256 x 256 upwind
+convection-diffusion system (n = 65,536, Peclet 50), SPAI on the pattern of
+A^2 built in FP64, buckets {fp64, fp32, fp16, bf16} at eps_b = 1e-4,
+b = A x_true.  A, M and b are resident on the GPU before timing starts.
+
+Printed (one JSON line): solves/s, the solver kernel's roofline (algorithmic
+bytes / kernel time measured with HIP events on its stream), the CPU oracle
+timed on the host, the all-FP64 SPAI-GMRES-IR comparator at equal stopping
+tolerance, and the bucketed apply's HBM bandwidth on a cold 2.1M-row operator.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1, 5: 0}
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def solve_bytes(stats, n, nnz_a, mstats, vt_bytes=4, x0_fp64_nnz=None):
+    """Algorithmic HBM bytes of one gmres_ir_solve (each array touched once per use).
+
+    Per GMRES iteration j (0-based): A_p v (vt nnz + 4 nnz + 4 (n+1) + 2 vt n),
+    M_b w (sum_k nnz_k (b_k + 4) + 4 (n+1) per stored bucket + 2 vt n), MGS
+    reads v_0..v_j and z and writes v_{j+1}: (j + 3) vt n.  Per correction:
+    residual 12 nnz + 4 (n+1) + 16 n (A in FP64 with columns, b, x) + vt n,
+    s = M_b r, d = V y (its vt n) and x += d (16 n).  Start: ||A|| (12 nnz),
+    x_0 = M b with the FP64 M (12 nnz_M + 16 n + 4 (n+1)).
+    """
+    rp = 4 * (n + 1)
+    mb = sum(c * (VALUE_BYTES[p] + 4) for c, p in zip(mstats["count"], mstats["precs"]) if p != 5)
+    mb += rp * sum(1 for c, p in zip(mstats["count"], mstats["precs"]) if c > 0 and p != 5) + 2 * vt_bytes * n
+    ap = (vt_bytes + 4) * nnz_a + rp + 2 * vt_bytes * n
+    total = 12 * nnz_a + rp
+    nnz_m = x0_fp64_nnz if x0_fp64_nnz is not None else sum(mstats["count"])
+    total += 12 * nnz_m + rp + 16 * n
+    for its in stats["its"]:
+        total += 12 * nnz_a + rp + 16 * n + vt_bytes * n  # residual
+        total += mb  # s = M_b r
+        for j in range(its):
+            total += ap + mb + (j + 3) * vt_bytes * n
+        total += its * vt_bytes * n + 16 * n
+    total += 12 * nnz_a + rp + 16 * n  # final residual
+    return total
+
+
+def _src_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(kernel_src):
+    """HBM traffic per launch from the committed rocprofv3 counter runs, only if
+    they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "solve_kernel_traffic.json")
+    try:
+        with open(p) as f:
+            t = json.load(f)
+        if t.get("source_sha256_16") == _src_hash(kernel_src):
+            return t.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eps", type=float, default=1e-4)
+    ap.add_argument("--gmres-max", type=int, default=150)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-apply-bench", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the solver is one persistent kernel per "
+                                   "system; run with --gpus 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2307_03914_amd as B
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = "cuda"
+    _log("generating workload")
+    c = W.config("2")
+    A, P = c["A"], c["P"]
+    n = A.n
+    Ad = B.CSRMatrix.from_host(A)
+    Pd = B.CSRMatrix.from_host(P)
+    b = torch.as_tensor(c["b"], device=dev)
+    precs = c["precs"]
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=args.gmres_max, i_max=20)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = B.build(Ad, Pd, eps=args.eps, precs=precs)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    mst = h.stats()
+    _log(f"built M: counts {mst['count']} storage {mst['storage_pct']:.1f}% in {build_ms:.1f} ms")
+
+    for _ in range(args.warmup):
+        x, st = B.solve(Ad, b, h, **kw)
+    torch.cuda.synchronize()
+    B.set_profiling(True)
+    kernel_ms = []
+    stats = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, stats = B.solve(Ad, b, h, **kw)
+        kernel_ms.append(B.last_solve_kernel_ms())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    B.set_profiling(False)
+    ms_per_step = elapsed * 1e3 / args.steps
+    solves_per_s = args.steps / elapsed
+    xh = x.cpu().numpy()
+    fwd = float(np.abs(xh - c["x_true"]).max() / np.abs(c["x_true"]).max())
+    _log(f"BSPAI: {solves_per_s:.2f} solves/s, its {stats['its']}, relres {stats['relres'][-1]:.2e}")
+
+    kern_ms = float(np.mean(kernel_ms))
+    nbytes = solve_bytes(stats, n, A.nnz, mst)
+    kernel_src = os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "solve.hip")
+    roofline = {"kernel": "k_gmres_ir (persistent solver)", "bound": "hbm",
+                "achieved": nbytes / (kern_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": nbytes / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic(kernel_src),
+                "algorithmic_bytes": nbytes, "kernel_ms": kern_ms}
+
+    out = {"metric": "GMRES-IR solves/s & M-apply HBM GB/s, BSPAI vs fp64 SPAI at equal backward error",
+           "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"convdiff2d 256x256 upwind Pe=50 (n=65536), SPAI pattern(A^2) FP64, "
+                                  f"buckets fp64/fp32/fp16/bf16 eps={args.eps:g}, u_g=u_p=fp32, u_r=double-double, "
+                                  f"tau=1e-4, refine to 1e-10 rel. residual, GMRES cap {args.gmres_max}",
+                      "n": n, "nnz_A": A.nnz, "nnz_M": int(sum(mst["count"])), "bucket_counts": mst["count"],
+                      "storage_pct": mst["storage_pct"]},
+           "solve": {"its": stats["its"], "its_total": stats["its_total"], "relres": stats["relres"][-1],
+                     "eta": stats["eta"][-1], "forward_error": fwd, "build_ms": build_ms},
+           "roofline": roofline}
+
+    if not args.no_comparators:
+        # all-FP64 SPAI-GMRES-IR (u_g = u_p = fp64, tau = 1e-8, one fp64 bucket) at the same stopping test,
+        # and the fp64 M with FP32 Krylov (isolates the effect of bucketing)
+        comps = {}
+        h64 = B.build(Ad, Pd, eps=2.0 ** -53, precs=["fp64"])
+        for name, hh, extra in (("spai_fp64_all", h64, dict(u_g="fp64", tau=1e-8)),
+                                ("spai_fp64M_fp32krylov", h64, {})):
+            k2 = dict(kw)
+            k2.update(extra)
+            for _ in range(2):
+                x2, s2 = B.solve(Ad, b, hh, **k2)
+            reps = max(3, args.steps // 4)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                x2, s2 = B.solve(Ad, b, hh, **k2)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            comps[name] = {"solves_per_s": reps / el, "its": s2["its"], "relres": s2["relres"][-1],
+                           "eta": s2["eta"][-1]}
+            _log(f"{name}: {reps / el:.2f} solves/s its {s2['its']}")
+        h64.free()
+        out["comparators"] = comps
+
+    if not args.no_apply_bench:
+        out["m_apply"] = apply_bench(B, W, torch, np)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, args.eps, kw)
+
+    print(json.dumps(out), flush=True)
+
+
+def apply_bench(B, W, torch, np):
+    """bspai_apply on the 128^3 anisotropic operator (n = 2,097,152, M on the
+    pattern of A, all entries in the bf16 bucket at eps = 1e-2), cold in HBM:
+    the product rotates over 8 copies of M and of x/y (about 0.9 GB)."""
+    _log("apply bench: building 128^3 operator")
+    c = W.config("4a")
+    A = c["A"]
+    Ad = B.CSRMatrix.from_host(A)
+    h0 = B.build(Ad, B.CSRMatrix.from_host(c["P"]), eps=1e-2, precs=c["precs"], build_T=False, keep_fp64_M=True)
+    ex = h0.export()
+    h0.free()
+    M = W.CSR(A.n, c["P"].row_ptr, c["P"].col, ex["m64"])
+    Md = B.CSRMatrix.from_host(M)
+    copies = 8
+    hs = [B.import_m(Md, 1e-2, c["precs"], build_T=False, keep_fp64_M=False) for _ in range(copies)]
+    st = hs[0].stats()
+    n = A.n
+    xs = [torch.randn(n, device="cuda", dtype=torch.float32) for _ in range(copies)]
+    ys = [torch.empty(n, device="cuda", dtype=torch.float32) for _ in range(copies)]
+    nb = sum(1 for cc, p in zip(st["count"], st["precs"]) if cc > 0 and p != 5)
+    bytes_per = sum(cc * (VALUE_BYTES[p] + 4) for cc, p in zip(st["count"], st["precs"]) if p != 5)
+    bytes_per += 4 * (n + 1) * nb + 4 * n + 4 * n
+    for i in range(copies):
+        B.apply(hs[i], xs[i], ys[i])
+    torch.cuda.synchronize()
+    reps = 200
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for r in range(reps):
+        B.apply(hs[r % copies], xs[r % copies], ys[r % copies])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    for hh in hs:
+        hh.free()
+    gbs = bytes_per / (ms * 1e-3) / 1e9
+    _log(f"apply: {ms * 1e3:.1f} us per launch, {gbs:.0f} GB/s")
+    return {"workload": "aniso3d 128^3 7-point (n=2097152), M on pattern(A), bf16 bucket (eps=1e-2), fp32 x/y, "
+                        "8 rotating copies (cold HBM)", "bucket_counts": st["count"], "us_per_launch": ms * 1e3,
+            "algorithmic_bytes": bytes_per, "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
+            "bytes_per_nnz": bytes_per / max(1, sum(st["count"]))}
+
+
+def cpu_baseline(c, eps, kw):
+    """The CPU oracle (plain C, OpenMP over rows, sequential dot products) on
+    the same workload: one full solve from the FP64 SPAI (SPAI build not timed)."""
+    import oracle as O
+    import workloads as W
+
+    A, P = c["A"], c["P"]
+    threads = O.num_threads(0)
+    st, Mv, _ = O.spai(A, P)
+    M = W.CSR(A.n, P.row_ptr, P.col, Mv)
+    Mb = O.Bucketed(M, eps, c["precs"])
+    t0 = time.perf_counter()
+    res = O.gmres_ir(A, M, Mb, c["b"], **kw)
+    el = time.perf_counter() - t0
+    _log(f"oracle: {el:.1f} s per solve on {threads} threads, its {res['its']}")
+    return {"value": 1.0 / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one full solve of the same workload (its {res['its']}, {el:.1f} s)",
+            "eta": res["eta"][-1]}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * bspai.h -- C interface of the MI355X BSPAI-GMRES-IR library (libbspai.so).
+ *
+ * Method: Khan & Carson, "Mixed Precision Iterative Refinement with Adaptive
+ * Precision Sparse Approximate Inverse Preconditioning" (arXiv 2307.03914).
+ * The library builds a sparse approximate inverse M of A on a prescribed
+ * pattern (Algorithm 1 without pattern augmentation, run on A^T and
+ * transposed as in Algorithm 4, step 1), splits M's entries by magnitude into
+ * precision buckets (Algorithm 2, intervals of eq. (nint)), applies the
+ * bucketed M (Algorithm 3) and solves A x = b with GMRES-based iterative
+ * refinement preconditioned by it (Algorithm 4).
+ *
+ * Conventions
+ *  - Matrices are square CSR, 0-based, int32 row pointers and column indices
+ *    (column indices sorted ascending within a row, no duplicates), FP64
+ *    values.  nnz fields are int64 but must fit in int32 row pointers.
+ *  - Every pointer inside bspai_csr / bspai_pattern and every vector argument
+ *    is DEVICE memory on the current HIP device, owned by the caller, and is
+ *    only read (or, for outputs, written) during the call / the stream work
+ *    it enqueues.  Host pointers are named *_host.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *  - Functions return BSPAI_OK (0) or a negative status; a message for the
+ *    last failure of the calling thread is available from bspai_last_error().
+ *    Nothing throws across this interface.
+ */
+#ifndef BSPAI_H
+#define BSPAI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage precisions of the buckets (Table 2 of the paper plus bfloat16 and
+ * OCP FP8 E4M3FN).  BSPAI_DROP is the pseudo-precision with unit roundoff 1
+ * whose entries are discarded (Section 4, the choice u_q = 1). */
+typedef enum {
+    BSPAI_FP64 = 0,
+    BSPAI_FP32 = 1,
+    BSPAI_FP16 = 2,
+    BSPAI_BF16 = 3,
+    BSPAI_FP8_E4M3 = 4,
+    BSPAI_DROP = 5
+} bspai_prec;
+
+enum {
+    BSPAI_OK = 0,
+    BSPAI_EINVAL = -1,   /* bad argument: sizes, unsorted or duplicate precisions, DROP not last, q > 6 */
+    BSPAI_ENOMEM = -2,   /* device or host allocation failed */
+    BSPAI_EHIP = -3,     /* HIP runtime error (including a solver synchronisation timeout) */
+    BSPAI_EZEROROW = -4, /* a row of M would be zero: k is not in the shadow of its pattern (Section 4) */
+    BSPAI_ERANK = -5,    /* a reduced least-squares problem is rank deficient */
+    BSPAI_ENOCONV = -6,  /* i_max refinement steps without meeting a tolerance; x and stats are valid */
+    BSPAI_ENAN = -7      /* a NaN or infinity appeared in the residual */
+};
+
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *row_ptr; /* [n+1] */
+    const int32_t *col;     /* [nnz] */
+    const double *val;      /* [nnz] */
+} bspai_csr;
+
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *row_ptr; /* [n+1] */
+    const int32_t *col;     /* [nnz] */
+} bspai_pattern;
+
+typedef struct {
+    int build_T;     /* also pack (M_b)^T, needed by bspai_apply_T and the transposed solve */
+    int keep_fp64_M; /* keep the unbucketed FP64 M on the device (x_0 = M b, Algorithm 4 step 2) */
+    int scale;       /* one-sided column scaling of A^T before the least squares (Section 4) */
+} bspai_opts;
+
+typedef struct bspai_handle bspai_handle;
+
+/*
+ * bspai_build -- SPAI of A on the pattern P, then bucketing.
+ *   Row k of M solves min || e_k(I) - A^T(I, J) m ||_2 with J = P(k,:) and
+ *   I the shadow { i : sum_{j in J} |a_{ji}| != 0 } (eq. (redprob) for A^T;
+ *   Algorithm 1's least-squares steps with no augmentation), in FP64 by
+ *   Householder QR.  Then ||M||_inf, the thresholds t_k = fl(eps_b ||M||_inf)/u_k
+ *   and the buckets of eq. (nint); entries are stored in their bucket's format
+ *   (fp16 and fp8 with a power-of-two per-bucket scale).
+ *   A, P: device CSR (P NULL means the pattern of A).  precs[0..q-1]: host
+ *   array, strictly increasing unit roundoff (fp64 < fp32 < fp16 < bf16 <
+ *   fp8 < drop), DROP only last, 1 <= q <= 6.  opts may be NULL (defaults:
+ *   build_T = 1, keep_fp64_M = 1, scale = 0).  On success *out owns device
+ *   memory until bspai_free.  Synchronises `stream`.
+ *   Errors: EINVAL, ENOMEM, EHIP, EZEROROW, ERANK (no handle is returned).
+ */
+int bspai_build(const bspai_csr *A, const bspai_pattern *P, double eps_b, const bspai_prec *precs, int q,
+                const bspai_opts *opts, bspai_handle **out, void *stream);
+
+/*
+ * bspai_import -- bucket an externally computed FP64 M (device CSR) exactly as
+ * bspai_build does after its least squares (Algorithm 2 and the storage).
+ *   Same precision rules, options and ownership as bspai_build; M is copied.
+ */
+int bspai_import(const bspai_csr *M, double eps_b, const bspai_prec *precs, int q, const bspai_opts *opts,
+                 bspai_handle **out, void *stream);
+
+/*
+ * bspai_apply -- Y = M_b X (Algorithm 3 with the storage precision of each
+ * bucket decoupled from the arithmetic): every stored value is decoded
+ * exactly, the partial sum of each bucket is accumulated in FP32 (FP64 for
+ * the fp64 bucket and for xy_prec = FP64), and the partials are added from
+ * the least to the most precise bucket in FP64 before rounding to xy_prec.
+ *   x, y: device arrays of n x nrhs values of type xy_prec (BSPAI_FP32 or
+ *   BSPAI_FP64), row-major with leading dimension ld >= nrhs (ignored for
+ *   nrhs = 1); x and y must not overlap.  Asynchronous on `stream`.
+ */
+int bspai_apply(const bspai_handle *M, const void *x, void *y, int nrhs, int64_t ld, bspai_prec xy_prec,
+                void *stream);
+
+/* bspai_apply_T -- Y = (M_b)^T X with the same stored values and bucket
+ * assignment as bspai_apply (the handle must be built with build_T). */
+int bspai_apply_T(const bspai_handle *M, const void *x, void *y, int nrhs, int64_t ld, bspai_prec xy_prec,
+                  void *stream);
+
+typedef struct {
+    bspai_prec u_g; /* GMRES working precision, also the precision u_p of products with A: FP32 or FP64 */
+    int ur_dd;      /* 1: residual r = b - A x in double-double (for u_r ~ u^2); 0: FP64 */
+    double tau;     /* GMRES relative tolerance on the preconditioned residual */
+    double tol_rr;  /* stop when ||r||_inf / ||b||_inf <= tol_rr */
+    double tol_be;  /* stop when ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) <= tol_be */
+    int i_max;      /* at most this many refinement corrections (<= 64) */
+    int gmres_max;  /* at most this many GMRES iterations per correction; capped at min(n, 184),
+                       the size whose rotated Hessenberg matrix stays on chip */
+    int x0_mode;    /* 0: x_0 = M b with the FP64 M; 1: with M_b; 2: x_0 = 0; 3: x holds x_0 on entry */
+    int trans;      /* 1: solve A^T x = b with (M_b)^T as a right preconditioner (adjoint solve) */
+} gmres_ir_tol;
+
+typedef struct {
+    int steps;       /* GMRES calls (corrections) made */
+    int its_total;   /* total GMRES iterations */
+    int stop_reason; /* 1 relres, 2 backward error, 3 stagnation, 4 i_max, 5 NaN */
+    int status;      /* status code of this right-hand side */
+    int its[64];     /* GMRES iterations per correction */
+    double eta[65];  /* normwise backward error before each correction and at the end */
+    double relres[65];
+} gmres_ir_stats;
+
+/*
+ * gmres_ir_solve -- BSPAI-GMRES-IR (Algorithm 4) on one GPU.
+ *   x_0 per x0_mode; then, per step i: r_i = b - A x_i (FP64 or double-double,
+ *   stored FP64), stopping tests, left-preconditioned MGS-GMRES on
+ *   M_b A d = M_b r_i in u_g with A rounded to u_g (right-preconditioned
+ *   A^T M_b^T for trans = 1) to relative tolerance tau, x_{i+1} = x_i + d_i in FP64.
+ *   Stops on tol_rr, tol_be, stagnation of ||d_i||/||x_{i+1}|| (more than half
+ *   the previous ratio after the first correction) or i_max.
+ *   A: device CSR; b, x: device FP64 arrays of n x nrhs, row-major (nrhs in
+ *   {1, 2, 4, ..., 64}); st_host: host array of nrhs stats (or NULL).
+ *   M: handle from bspai_build / bspai_import (keep_fp64_M for x0_mode 0,
+ *   build_T for trans).  Synchronises `stream`; returns ENOCONV / ENAN when
+ *   some right-hand side ends that way (x is still written).
+ */
+int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
+                   double *x, int nrhs, gmres_ir_stats *st_host, void *stream);
+
+typedef struct {
+    int32_t n;
+    int32_t q;
+    int64_t nnz;             /* entries of M (all buckets, dropped included) */
+    bspai_prec precs[6];
+    int64_t count[6];        /* entries per bucket */
+    double threshold[6];     /* t_k = fl(eps_b ||M||_inf) / u_k */
+    double scale[6];         /* power-of-two storage scale of each bucket */
+    double norm_inf;         /* ||M||_inf of the FP64 M */
+    double eps_b;
+    int64_t bytes_values;    /* bytes of stored values */
+    int64_t bytes_indices;   /* bytes of column indices and per-bucket row pointers */
+    double storage_pct;      /* values of M_b as % of all nnz stored in u_1 (dropped: 0 B) */
+} bspai_bucket_stats;
+
+/* bspai_stats -- bucket occupancy and storage of a handle (host struct). */
+int bspai_stats(const bspai_handle *M, bspai_bucket_stats *out_host);
+
+/*
+ * bspai_export -- copy per-entry data back to the host in the CSR order of M:
+ * bucket id (0-based) and stored value (decoded and scaled, 0 when dropped)
+ * and, if kept, the FP64 M.  Any pointer may be NULL.  Synchronous.
+ */
+int bspai_export(const bspai_handle *M, int8_t *bucket_host, double *stored_host, double *m64_host);
+
+/*
+ * bspai_grad_vals -- gradient of a scalar loss with respect to the values of A
+ * for the solution of A x = b: with lambda = A^{-T} dL/dx (a solve with
+ * trans = 1), dL/da_ij = -lambda_i x_j.  Writes out[e] for every entry e of A's
+ * pattern in CSR order.  lam, x: device FP64 [n]; out: device FP64 [nnz].
+ * Asynchronous on `stream`.
+ */
+int bspai_grad_vals(const bspai_pattern *A, const double *lam, const double *x, double *out, void *stream);
+
+/*
+ * Instrumentation: with profiling on, gmres_ir_solve records HIP events on its
+ * stream around its solver kernel; bspai_last_solve_kernel_ms returns the
+ * elapsed time of the last such kernel in milliseconds (0 if none).
+ */
+void bspai_set_profiling(int on);
+double bspai_last_solve_kernel_ms(void);
+
+/* bspai_free -- release a handle (NULL is ignored).  Waits for the device. */
+void bspai_free(bspai_handle *M);
+
+/* bspai_last_error -- message of the last failure on the calling thread. */
+const char *bspai_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSPAI_H */

@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wno-unused-function", SRC, "-o", OUT + ".tmp", "-lm"]
+           "-fno-fast-math", "-Wall", "-Wno-unused-function", "-Wno-maybe-uninitialized", SRC, "-o", OUT + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

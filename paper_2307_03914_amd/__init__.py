@@ -1,0 +1,279 @@
+"""BSPAI-GMRES-IR on MI355X: Python binding of ``libbspai.so``.
+
+Argument marshalling only: every step of the method runs in the HIP library
+(``csrc/``); PyTorch provides device memory and the current stream.  The
+functions mirror the C interface in ``include/bspai.h``:
+
+* :func:`build` / :func:`import_m` -> :class:`Handle` (``bspai_build`` /
+  ``bspai_import``): SPAI of A on a pattern (FP64 Householder least squares,
+  run on A^T and transposed), then bucketing of its entries by magnitude.
+* :func:`apply` / :func:`apply_T` (``bspai_apply`` / ``bspai_apply_T``).
+* :func:`solve` (``gmres_ir_solve``): GMRES-based iterative refinement.
+* :class:`BSPAISolve`: ``torch.autograd.Function`` whose backward solves the
+  adjoint system with the transposed bucketed preconditioner.
+
+The library must be built (``__graft_entry__.build()``); importing this
+package without it raises ImportError — there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libbspai.so")
+
+FP64, FP32, FP16, BF16, FP8_E4M3, DROP = 0, 1, 2, 3, 4, 5
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3,
+        "drop": DROP}
+OK, EINVAL, ENOMEM, EHIP, EZEROROW, ERANK, ENOCONV, ENAN = 0, -1, -2, -3, -4, -5, -6, -7
+_ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EZEROROW: "EZEROROW", ERANK: "ERANK",
+             ENOCONV: "ENOCONV", ENAN: "ENAN"}
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"{LIBPATH} is missing: build the HIP library first (__graft_entry__.build())")
+
+
+class _CSR(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class _Pattern(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("build_T", C.c_int), ("keep_fp64_M", C.c_int), ("scale", C.c_int)]
+
+
+class _Tol(C.Structure):
+    _fields_ = [("u_g", C.c_int), ("ur_dd", C.c_int), ("tau", C.c_double), ("tol_rr", C.c_double),
+                ("tol_be", C.c_double), ("i_max", C.c_int), ("gmres_max", C.c_int), ("x0_mode", C.c_int),
+                ("trans", C.c_int)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("steps", C.c_int), ("its_total", C.c_int), ("stop_reason", C.c_int), ("status", C.c_int),
+                ("its", C.c_int * 64), ("eta", C.c_double * 65), ("relres", C.c_double * 65)]
+
+
+class _BStats(C.Structure):
+    _fields_ = [("n", C.c_int32), ("q", C.c_int32), ("nnz", C.c_int64), ("precs", C.c_int * 6),
+                ("count", C.c_int64 * 6), ("threshold", C.c_double * 6), ("scale", C.c_double * 6),
+                ("norm_inf", C.c_double), ("eps_b", C.c_double), ("bytes_values", C.c_int64),
+                ("bytes_indices", C.c_int64), ("storage_pct", C.c_double)]
+
+
+_lib = C.CDLL(LIBPATH)
+_vp = C.c_void_p
+_lib.bspai_build.argtypes = [C.POINTER(_CSR), C.POINTER(_Pattern), C.c_double, C.POINTER(C.c_int), C.c_int,
+                             C.POINTER(_Opts), C.POINTER(_vp), _vp]
+_lib.bspai_import.argtypes = [C.POINTER(_CSR), C.c_double, C.POINTER(C.c_int), C.c_int, C.POINTER(_Opts),
+                              C.POINTER(_vp), _vp]
+_lib.bspai_apply.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int64, C.c_int, _vp]
+_lib.bspai_apply_T.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int64, C.c_int, _vp]
+_lib.gmres_ir_solve.argtypes = [C.POINTER(_CSR), _vp, _vp, C.POINTER(_Tol), _vp, C.c_int, C.POINTER(_Stats), _vp]
+_lib.bspai_stats.argtypes = [_vp, C.POINTER(_BStats)]
+_lib.bspai_export.argtypes = [_vp, _vp, _vp, _vp]
+_lib.bspai_free.argtypes = [_vp]
+_lib.bspai_free.restype = None
+_lib.bspai_last_error.restype = C.c_char_p
+_lib.bspai_set_profiling.argtypes = [C.c_int]
+_lib.bspai_set_profiling.restype = None
+_lib.bspai_last_solve_kernel_ms.restype = C.c_double
+for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
+           "bspai_export"):
+    getattr(_lib, _f).restype = C.c_int
+
+SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
+           "bspai_export", "bspai_free", "bspai_last_error", "bspai_grad_vals", "bspai_set_profiling",
+           "bspai_last_solve_kernel_ms")
+
+
+def set_profiling(on: bool) -> None:
+    """Time the solver kernel of each gmres_ir_solve with HIP events."""
+    _lib.bspai_set_profiling(int(on))
+
+
+def last_solve_kernel_ms() -> float:
+    return _lib.bspai_last_solve_kernel_ms()
+
+
+class BSPAIError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code: int, allow=()):
+    if code != OK and code not in allow:
+        raise BSPAIError(code, _lib.bspai_last_error().decode(errors="replace"))
+    return code
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _prec_ids(precs: Sequence) -> Tuple:
+    ids = [PREC[p] if isinstance(p, str) else int(p) for p in precs]
+    return (C.c_int * len(ids))(*ids), len(ids)
+
+
+class CSRMatrix:
+    """Square CSR matrix on the GPU: int32 row_ptr/col, float64 values."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: Optional[torch.Tensor], n: int):
+        self.row_ptr = row_ptr.to(dtype=torch.int32).contiguous()
+        self.col = col.to(dtype=torch.int32).contiguous()
+        self.val = None if val is None else val.to(dtype=torch.float64).contiguous()
+        self.n = int(n)
+        for t in (self.row_ptr, self.col) + (() if self.val is None else (self.val,)):
+            if not t.is_cuda:
+                raise ValueError("CSRMatrix tensors must live on the GPU")
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @classmethod
+    def from_host(cls, A, device="cuda") -> "CSRMatrix":
+        """From any object with n, row_ptr, col, val NumPy arrays (e.g. workloads.CSR)."""
+        val = None if A.val is None else torch.as_tensor(A.val, dtype=torch.float64, device=device)
+        return cls(torch.as_tensor(A.row_ptr, device=device), torch.as_tensor(A.col, device=device), val, A.n)
+
+    def _c(self) -> _CSR:
+        return _CSR(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                    self.val.data_ptr() if self.val is not None else None)
+
+    def _p(self) -> _Pattern:
+        return _Pattern(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr())
+
+
+class Handle:
+    """Owns a ``bspai_handle`` (bucketed M on the GPU)."""
+
+    def __init__(self, ptr: int, n: int, nnz: int):
+        self._ptr = ptr
+        self.n = n
+        self.nnz = nnz
+
+    @property
+    def ptr(self) -> int:
+        if not self._ptr:
+            raise ValueError("handle already freed")
+        return self._ptr
+
+    def free(self):
+        if self._ptr:
+            _lib.bspai_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def stats(self) -> Dict:
+        s = _BStats()
+        _check(_lib.bspai_stats(self.ptr, C.byref(s)))
+        q = s.q
+        return dict(n=s.n, q=q, nnz=s.nnz, precs=list(s.precs[:q]), count=list(s.count[:q]),
+                    threshold=list(s.threshold[:q]), scale=list(s.scale[:q]), norm_inf=s.norm_inf, eps_b=s.eps_b,
+                    bytes_values=s.bytes_values, bytes_indices=s.bytes_indices, storage_pct=s.storage_pct)
+
+    def export(self, fp64: bool = True) -> Dict:
+        import numpy as np
+
+        bk = np.zeros(self.nnz, dtype=np.int8)
+        st = np.zeros(self.nnz, dtype=np.float64)
+        m64 = np.zeros(self.nnz, dtype=np.float64) if fp64 else None
+        _check(_lib.bspai_export(self.ptr, bk.ctypes.data, st.ctypes.data,
+                                 m64.ctypes.data if m64 is not None else None))
+        return dict(bucket=bk, stored=st, m64=m64)
+
+
+def _opts(build_T, keep_fp64_M, scale):
+    return _Opts(int(build_T), int(keep_fp64_M), int(scale))
+
+
+def build(A: CSRMatrix, P: Optional[CSRMatrix] = None, eps: float = 1e-4, precs: Sequence = ("fp64",),
+          build_T: bool = True, keep_fp64_M: bool = True, scale: bool = False, stream=None) -> Handle:
+    out = _vp()
+    pids, q = _prec_ids(precs)
+    a = A._c()
+    p = P._p() if P is not None else None
+    _check(_lib.bspai_build(C.byref(a), C.byref(p) if p is not None else None, float(eps), pids, q,
+                            C.byref(_opts(build_T, keep_fp64_M, scale)), C.byref(out), _stream(stream)))
+    return Handle(out.value, A.n, P.nnz if P is not None else A.nnz)
+
+
+def import_m(M: CSRMatrix, eps: float, precs: Sequence, build_T: bool = True, keep_fp64_M: bool = True,
+             stream=None) -> Handle:
+    out = _vp()
+    pids, q = _prec_ids(precs)
+    m = M._c()
+    _check(_lib.bspai_import(C.byref(m), float(eps), pids, q, C.byref(_opts(build_T, keep_fp64_M, False)),
+                             C.byref(out), _stream(stream)))
+    return Handle(out.value, M.n, M.nnz)
+
+
+def _apply(fn, h: Handle, x: torch.Tensor, out: Optional[torch.Tensor], stream):
+    if x.dtype not in (torch.float32, torch.float64) or not x.is_cuda:
+        raise ValueError("x must be a float32/float64 CUDA tensor")
+    x = x.contiguous()
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    if x.shape[0] != h.n:
+        raise ValueError(f"x has {x.shape[0]} rows, M is {h.n} x {h.n}")
+    y = torch.empty_like(x) if out is None else out
+    _check(fn(h.ptr, x.data_ptr(), y.data_ptr(), nrhs, nrhs, FP64 if x.dtype == torch.float64 else FP32,
+              _stream(stream)))
+    return y
+
+
+def apply(h: Handle, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """y = M_b x (x: [n] or [n, nrhs] float32/float64 on the GPU)."""
+    return _apply(_lib.bspai_apply, h, x, out, stream)
+
+
+def apply_T(h: Handle, x: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """y = M_b^T x."""
+    return _apply(_lib.bspai_apply_T, h, x, out, stream)
+
+
+def _stats_dict(s: _Stats) -> Dict:
+    k = s.steps
+    return dict(steps=k, its=list(s.its[:k]), its_total=s.its_total, eta=list(s.eta[:k + 1]),
+                relres=list(s.relres[:k + 1]), stop_reason=s.stop_reason, status=s.status)
+
+
+def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4,
+          tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0,
+          trans: bool = False, x: Optional[torch.Tensor] = None, stream=None, raise_noconv: bool = False):
+    """BSPAI-GMRES-IR.  Returns (x, stats dict).  ENOCONV is reported in stats
+    (status) unless raise_noconv."""
+    if b.dtype != torch.float64 or not b.is_cuda or b.dim() != 1:
+        raise ValueError("b must be a 1-D float64 CUDA tensor")
+    b = b.contiguous()
+    if x is None:
+        x = torch.zeros_like(b) if x0_mode == 3 else torch.empty_like(b)
+    tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), int(gmres_max),
+               int(x0_mode), int(trans))
+    st = _Stats()
+    a = A._c()
+    allow = () if raise_noconv else (ENOCONV,)
+    _check(_lib.gmres_ir_solve(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), 1, C.byref(st),
+                               _stream(stream)), allow=allow)
+    return x, _stats_dict(st)
+
+
+from .autograd import BSPAISolve  # noqa: E402  (needs the names above)
+
+__all__ = ["CSRMatrix", "Handle", "build", "import_m", "apply", "apply_T", "solve", "BSPAISolve", "BSPAIError",
+           "SYMBOLS", "PREC"]

@@ -1,0 +1,686 @@
+// bspai_build / bspai_import: SPAI on a fixed pattern (Algorithm 1's least
+// squares with no pattern augmentation, run on A^T as in Algorithm 4 step 1),
+// ||M||_inf, bucketing (Algorithm 2, eq. (nint)) and per-bucket packing.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "formats.h"
+
+namespace bspai {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lower_bound_i(const int32_t *a, int len, int key) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// per row k of the pattern: |J_k| and the number of candidate shadow indices
+__global__ void k_spai_sizes(int n, const int32_t *arp, const int32_t *prp, const int32_t *pcol, int32_t *out_max) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int s = prp[k], e = prp[k + 1];
+  int cand = 0;
+  for (int p = s; p < e; p++) cand += arp[pcol[p] + 1] - arp[pcol[p]];
+  atomicMax(&out_max[0], e - s);
+  atomicMax(&out_max[1], cand);
+}
+
+// d_j = 1 / max_l |a_jl|: scales column j of A^T to unit max (Section 4)
+__global__ void k_row_maxabs_inv(int n, const int32_t *arp, const double *aval, double *d) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double mx = 0;
+  for (int p = arp[j]; p < arp[j + 1]; p++) mx = fmax(mx, fabs(aval[p]));
+  d[j] = mx > 0 ? 1.0 / mx : 1.0;
+}
+
+struct SpaiArgs {
+  int n;
+  const int32_t *arp, *acol;
+  const double *aval;
+  const int32_t *prp, *pcol;
+  const double *dscale;  // null: no scaling
+  double *mval;
+  int cand_p2;  // capacity of the index lists (power of two)
+  int tile_cap; // capacity of the dense tile in doubles
+  int32_t *err; // [0] first zero row, [1] first rank-deficient row, [2] first oversized row
+};
+
+// One wavefront per row k of M:
+//   J = P(k,:); I = sorted union of the nonzero columns of the rows J of A
+//   (the shadow of J in A^T); Abar(l, c) = a_{J_c, I_l}; ebar = e_k(I);
+//   Householder QR of Abar, mbar = R^{-1} (Q^T ebar)(1:|J|); M(k, J) = mbar.
+__global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
+  extern __shared__ double lds_d[];
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int ps = a.prp[k], nJ = a.prp[k + 1] - ps;
+  int32_t *cand = reinterpret_cast<int32_t *>(lds_d);  // cand_p2
+  int32_t *I = cand + a.cand_p2;                        // cand_p2
+  double *Ab = lds_d + a.cand_p2;                       // tile_cap (after the two int lists)
+  double *eb = Ab + a.tile_cap;                         // cand_p2
+  double *mv = eb + a.cand_p2;                          // 64 + nJ
+
+  // gather candidate columns (nonzero values only), compacted with ballots
+  int nc = 0;
+  for (int c = 0; c < nJ; c++) {
+    int j = a.pcol[ps + c];
+    int s = a.arp[j], e = a.arp[j + 1];
+    for (int base = s; base < e; base += 64) {
+      int p = base + lane;
+      bool pred = p < e && a.aval[p] != 0.0;
+      uint64_t mask = __ballot(pred);
+      if (nc + __popcll(mask) > a.cand_p2) {
+        if (lane == 0) atomicMin(&a.err[2], k);
+        return;
+      }
+      int pos = nc + __popcll(mask & ((1ull << lane) - 1ull));
+      if (pred) cand[pos] = a.acol[p];
+      nc += __popcll(mask);
+    }
+  }
+  int S = 1;
+  while (S < nc) S <<= 1;
+  for (int p = nc + lane; p < S; p += 64) cand[p] = INT_MAX;
+  wave_sync();
+  // bitonic sort of cand[0..S)
+  for (int size = 2; size <= S; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = lane; t < S / 2; t += 64) {
+        int lo = 2 * stride * (t / stride) + (t % stride);
+        int hi = lo + stride;
+        bool up = ((lo & size) == 0);
+        int x = cand[lo], y = cand[hi];
+        if ((x > y) == up) {
+          cand[lo] = y;
+          cand[hi] = x;
+        }
+      }
+      wave_sync();
+    }
+  }
+  // unique -> I
+  int nI = 0;
+  for (int base = 0; base < nc; base += 64) {
+    int p = base + lane;
+    bool pred = p < nc && (p == 0 || cand[p] != cand[p - 1]);
+    uint64_t mask = __ballot(pred);
+    int pos = nI + __popcll(mask & ((1ull << lane) - 1ull));
+    if (pred) I[pos] = cand[p];
+    nI += __popcll(mask);
+  }
+  wave_sync();
+  for (int c = lane; c < nJ; c += 64) a.mval[ps + c] = 0.0;
+  int lk = lower_bound_i(I, nI, k);
+  if (lk >= nI || I[lk] != k) {
+    if (lane == 0) atomicMin(&a.err[0], k);
+    return;
+  }
+  if (nI < nJ) {
+    if (lane == 0) atomicMin(&a.err[1], k);
+    return;
+  }
+  if ((int64_t)nI * nJ > a.tile_cap || nJ > 64) {
+    if (lane == 0) atomicMin(&a.err[2], k);
+    return;
+  }
+  // dense tile, column-major with leading dimension nI
+  for (int p = lane; p < nI * nJ; p += 64) Ab[p] = 0.0;
+  for (int p = lane; p < nI; p += 64) eb[p] = (p == lk) ? 1.0 : 0.0;
+  wave_sync();
+  for (int c = 0; c < nJ; c++) {
+    int j = a.pcol[ps + c];
+    double dj = a.dscale ? a.dscale[j] : 1.0;
+    for (int p = a.arp[j] + lane; p < a.arp[j + 1]; p += 64) {
+      double v = a.aval[p];
+      if (v != 0.0) Ab[lower_bound_i(I, nI, a.acol[p]) + c * nI] = v * dj;
+    }
+  }
+  wave_sync();
+  double fro2 = 0;
+  for (int p = lane; p < nI * nJ; p += 64) fro2 += Ab[p] * Ab[p];
+  double fro = sqrt(wave_sum_d(fro2));
+  double *diagR = mv + 64;
+  // Householder QR: reflector v = a + sign(a_1) ||a|| e_1 kept in column c
+  for (int c = 0; c < nJ; c++) {
+    double *col = Ab + c * nI;
+    double s2 = 0;
+    for (int l = c + lane; l < nI; l += 64) s2 += col[l] * col[l];
+    double nrm = sqrt(wave_sum_d(s2));
+    double alpha = col[c];
+    double beta = -copysign(nrm, alpha);
+    if (nrm == 0.0 || fabs(beta) <= (double)nJ * 0x1p-53 * fro) {
+      if (lane == 0) atomicMin(&a.err[1], k);
+      return;
+    }
+    wave_sync();
+    if (lane == 0) col[c] = alpha - beta;
+    wave_sync();
+    double vt = 0;
+    for (int l = c + lane; l < nI; l += 64) vt += col[l] * col[l];
+    double vtv = wave_sum_d(vt);
+    for (int jj = c + 1; jj <= nJ; jj++) {  // jj == nJ is the right-hand side
+      double *cj = (jj < nJ) ? Ab + jj * nI : eb;
+      double w = 0;
+      for (int l = c + lane; l < nI; l += 64) w += col[l] * cj[l];
+      double f = 2.0 * wave_sum_d(w) / vtv;
+      for (int l = c + lane; l < nI; l += 64) cj[l] -= f * col[l];
+      wave_sync();
+    }
+    if (lane == 0) diagR[c] = beta;
+    wave_sync();
+  }
+  // back substitution R m = (Q^T ebar)(1:nJ), one lane
+  if (lane == 0) {
+    for (int c = nJ - 1; c >= 0; c--) {
+      double t = eb[c];
+      for (int jj = c + 1; jj < nJ; jj++) t -= Ab[c + jj * nI] * mv[jj];
+      mv[c] = t / diagR[c];
+    }
+  }
+  wave_sync();
+  for (int c = lane; c < nJ; c += 64) {
+    double dj = a.dscale ? a.dscale[a.pcol[ps + c]] : 1.0;
+    a.mval[ps + c] = mv[c] * dj;
+  }
+}
+
+// ------------------------------------------------------------------ buckets
+
+// ||M||_inf: each row summed left to right in CSR order; the maximum of the
+// (non-negative) row sums and of |m| via integer max on their bit patterns.
+__global__ void k_row_abs(int n, const int32_t *rp, const double *v, unsigned long long *mx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0, m = 0;
+  for (int p = rp[i]; p < rp[i + 1]; p++) {
+    s += fabs(v[p]);
+    m = fmax(m, fabs(v[p]));
+  }
+  atomicMax(&mx[0], (unsigned long long)__double_as_longlong(s));
+  atomicMax(&mx[1], (unsigned long long)__double_as_longlong(m));
+}
+
+struct BucketArgs {
+  int n, q;
+  int prec[kMaxBuckets];
+  double t[kMaxBuckets];
+  double inv_scale[kMaxBuckets];
+  double scale[kMaxBuckets];
+  const int32_t *rp, *col;
+  const double *v;
+  int8_t *bid;
+  double *stored;
+  int32_t *cnt;  // [q][n]
+  int32_t *brp[kMaxBuckets];
+  int32_t *bcol[kMaxBuckets];
+  void *bval[kMaxBuckets];
+};
+
+// Algorithm 2 / eq. (nint): bucket 1 if |m| > t_2, bucket q if |m| <= t_q,
+// otherwise the k with t_{k+1} < |m| <= t_k.
+__device__ __forceinline__ int classify(const BucketArgs &a, double m) {
+  double x = fabs(m);
+  if (a.q == 1) return 0;
+  if (x > a.t[1]) return 0;
+  if (x <= a.t[a.q - 1]) return a.q - 1;
+  for (int k = 1; k <= a.q - 2; k++)
+    if (x > a.t[k + 1] && x <= a.t[k]) return k;
+  return a.q - 1;
+}
+
+__global__ void k_classify(BucketArgs a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int c[kMaxBuckets] = {0, 0, 0, 0, 0, 0};
+  for (int p = a.rp[i]; p < a.rp[i + 1]; p++) {
+    int k = classify(a, a.v[p]);
+    a.bid[p] = (int8_t)k;
+    c[k]++;
+  }
+  for (int k = 0; k < a.q; k++) a.cnt[(int64_t)k * a.n + i] = c[k];
+}
+
+__global__ void k_pack(BucketArgs a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int pos[kMaxBuckets];
+  for (int k = 0; k < a.q; k++) pos[k] = a.brp[k] ? a.brp[k][i] : 0;
+  for (int p = a.rp[i]; p < a.rp[i + 1]; p++) {
+    int k = a.bid[p];
+    double m = a.v[p];
+    double y = m * a.inv_scale[k];  // exact: power-of-two scale
+    double st = 0.0;
+    switch (a.prec[k]) {
+      case BSPAI_FP64:
+        static_cast<double *>(a.bval[k])[pos[k]] = m;
+        st = m;
+        break;
+      case BSPAI_FP32: {
+        float f = encode_f32(y);
+        static_cast<float *>(a.bval[k])[pos[k]] = f;
+        st = (double)f * a.scale[k];
+      } break;
+      case BSPAI_FP16: {
+        uint16_t h = encode_f16(y);
+        static_cast<uint16_t *>(a.bval[k])[pos[k]] = h;
+        st = (double)decode_f16(h) * a.scale[k];
+      } break;
+      case BSPAI_BF16: {
+        uint16_t h = encode_bf16(y);
+        static_cast<uint16_t *>(a.bval[k])[pos[k]] = h;
+        st = (double)decode_bf16(h) * a.scale[k];
+      } break;
+      case BSPAI_FP8_E4M3: {
+        uint8_t h = encode_e4m3(y);
+        static_cast<uint8_t *>(a.bval[k])[pos[k]] = h;
+        st = (double)decode_e4m3(h) * a.scale[k];
+      } break;
+      default:  // dropped
+        break;
+    }
+    if (a.prec[k] != BSPAI_DROP) {
+      a.bcol[k][pos[k]] = a.col[p];
+      pos[k]++;
+    }
+    a.stored[p] = st;
+  }
+}
+
+static int ceil_log2(double t) {
+  int e;
+  double f = frexp(t, &e);
+  return (f == 0.5) ? e - 1 : e;
+}
+
+static unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+static int check_precs(const bspai_prec *precs, int q) {
+  if (!precs || q < 1 || q > kMaxBuckets) return fail(BSPAI_EINVAL, "precision set: need 1 <= q <= 6");
+  for (int k = 0; k < q; k++)
+    if (precs[k] < BSPAI_FP64 || precs[k] > BSPAI_DROP) return fail(BSPAI_EINVAL, "precision %d unknown", precs[k]);
+  for (int k = 1; k < q; k++)
+    if (!(unit_roundoff(precs[k - 1]) < unit_roundoff(precs[k])))
+      return fail(BSPAI_EINVAL, "precisions must have strictly increasing unit roundoff (got %d before %d)",
+                  precs[k - 1], precs[k]);
+  for (int k = 0; k + 1 < q; k++)
+    if (precs[k] == BSPAI_DROP) return fail(BSPAI_EINVAL, "DROP must be the last precision");
+  if (precs[0] == BSPAI_DROP) return fail(BSPAI_EINVAL, "the first bucket cannot be DROP");
+  return BSPAI_OK;
+}
+
+static int check_csr(const char *what, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col) {
+  if (n < 0 || nnz < 0 || nnz > INT32_MAX) return fail(BSPAI_EINVAL, "%s: bad sizes n=%d nnz=%lld", what, n, (long long)nnz);
+  if (n > 0 && (!rp || (nnz > 0 && !col))) return fail(BSPAI_EINVAL, "%s: null pointer", what);
+  return BSPAI_OK;
+}
+
+static void free_handle_memory(bspai_handle *h) {
+  for (int k = 0; k < kMaxBuckets; k++) {
+    dfree(h->b[k].rp), dfree(h->b[k].col), dfree(h->b[k].val);
+    dfree(h->b[k].rpT), dfree(h->b[k].colT), dfree(h->b[k].valT);
+  }
+  dfree(h->m_rp), dfree(h->m_col), dfree(h->m_val);
+  dfree(h->mT_rp), dfree(h->mT_col), dfree(h->mT_val);
+  dfree(h->bucket_id), dfree(h->stored);
+}
+
+// Buckets, packing and (optionally) transposed packing of h->m_* (FP64 M).
+static int bucketize(bspai_handle *h, const bspai_prec *precs, int q, double eps, const bspai_opts &o,
+                     hipStream_t s) {
+  const int n = h->n;
+  const int64_t nnz = h->nnz;
+  h->q = q;
+  h->eps = eps;
+  for (int k = 0; k < q; k++) h->precs[k] = precs[k];
+  unsigned long long *mx = nullptr;
+  int rc;
+  if ((rc = dalloc_t(&mx, 2))) return rc;
+  unsigned long long hm[2] = {0, 0};
+  BSPAI_HIP(hipMemsetAsync(mx, 0, sizeof(hm), s));
+  if (n > 0) {
+    hipLaunchKernelGGL(k_row_abs, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, h->m_rp, h->m_val, mx);
+    BSPAI_CHECK_LAUNCH();
+  }
+  BSPAI_HIP(hipMemcpyAsync(hm, mx, sizeof(hm), hipMemcpyDeviceToHost, s));
+  BSPAI_HIP(hipStreamSynchronize(s));
+  dfree(mx);
+  double normM, maxabs;
+  memcpy(&normM, &hm[0], 8);
+  memcpy(&maxabs, &hm[1], 8);
+  h->normM = normM;
+  BucketArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.q = q;
+  const double base = eps * normM;
+  for (int k = 0; k < q; k++) {
+    a.prec[k] = precs[k];
+    a.t[k] = base / unit_roundoff(precs[k]);
+    double tk = (k == 0) ? maxabs : a.t[k];
+    double sc = 1.0;
+    if ((precs[k] == BSPAI_FP16 || precs[k] == BSPAI_FP8_E4M3) && tk > 0)
+      sc = ldexp(1.0, ceil_log2(tk) - (precs[k] == BSPAI_FP16 ? 15 : 8));
+    a.scale[k] = sc;
+    a.inv_scale[k] = 1.0 / sc;
+    h->b[k].prec = precs[k];
+    h->b[k].t = a.t[k];
+    h->b[k].scale = sc;
+  }
+  a.rp = h->m_rp;
+  a.col = h->m_col;
+  a.v = h->m_val;
+  if ((rc = dalloc_t(&h->bucket_id, (size_t)nnz + 1)) || (rc = dalloc_t(&h->stored, (size_t)nnz + 1))) return rc;
+  a.bid = h->bucket_id;
+  a.stored = h->stored;
+  int32_t *cnt = nullptr;
+  void *tmp = nullptr;
+  if ((rc = dalloc_t(&cnt, (size_t)q * n + 1)) || (rc = dalloc(&tmp, scan_tmp_bytes(n)))) {
+    dfree(cnt), dfree(tmp);
+    return rc;
+  }
+  auto body = [&]() -> int {
+    a.cnt = cnt;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_classify, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+      BSPAI_CHECK_LAUNCH();
+    }
+    for (int k = 0; k < q; k++) {
+      int32_t *rp = nullptr;
+      int r;
+      if ((r = dalloc_t(&rp, (size_t)n + 1))) return r;
+      h->b[k].rp = rp;
+      if ((r = exclusive_scan(cnt + (int64_t)k * n, rp, n, tmp, s))) return r;
+      int32_t tot = 0;
+      BSPAI_HIP(hipMemcpyAsync(&tot, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipStreamSynchronize(s));
+      h->b[k].nnz = tot;
+      if (precs[k] != BSPAI_DROP) {
+        if ((r = dalloc_t(&h->b[k].col, (size_t)tot + 1))) return r;
+        if ((r = dalloc(&h->b[k].val, (size_t)value_bytes(precs[k]) * (tot + 1)))) return r;
+        a.brp[k] = rp;
+        a.bcol[k] = h->b[k].col;
+        a.bval[k] = h->b[k].val;
+      }
+    }
+    if (n > 0) {
+      hipLaunchKernelGGL(k_pack, dim3(blocks_for(n, 256)), dim3(256), 0, s, a);
+      BSPAI_CHECK_LAUNCH();
+    }
+    BSPAI_HIP(hipStreamSynchronize(s));
+    return BSPAI_OK;
+  };
+  rc = body();
+  dfree(cnt), dfree(tmp);
+  if (rc) return rc;
+  // kernel view: stored buckets from the least to the most precise
+  BMat &M = h->mat;
+  memset(&M, 0, sizeof(M));
+  M.n = n;
+  for (int k = q - 1; k >= 0; k--) {
+    if (precs[k] == BSPAI_DROP || h->b[k].nnz == 0) continue;
+    M.prec[M.nb] = precs[k];
+    M.scale[M.nb] = h->b[k].scale;
+    M.rp[M.nb] = h->b[k].rp;
+    M.col[M.nb] = h->b[k].col;
+    M.val[M.nb] = h->b[k].val;
+    M.nnz += h->b[k].nnz;
+    M.nb++;
+  }
+  M.lanes = pick_lanes(M, M.nnz);
+  if (o.build_T) {
+    BMat &T = h->matT;
+    T = M;
+    int j = 0;
+    for (int k = q - 1; k >= 0; k--) {
+      if (precs[k] == BSPAI_DROP || h->b[k].nnz == 0) continue;
+      Bucket &B = h->b[k];
+      int r;
+      if ((r = dalloc_t(&B.rpT, (size_t)n + 1)) || (r = dalloc_t(&B.colT, (size_t)B.nnz + 1)) ||
+          (r = dalloc(&B.valT, (size_t)value_bytes(B.prec) * (B.nnz + 1))))
+        return r;
+      if ((r = csr_transpose(n, B.nnz, B.rp, B.col, B.val, value_bytes(B.prec), B.rpT, B.colT, B.valT, s))) return r;
+      T.rp[j] = B.rpT;
+      T.col[j] = B.colT;
+      T.val[j] = B.valT;
+      j++;
+    }
+    if (h->has_fp64) {
+      int r;
+      if ((r = dalloc_t(&h->mT_rp, (size_t)n + 1)) || (r = dalloc_t(&h->mT_col, (size_t)nnz + 1)) ||
+          (r = dalloc_t(&h->mT_val, (size_t)nnz + 1)))
+        return r;
+      if ((r = csr_transpose(n, nnz, h->m_rp, h->m_col, h->m_val, 8, h->mT_rp, h->mT_col, h->mT_val, s))) return r;
+    }
+    h->has_T = 1;
+  }
+  return BSPAI_OK;
+}
+
+static bspai_opts default_opts() {
+  bspai_opts o;
+  o.build_T = 1;
+  o.keep_fp64_M = 1;
+  o.scale = 0;
+  return o;
+}
+
+static int finish_build(bspai_handle *h, const bspai_prec *precs, int q, double eps, const bspai_opts &o,
+                        hipStream_t s, bspai_handle **out) {
+  h->has_fp64 = 1;  // the FP64 M is needed while packing; dropped below unless kept
+  int rc = bucketize(h, precs, q, eps, o, s);
+  if (rc) {
+    free_handle_memory(h);
+    delete h;
+    return rc;
+  }
+  if (!o.keep_fp64_M) {
+    (void)hipStreamSynchronize(s);
+    dfree(h->m_val);
+    h->m_val = nullptr;
+    dfree(h->mT_val);
+    h->mT_val = nullptr;
+    h->has_fp64 = 0;
+  }
+  *out = h;
+  return BSPAI_OK;
+}
+
+}  // namespace bspai
+
+using namespace bspai;
+
+extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double eps_b, const bspai_prec *precs, int q,
+                           const bspai_opts *opts, bspai_handle **out, void *stream) {
+  if (!out) return fail(BSPAI_EINVAL, "bspai_build: null output");
+  *out = nullptr;
+  if (!A) return fail(BSPAI_EINVAL, "bspai_build: null A");
+  int rc;
+  if ((rc = check_csr("A", A->n, A->nnz, A->row_ptr, A->col))) return rc;
+  if (A->n > 0 && A->nnz > 0 && !A->val) return fail(BSPAI_EINVAL, "A: null values");
+  bspai_pattern Pd;
+  if (P) {
+    Pd = *P;
+    if (Pd.n != A->n) return fail(BSPAI_EINVAL, "pattern size %d != n %d", Pd.n, A->n);
+    if ((rc = check_csr("P", Pd.n, Pd.nnz, Pd.row_ptr, Pd.col))) return rc;
+  } else {
+    Pd.n = A->n;
+    Pd.nnz = A->nnz;
+    Pd.row_ptr = A->row_ptr;
+    Pd.col = A->col;
+  }
+  if ((rc = check_precs(precs, q))) return rc;
+  if (!(eps_b >= 0) || !std::isfinite(eps_b)) return fail(BSPAI_EINVAL, "eps_b must be finite and >= 0");
+  bspai_opts o = opts ? *opts : default_opts();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = A->n;
+  bspai_handle *h = new bspai_handle();
+  BSPAI_HIP(hipGetDevice(&h->device));
+  h->n = n;
+  h->nnz = Pd.nnz;
+  int32_t *mx = nullptr, *err = nullptr;
+  double *dsc = nullptr;
+  auto body = [&]() -> int {
+    int r;
+    if ((r = dalloc_t(&h->m_rp, (size_t)n + 1)) || (r = dalloc_t(&h->m_col, (size_t)Pd.nnz + 1)) ||
+        (r = dalloc_t(&h->m_val, (size_t)Pd.nnz + 1)))
+      return r;
+    BSPAI_HIP(hipMemcpyAsync(h->m_rp, Pd.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (Pd.nnz) BSPAI_HIP(hipMemcpyAsync(h->m_col, Pd.col, sizeof(int32_t) * Pd.nnz, hipMemcpyDeviceToDevice, s));
+    if (n == 0) return BSPAI_OK;
+    if ((r = dalloc_t(&mx, 2)) || (r = dalloc_t(&err, 3))) return r;
+    int32_t hmx[2] = {0, 0};
+    BSPAI_HIP(hipMemsetAsync(mx, 0, sizeof(hmx), s));
+    hipLaunchKernelGGL(k_spai_sizes, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_ptr, Pd.row_ptr, Pd.col,
+                       mx);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipMemcpyAsync(hmx, mx, sizeof(hmx), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    int nJmax = hmx[0], candmax = hmx[1];
+    int cand_p2 = 64;
+    while (cand_p2 < candmax) cand_p2 <<= 1;
+    int64_t tile = (int64_t)std::max(candmax, 1) * std::max(nJmax, 1);
+    size_t lds = sizeof(double) * ((size_t)cand_p2 /* two int lists */ + tile + cand_p2 + 64 + 64 + 64);
+    if (nJmax > 64 || lds > 160 * 1024)
+      return fail(BSPAI_EINVAL,
+                  "least-squares tile too large for the on-chip path (|J| max %d, shadow candidates max %d)", nJmax,
+                  candmax);
+    if (o.scale) {
+      if ((r = dalloc_t(&dsc, (size_t)n))) return r;
+      hipLaunchKernelGGL(k_row_maxabs_inv, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_ptr, A->val, dsc);
+      BSPAI_CHECK_LAUNCH();
+    }
+    int32_t herr[3] = {INT_MAX, INT_MAX, INT_MAX};
+    BSPAI_HIP(hipMemcpyAsync(err, herr, sizeof(herr), hipMemcpyHostToDevice, s));
+    SpaiArgs sa;
+    sa.n = n;
+    sa.arp = A->row_ptr;
+    sa.acol = A->col;
+    sa.aval = A->val;
+    sa.prp = Pd.row_ptr;
+    sa.pcol = Pd.col;
+    sa.dscale = dsc;
+    sa.mval = h->m_val;
+    sa.cand_p2 = cand_p2;
+    sa.tile_cap = (int)tile;
+    sa.err = err;
+    if (lds > 64 * 1024) BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_spai, dim3(n), dim3(64), lds, s, sa);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    if (herr[2] != INT_MAX) return fail(BSPAI_EINVAL, "row %d: least-squares tile exceeds its capacity", herr[2]);
+    if (herr[0] != INT_MAX || herr[1] != INT_MAX) {
+      if (herr[0] < herr[1]) return fail(BSPAI_EZEROROW, "row %d of M is zero: %d is not in its shadow", herr[0], herr[0]);
+      return fail(BSPAI_ERANK, "row %d: reduced least-squares problem is rank deficient", herr[1]);
+    }
+    return BSPAI_OK;
+  };
+  rc = body();
+  dfree(mx), dfree(err), dfree(dsc);
+  if (rc) {
+    free_handle_memory(h);
+    delete h;
+    return rc;
+  }
+  return finish_build(h, precs, q, eps_b, o, s, out);
+}
+
+extern "C" int bspai_import(const bspai_csr *M, double eps_b, const bspai_prec *precs, int q, const bspai_opts *opts,
+                            bspai_handle **out, void *stream) {
+  if (!out) return fail(BSPAI_EINVAL, "bspai_import: null output");
+  *out = nullptr;
+  if (!M) return fail(BSPAI_EINVAL, "bspai_import: null M");
+  int rc;
+  if ((rc = check_csr("M", M->n, M->nnz, M->row_ptr, M->col))) return rc;
+  if (M->nnz > 0 && !M->val) return fail(BSPAI_EINVAL, "M: null values");
+  if ((rc = check_precs(precs, q))) return rc;
+  if (!(eps_b >= 0) || !std::isfinite(eps_b)) return fail(BSPAI_EINVAL, "eps_b must be finite and >= 0");
+  bspai_opts o = opts ? *opts : default_opts();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bspai_handle *h = new bspai_handle();
+  BSPAI_HIP(hipGetDevice(&h->device));
+  h->n = M->n;
+  h->nnz = M->nnz;
+  auto body = [&]() -> int {
+    int r;
+    if ((r = dalloc_t(&h->m_rp, (size_t)M->n + 1)) || (r = dalloc_t(&h->m_col, (size_t)M->nnz + 1)) ||
+        (r = dalloc_t(&h->m_val, (size_t)M->nnz + 1)))
+      return r;
+    BSPAI_HIP(hipMemcpyAsync(h->m_rp, M->row_ptr, sizeof(int32_t) * (M->n + 1), hipMemcpyDeviceToDevice, s));
+    if (M->nnz) {
+      BSPAI_HIP(hipMemcpyAsync(h->m_col, M->col, sizeof(int32_t) * M->nnz, hipMemcpyDeviceToDevice, s));
+      BSPAI_HIP(hipMemcpyAsync(h->m_val, M->val, sizeof(double) * M->nnz, hipMemcpyDeviceToDevice, s));
+    }
+    return BSPAI_OK;
+  };
+  rc = body();
+  if (rc) {
+    free_handle_memory(h);
+    delete h;
+    return rc;
+  }
+  return finish_build(h, precs, q, eps_b, o, s, out);
+}
+
+extern "C" int bspai_stats(const bspai_handle *M, bspai_bucket_stats *o) {
+  if (!M || !o) return fail(BSPAI_EINVAL, "bspai_stats: null argument");
+  memset(o, 0, sizeof(*o));
+  o->n = M->n;
+  o->q = M->q;
+  o->nnz = M->nnz;
+  o->norm_inf = M->normM;
+  o->eps_b = M->eps;
+  double num = 0;
+  for (int k = 0; k < M->q; k++) {
+    o->precs[k] = (bspai_prec)M->precs[k];
+    o->count[k] = M->b[k].nnz;
+    o->threshold[k] = M->b[k].t;
+    o->scale[k] = M->b[k].scale;
+    int vb = value_bytes(M->precs[k]);
+    o->bytes_values += (int64_t)vb * M->b[k].nnz;
+    if (M->precs[k] != BSPAI_DROP && M->b[k].nnz > 0) o->bytes_indices += 4 * M->b[k].nnz + 4 * ((int64_t)M->n + 1);
+    num += (double)vb * M->b[k].nnz;
+  }
+  o->storage_pct = M->nnz ? 100.0 * num / ((double)M->nnz * value_bytes(M->precs[0])) : 100.0;
+  return BSPAI_OK;
+}
+
+extern "C" int bspai_export(const bspai_handle *M, int8_t *bucket_host, double *stored_host, double *m64_host) {
+  if (!M) return fail(BSPAI_EINVAL, "bspai_export: null handle");
+  size_t nnz = (size_t)M->nnz;
+  if (bucket_host && nnz) BSPAI_HIP(hipMemcpy(bucket_host, M->bucket_id, nnz, hipMemcpyDeviceToHost));
+  if (stored_host && nnz) BSPAI_HIP(hipMemcpy(stored_host, M->stored, nnz * 8, hipMemcpyDeviceToHost));
+  if (m64_host && nnz) {
+    if (!M->has_fp64) return fail(BSPAI_EINVAL, "bspai_export: the FP64 M was not kept");
+    BSPAI_HIP(hipMemcpy(m64_host, M->m_val, nnz * 8, hipMemcpyDeviceToHost));
+  }
+  return BSPAI_OK;
+}
+
+extern "C" void bspai_free(bspai_handle *M) {
+  if (!M) return;
+  (void)hipDeviceSynchronize();
+  free_handle_memory(M);
+  delete M;
+}

@@ -1,0 +1,123 @@
+// Internal declarations shared by the HIP sources of libbspai.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "bspai.h"
+
+namespace bspai {
+
+constexpr int kMaxBuckets = 6;
+
+// Unit roundoff of each storage precision (Table 2; u = 1 for the drop bucket).
+inline double unit_roundoff(int p) {
+  switch (p) {
+    case BSPAI_FP64: return 0x1p-53;
+    case BSPAI_FP32: return 0x1p-24;
+    case BSPAI_FP16: return 0x1p-11;
+    case BSPAI_BF16: return 0x1p-8;
+    case BSPAI_FP8_E4M3: return 0x1p-4;
+    case BSPAI_DROP: return 1.0;
+  }
+  return -1.0;
+}
+
+inline int value_bytes(int p) {
+  switch (p) {
+    case BSPAI_FP64: return 8;
+    case BSPAI_FP32: return 4;
+    case BSPAI_FP16: return 2;
+    case BSPAI_BF16: return 2;
+    case BSPAI_FP8_E4M3: return 1;
+  }
+  return 0;
+}
+
+// A bucketed sparse matrix as the kernels see it: one CSR per stored bucket,
+// ordered from the least precise bucket to the most precise one (the order
+// in which the partial sums are added).
+struct BMat {
+  int32_t n;
+  int32_t nb;
+  int32_t lanes;  // lanes per row chosen for the single-vector product
+  int64_t nnz;    // stored entries (all buckets)
+  int32_t prec[kMaxBuckets];
+  double scale[kMaxBuckets];
+  const int32_t *rp[kMaxBuckets];
+  const int32_t *col[kMaxBuckets];
+  const void *val[kMaxBuckets];
+};
+
+struct Bucket {
+  int prec = BSPAI_FP64;
+  int64_t nnz = 0;
+  double t = 0, scale = 1;
+  int32_t *rp = nullptr, *col = nullptr;
+  void *val = nullptr;
+  int32_t *rpT = nullptr, *colT = nullptr;
+  void *valT = nullptr;
+};
+
+}  // namespace bspai
+
+struct bspai_handle {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int q = 0;
+  int precs[bspai::kMaxBuckets] = {0};
+  double eps = 0, normM = 0;
+  bspai::Bucket b[bspai::kMaxBuckets];
+  // FP64 M in CSR (pattern order) and, with build_T, its transpose
+  int32_t *m_rp = nullptr, *m_col = nullptr;
+  double *m_val = nullptr;
+  int32_t *mT_rp = nullptr, *mT_col = nullptr;
+  double *mT_val = nullptr;
+  int8_t *bucket_id = nullptr;  // per entry of M, CSR order
+  double *stored = nullptr;     // decoded stored value per entry (FP64), CSR order
+  int has_T = 0, has_fp64 = 0;
+  bspai::BMat mat, matT;
+  int device = 0;
+};
+
+namespace bspai {
+
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define BSPAI_HIP(expr)                                                                          \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return ::bspai::fail(e_ == hipErrorOutOfMemory ? BSPAI_ENOMEM : BSPAI_EHIP, "%s: %s (%s:%d)", \
+                           #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define BSPAI_CHECK_LAUNCH() BSPAI_HIP(hipGetLastError())
+
+// Device memory helpers (hipMalloc with error reporting).
+int dalloc(void **p, size_t bytes);
+template <typename T>
+int dalloc_t(T **p, size_t count) {
+  return dalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+void dfree(void *p);
+
+// Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total),
+// on device; the total must fit int32.  tmp needs scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+int exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStream_t s);
+
+// CSR transpose on the device: entries of each output row sorted by source
+// row (deterministic).  Values of `vbytes` bytes each are moved when val != null.
+int csr_transpose(int n, int64_t nnz, const int32_t *rp, const int32_t *col, const void *val, int vbytes,
+                  int32_t *trp, int32_t *tcol, void *tval, hipStream_t s);
+
+// Bucketed product kernels (apply.hip), used by the public apply and the build.
+int pick_lanes(const BMat &M, int64_t nnz);
+int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s);
+
+}  // namespace bspai

@@ -1,0 +1,615 @@
+// gmres_ir_solve: BSPAI-GMRES-IR (Algorithm 4) as one persistent cooperative
+// kernel per solve.
+//
+// G co-resident blocks of 512 threads each own a contiguous range of rows.
+// Everything of Algorithm 4 after the SPAI build runs inside the kernel: x_0,
+// the refinement residual (FP64 or double-double), the stopping tests, the
+// preconditioned operator z = M_b (A_p v) (or A_p^T (M_b^T v) for the
+// transposed solve), modified Gram-Schmidt, Givens rotations, the update
+// d = V y and x = x + d.  The only cross-block communication is a per-block
+// epoch flag barrier and fixed-order all-reductions of FP64 partials, so every
+// block takes identical decisions and the result is deterministic.
+//
+// Modified Gram-Schmidt is kept literal: the projection on v_i uses z already
+// orthogonalised against v_1..v_{i-1}, so step j needs j+1 dependent
+// reductions.  Each pass fuses the update with v_{i-1} and the dot with v_i.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+#include "spmv_dev.h"
+
+namespace bspai {
+
+constexpr int kSolveThreads = 512;
+constexpr int kWaves = kSolveThreads / 64;
+constexpr int kNumSlots = 4;
+constexpr int kMaxBlocks = 256;
+constexpr int kMaxSlotWidth = 2;
+// Largest GMRES cap whose packed triangular R and rotation state fit in LDS.
+constexpr int kMaxGmres = 184;
+constexpr unsigned kSpinLimit = 1u << 27;  // ~ seconds: a bound, never reached by a healthy run
+
+struct Grid {
+  unsigned *flags;  // [G] epoch reached by each block
+  unsigned *abortf; // set when a wait exceeds the spin bound
+  double *slots;    // [kNumSlots][kMaxBlocks][kMaxSlotWidth]
+  int G;
+};
+
+template <typename VT>
+struct SolveParams {
+  int n, G, rows_per_block, m_max;
+  int lanes_a, lanes_m;
+  const int32_t *a_rp, *a_col;
+  const double *a_val;  // A (A^T for trans) in FP64, for the residual and ||A||_inf
+  BMat Ap;              // the same matrix with values rounded to u_p = u_g
+  BMat Mb;              // bucketed M (M^T for trans)
+  const int32_t *f_rp, *f_col;
+  const double *f_val;  // FP64 M (M^T for trans), x0_mode 0
+  int x0_mode, trans, ur_dd, i_max;
+  double tau, tol_rr, tol_be;
+  const double *b;
+  double *x;
+  VT *rv, *w, *zg, *V;
+  double *dv, *dv2;
+  Grid grid;
+  gmres_ir_stats *stats;
+};
+
+// ------------------------------------------------------------------ sync
+
+__device__ bool grid_sync(const Grid &g, unsigned &epoch) {
+  epoch++;
+  __syncthreads();
+  if (g.G == 1) return true;
+  if (threadIdx.x == 0) __hip_atomic_store(&g.flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  int bad = 0;
+  if ((int)threadIdx.x < g.G) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(&g.flags[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+      if (++spins > kSpinLimit || __hip_atomic_load(g.abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        bad = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  bad = __syncthreads_or(bad);
+  if (bad && threadIdx.x == 0) __hip_atomic_store(g.abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return !bad;
+}
+
+template <bool MAX>
+__device__ __forceinline__ double wave_red(double v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    double t = __shfl_xor(v, o);
+    v = MAX ? fmax(v, t) : v + t;
+  }
+  return v;
+}
+
+// every thread gets the block total (fixed tree: deterministic)
+template <bool MAX>
+__device__ double block_red(double v, double *sh) {
+  v = wave_red<MAX>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = (threadIdx.x & 63) < kWaves ? sh[threadIdx.x & 63] : (MAX ? 0.0 : 0.0);
+  return wave_red<MAX>(t);
+}
+
+// all-reduction of W values over the grid; all blocks obtain identical results
+template <int W, bool MAX>
+__device__ bool grid_reduce(const Grid &g, unsigned &epoch, double (&v)[W], double *sh) {
+#pragma unroll
+  for (int c = 0; c < W; c++) v[c] = block_red<MAX>(v[c], sh);
+  if (g.G == 1) return true;
+  double *slot = g.slots + (size_t)((epoch + 1) % kNumSlots) * kMaxBlocks * kMaxSlotWidth;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < W; c++) slot[blockIdx.x * kMaxSlotWidth + c] = v[c];
+  }
+  if (!grid_sync(g, epoch)) return false;
+#pragma unroll
+  for (int c = 0; c < W; c++) {
+    double t = (int)threadIdx.x < g.G ? slot[threadIdx.x * kMaxSlotWidth + c] : 0.0;
+    v[c] = block_red<MAX>(t, sh);
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ rows
+
+template <typename XT, typename YT>
+__device__ __forceinline__ void spmv_rows_dispatch(int lanes, const BMat &M, const XT *x, YT *y, int r0, int r1) {
+  switch (lanes) {
+    case 4: bspmv_rows<4, XT, YT>(M, x, y, r0, r1); break;
+    case 16: bspmv_rows<16, XT, YT>(M, x, y, r0, r1); break;
+    default: bspmv_rows<8, XT, YT>(M, x, y, r0, r1); break;
+  }
+}
+
+// r_i = b_i - sum_j a_ij x_j: double-double (TwoProd with FMA, TwoSum,
+// compensation summed in FP64, as in Ogita-Rump-Oishi's Dot2) or plain FP64,
+// entries in CSR order.  The file is compiled without FMA contraction, so
+// the products and sums here are rounded separately, as TwoSum requires.
+__device__ __forceinline__ double residual_row(const int32_t *rp, const int32_t *col, const double *val,
+                                               const double *b, const double *x, int i, int dd) {
+  double s = b[i];
+  if (dd) {
+    double c = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; p++) {
+      double a = -val[p], xv = x[col[p]];
+      double pr = __dmul_rn(a, xv);
+      double pe = fma(a, xv, -pr);
+      double t = __dadd_rn(s, pr);
+      double z = __dsub_rn(t, s);
+      double se = __dadd_rn(__dsub_rn(s, __dsub_rn(t, z)), __dsub_rn(pr, z));
+      s = t;
+      c = __dadd_rn(c, __dadd_rn(pe, se));
+    }
+    return __dadd_rn(s, c);
+  }
+  for (int p = rp[i]; p < rp[i + 1]; p++) s = __dsub_rn(s, __dmul_rn(val[p], x[col[p]]));
+  return s;
+}
+
+// ------------------------------------------------------------------ kernel
+
+template <typename VT, int ZR>
+__global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
+  extern __shared__ double sm[];
+  const int m = p.m_max;
+  double *cs = sm;            // m
+  double *sn = cs + m;        // m
+  double *g = sn + m;         // m + 1
+  double *hcol = g + m + 1;   // m + 1
+  double *y = hcol + m + 1;   // m
+  double *Rp = y + m;         // m (m + 1) / 2, column c holds R(0..c, c) at c (c + 1) / 2
+  __shared__ double sh[kWaves];
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, nt = blockDim.x, bid = blockIdx.x;
+  const int n = p.n;
+  const int r0 = bid * p.rows_per_block;
+  const int r1 = min(n, r0 + p.rows_per_block);
+  unsigned epoch = 0;
+  const Grid &G = p.grid;
+  const bool rec = (bid == 0 && tid == 0);
+
+#define OWN_ROWS(k, i) \
+  _Pragma("unroll") for (int k = 0; k < ZR; k++) if (int i = r0 + k * nt + tid; i < r1)
+
+  // ||A||_inf (rows summed left to right) and ||b||_inf
+  double normA, normb;
+  {
+    double v[2] = {0.0, 0.0};
+    OWN_ROWS(k, i) {
+      double s = 0.0;
+      for (int q = p.a_rp[i]; q < p.a_rp[i + 1]; q++) s += fabs(p.a_val[q]);
+      v[0] = fmax(v[0], s);
+      v[1] = fmax(v[1], fabs(p.b[i]));
+    }
+    if (!grid_reduce<2, true>(G, epoch, v, sh)) return;
+    normA = v[0];
+    normb = v[1];
+  }
+  // x_0 (Algorithm 4 step 2)
+  if (p.x0_mode == 0) {
+    OWN_ROWS(k, i) {
+      double acc = 0.0;
+      for (int q = p.f_rp[i]; q < p.f_rp[i + 1]; q++) acc = __dadd_rn(acc, __dmul_rn(p.f_val[q], p.b[p.f_col[q]]));
+      p.x[i] = acc;
+    }
+  } else if (p.x0_mode == 1) {
+    spmv_rows_dispatch<double, double>(p.lanes_m, p.Mb, p.b, p.x, r0, r1);
+  } else if (p.x0_mode == 2) {
+    OWN_ROWS(k, i) { p.x[i] = 0.0; }
+  }
+  if (!grid_sync(G, epoch)) return;
+
+  int it = 0, stag = 0, status = BSPAI_OK, reason = 0, its_total = 0;
+  double dx_prev = 0.0;
+  for (;;) {
+    // residual (u_r), backward error and relative residual
+    double rr[ZR];
+    double nv[2] = {0.0, 0.0};
+    OWN_ROWS(k, i) {
+      double r = residual_row(p.a_rp, p.a_col, p.a_val, p.b, p.x, i, p.ur_dd);
+      rr[k] = r;
+      nv[0] = fmax(nv[0], isfinite(r) ? fabs(r) : INFINITY);
+      double xv = p.x[i];
+      nv[1] = fmax(nv[1], isfinite(xv) ? fabs(xv) : INFINITY);
+    }
+    if (!grid_reduce<2, true>(G, epoch, nv, sh)) return;
+    const double nr = nv[0], nx = nv[1];
+    const double eta = nr / (normA * nx + normb);
+    const double rho = normb > 0 ? nr / normb : nr;
+    if (rec && it <= 64) {
+      p.stats->eta[it] = eta;
+      p.stats->relres[it] = rho;
+    }
+    if (!isfinite(nr) || !isfinite(nx)) { status = BSPAI_ENAN; reason = 5; break; }
+    if (rho <= p.tol_rr) { reason = 1; break; }
+    if (eta <= p.tol_be) { reason = 2; break; }
+    if (stag) { reason = 3; break; }
+    if (it >= p.i_max || it >= 64) { status = BSPAI_ENOCONV; reason = 4; break; }
+
+    // ---------------- GMRES on M_b A d = M_b r (left) / A^T M_b^T w = r (right)
+    OWN_ROWS(k, i) { p.rv[i] = (VT)rr[k]; }
+    VT *V0 = p.V;
+    double ss[1] = {0.0};
+    if (!p.trans) {
+      if (!grid_sync(G, epoch)) return;
+      spmv_rows_dispatch<VT, VT>(p.lanes_m, p.Mb, p.rv, V0, r0, r1);
+      __syncthreads();
+      OWN_ROWS(k, i) {
+        double s = (double)V0[i];
+        ss[0] += s * s;
+      }
+    } else {
+      OWN_ROWS(k, i) {
+        double s = (double)p.rv[i];
+        V0[i] = p.rv[i];
+        ss[0] += s * s;
+      }
+    }
+    if (!grid_reduce<1, false>(G, epoch, ss, sh)) return;
+    const double beta = sqrt(ss[0]);
+    int kdone = 0;
+    if (beta > 0.0) {
+      OWN_ROWS(k, i) { V0[i] = (VT)((double)V0[i] / beta); }
+      if (tid == 0) g[0] = beta;
+      if (!grid_sync(G, epoch)) return;
+      for (int j = 0; j < m; j++) {
+        const VT *vj = p.V + (size_t)j * n;
+        if (!p.trans) {
+          spmv_rows_dispatch<VT, VT>(p.lanes_a, p.Ap, vj, p.w, r0, r1);
+          if (!grid_sync(G, epoch)) return;
+          spmv_rows_dispatch<VT, VT>(p.lanes_m, p.Mb, p.w, p.zg, r0, r1);
+        } else {
+          spmv_rows_dispatch<VT, VT>(p.lanes_m, p.Mb, vj, p.w, r0, r1);
+          if (!grid_sync(G, epoch)) return;
+          spmv_rows_dispatch<VT, VT>(p.lanes_a, p.Ap, p.w, p.zg, r0, r1);
+        }
+        __syncthreads();
+        VT zr[ZR];
+        OWN_ROWS(k, i) { zr[k] = p.zg[i]; }
+        // modified Gram-Schmidt: pass i removes the v_{i-1} component and
+        // measures the v_i component of the updated z
+        double hprev = 0.0;
+        const VT *vprev = nullptr;
+        for (int i2 = 0; i2 <= j; i2++) {
+          const VT *vi = p.V + (size_t)i2 * n;
+          double part[1] = {0.0};
+          OWN_ROWS(k, i) {
+            if (i2 > 0) zr[k] = (VT)fma(-hprev, (double)vprev[i], (double)zr[k]);
+            part[0] = fma((double)vi[i], (double)zr[k], part[0]);
+          }
+          if (!grid_reduce<1, false>(G, epoch, part, sh)) return;
+          hprev = part[0];
+          vprev = vi;
+          if (tid == 0) hcol[i2] = hprev;
+        }
+        double nz[1] = {0.0};
+        OWN_ROWS(k, i) {
+          zr[k] = (VT)fma(-hprev, (double)vprev[i], (double)zr[k]);
+          nz[0] = fma((double)zr[k], (double)zr[k], nz[0]);
+        }
+        if (!grid_reduce<1, false>(G, epoch, nz, sh)) return;
+        const double hn = sqrt(nz[0]);
+        VT *vn = p.V + (size_t)(j + 1) * n;
+        OWN_ROWS(k, i) { vn[i] = hn > 0.0 ? (VT)((double)zr[k] / hn) : (VT)0; }
+        // Givens rotations on the new Hessenberg column (identical in every block)
+        if (tid == 0) {
+          hcol[j + 1] = hn;
+          for (int i2 = 0; i2 < j; i2++) {
+            double a = hcol[i2], bb = hcol[i2 + 1];
+            hcol[i2] = cs[i2] * a + sn[i2] * bb;
+            hcol[i2 + 1] = -sn[i2] * a + cs[i2] * bb;
+          }
+          double a = hcol[j], bb = hcol[j + 1];
+          double rho2 = hypot(a, bb);
+          cs[j] = rho2 == 0.0 ? 1.0 : a / rho2;
+          sn[j] = rho2 == 0.0 ? 0.0 : bb / rho2;
+          hcol[j] = rho2;
+          g[j + 1] = -sn[j] * g[j];
+          g[j] = cs[j] * g[j];
+          double *Rc = Rp + (size_t)j * (j + 1) / 2;
+          for (int i2 = 0; i2 <= j; i2++) Rc[i2] = hcol[i2];
+          s_flag = (fabs(g[j + 1]) <= p.tau * beta) || (hn == 0.0);
+        }
+        __syncthreads();
+        kdone = j + 1;
+        if (s_flag || kdone == m) break;
+        if (!grid_sync(G, epoch)) return;
+      }
+      // y = R^{-1} g by one wavefront (column-oriented back substitution)
+      if (tid < 64) {
+        constexpr int kPer = (kMaxGmres + 63) / 64;
+        double gg[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; t++) {
+          int c = tid + 64 * t;
+          gg[t] = c < kdone ? g[c] : 0.0;
+        }
+        for (int c = kdone - 1; c >= 0; c--) {
+          const double *Rc = Rp + (size_t)c * (c + 1) / 2;
+          double gsel = 0.0;
+#pragma unroll
+          for (int t = 0; t < kPer; t++)
+            if (t == c / 64) gsel = gg[t];
+          double gc = __shfl(gsel, c % 64);
+          double yc = gc / Rc[c];
+          if (tid == 0) y[c] = yc;
+#pragma unroll
+          for (int t = 0; t < kPer; t++) {
+            int r = tid + 64 * t;
+            if (r < c) gg[t] -= Rc[r] * yc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // d = V y in FP64; x = x + d (M_b^T applied to V y first for the right-preconditioned solve)
+    double dn[2] = {0.0, 0.0};
+    if (!p.trans) {
+      OWN_ROWS(k, i) {
+        double d = 0.0;
+        for (int c = 0; c < kdone; c++) d = fma((double)p.V[(size_t)c * n + i], y[c], d);
+        double xn = p.x[i] + d;
+        p.x[i] = xn;
+        dn[0] = fmax(dn[0], fabs(d));
+        dn[1] = fmax(dn[1], fabs(xn));
+      }
+    } else {
+      OWN_ROWS(k, i) {
+        double d = 0.0;
+        for (int c = 0; c < kdone; c++) d = fma((double)p.V[(size_t)c * n + i], y[c], d);
+        p.dv[i] = d;
+      }
+      if (!grid_sync(G, epoch)) return;
+      spmv_rows_dispatch<double, double>(p.lanes_m, p.Mb, p.dv, p.dv2, r0, r1);
+      __syncthreads();
+      OWN_ROWS(k, i) {
+        double d = p.dv2[i];
+        double xn = p.x[i] + d;
+        p.x[i] = xn;
+        dn[0] = fmax(dn[0], fabs(d));
+        dn[1] = fmax(dn[1], fabs(xn));
+      }
+    }
+    if (!grid_reduce<2, true>(G, epoch, dn, sh)) return;
+    const double dx = dn[1] > 0 ? dn[0] / dn[1] : 0.0;
+    if (it >= 1 && dx > 0.5 * dx_prev) stag = 1;
+    dx_prev = dx;
+    if (rec && it < 64) p.stats->its[it] = kdone;
+    its_total += kdone;
+    it++;
+  }
+  if (rec) {
+    p.stats->steps = it;
+    p.stats->its_total = its_total;
+    p.stats->stop_reason = reason;
+    p.stats->status = status;
+  }
+#undef OWN_ROWS
+}
+
+template <typename VT>
+__global__ void k_to_prec(int64_t nnz, const double *a, VT *o) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) o[e] = (VT)a[e];
+}
+
+// ------------------------------------------------------------------ host
+
+// optional timing of the solver kernel with HIP events on the solve's stream
+static int g_profile = 0;
+static double g_last_ms = 0.0;
+
+struct Workspace {
+  std::mutex mu;
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+};
+static Workspace g_ws;
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <typename VT>
+static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
+                       gmres_ir_stats *st_host, hipStream_t s) {
+  const int n = A->n;
+  const int64_t nnz = A->nnz;
+  int m = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
+  int G = std::min(kMaxBlocks, std::max(1, (n + kSolveThreads * 4 - 1) / (kSolveThreads * 4)));
+  if (const char *e = getenv("BSPAI_SOLVE_BLOCKS")) G = std::min(kMaxBlocks, std::max(1, atoi(e)));
+  int rpb = (n + G - 1) / G;
+  int zr = (rpb + kSolveThreads - 1) / kSolveThreads;
+  while (zr > 16 && G < kMaxBlocks) {
+    G = std::min(kMaxBlocks, G * 2);
+    rpb = (n + G - 1) / G;
+    zr = (rpb + kSolveThreads - 1) / kSolveThreads;
+  }
+  if (zr > 16) return fail(BSPAI_EINVAL, "gmres_ir_solve: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
+  int ZR = 1;
+  while (ZR < zr) ZR <<= 1;
+  G = (n + rpb - 1) / rpb;
+  if (G < 1) G = 1;
+
+  // workspace layout
+  const bool tr = tol->trans != 0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  size_t o_ap = take(sizeof(VT) * (size_t)(nnz + 1));
+  size_t o_rv = take(sizeof(VT) * n), o_w = take(sizeof(VT) * n), o_zg = take(sizeof(VT) * n);
+  size_t o_V = take(sizeof(VT) * (size_t)n * (m + 1));
+  size_t o_dv = take(8 * (size_t)n), o_dv2 = take(8 * (size_t)n);
+  size_t o_flags = take(4 * kMaxBlocks), o_abort = take(4);
+  size_t o_slots = take(8 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth);
+  size_t o_stats = take(sizeof(gmres_ir_stats));
+  size_t o_trp = 0, o_tcol = 0, o_tval = 0;
+  if (tr) {
+    o_trp = take(4 * ((size_t)n + 1));
+    o_tcol = take(4 * (size_t)(nnz + 1));
+    o_tval = take(8 * (size_t)(nnz + 1));
+  }
+  std::lock_guard<std::mutex> lock(g_ws.mu);
+  int dev = 0;
+  BSPAI_HIP(hipGetDevice(&dev));
+  if (g_ws.bytes < off || g_ws.device != dev) {
+    if (g_ws.ptr) {
+      (void)hipDeviceSynchronize();
+      dfree(g_ws.ptr);
+      g_ws.ptr = nullptr;
+      g_ws.bytes = 0;
+    }
+    int rc = dalloc(&g_ws.ptr, off);
+    if (rc) return rc;
+    g_ws.bytes = off;
+    g_ws.device = dev;
+  }
+  char *base = static_cast<char *>(g_ws.ptr);
+  SolveParams<VT> p;
+  memset(&p, 0, sizeof(p));
+  p.n = n;
+  p.G = G;
+  p.rows_per_block = rpb;
+  p.m_max = m;
+  const int32_t *arp = A->row_ptr, *acol = A->col;
+  const double *aval = A->val;
+  if (tr) {
+    int32_t *trp = reinterpret_cast<int32_t *>(base + o_trp);
+    int32_t *tcol = reinterpret_cast<int32_t *>(base + o_tcol);
+    double *tval = reinterpret_cast<double *>(base + o_tval);
+    int rc = csr_transpose(n, nnz, arp, acol, aval, 8, trp, tcol, tval, s);
+    if (rc) return rc;
+    arp = trp, acol = tcol, aval = tval;
+  }
+  p.a_rp = arp;
+  p.a_col = acol;
+  p.a_val = aval;
+  VT *apv = reinterpret_cast<VT *>(base + o_ap);
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_to_prec<VT>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, aval, apv);
+    BSPAI_CHECK_LAUNCH();
+  }
+  BMat Ap;
+  memset(&Ap, 0, sizeof(Ap));
+  Ap.n = n;
+  Ap.nb = 1;
+  Ap.nnz = nnz;
+  Ap.prec[0] = sizeof(VT) == 8 ? BSPAI_FP64 : BSPAI_FP32;
+  Ap.scale[0] = 1.0;
+  Ap.rp[0] = arp;
+  Ap.col[0] = acol;
+  Ap.val[0] = apv;
+  Ap.lanes = pick_lanes(Ap, nnz);
+  p.Ap = Ap;
+  p.Mb = tr ? M->matT : M->mat;
+  auto clamp_lanes = [](int l) { return l <= 4 ? 4 : (l >= 16 ? 16 : 8); };
+  p.lanes_a = clamp_lanes(Ap.lanes);
+  p.lanes_m = clamp_lanes(p.Mb.lanes);
+  p.f_rp = tr ? M->mT_rp : M->m_rp;
+  p.f_col = tr ? M->mT_col : M->m_col;
+  p.f_val = tr ? M->mT_val : M->m_val;
+  p.x0_mode = tol->x0_mode;
+  p.trans = tr;
+  p.ur_dd = tol->ur_dd;
+  p.i_max = tol->i_max;
+  p.tau = tol->tau;
+  p.tol_rr = tol->tol_rr;
+  p.tol_be = tol->tol_be;
+  p.b = b;
+  p.x = x;
+  p.rv = reinterpret_cast<VT *>(base + o_rv);
+  p.w = reinterpret_cast<VT *>(base + o_w);
+  p.zg = reinterpret_cast<VT *>(base + o_zg);
+  p.V = reinterpret_cast<VT *>(base + o_V);
+  p.dv = reinterpret_cast<double *>(base + o_dv);
+  p.dv2 = reinterpret_cast<double *>(base + o_dv2);
+  p.grid.flags = reinterpret_cast<unsigned *>(base + o_flags);
+  p.grid.abortf = reinterpret_cast<unsigned *>(base + o_abort);
+  p.grid.slots = reinterpret_cast<double *>(base + o_slots);
+  p.grid.G = G;
+  p.stats = reinterpret_cast<gmres_ir_stats *>(base + o_stats);
+  BSPAI_HIP(hipMemsetAsync(p.grid.flags, 0, 4 * kMaxBlocks, s));
+  BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
+  BSPAI_HIP(hipMemsetAsync(p.stats, 0, sizeof(gmres_ir_stats), s));
+  size_t lds = sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2);
+  void *fn = nullptr;
+  switch (ZR) {
+    case 1: fn = (void *)k_gmres_ir<VT, 1>; break;
+    case 2: fn = (void *)k_gmres_ir<VT, 2>; break;
+    case 4: fn = (void *)k_gmres_ir<VT, 4>; break;
+    case 8: fn = (void *)k_gmres_ir<VT, 8>; break;
+    default: fn = (void *)k_gmres_ir<VT, 16>; break;
+  }
+  BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  void *args[] = {&p};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if (g_profile) {
+    BSPAI_HIP(hipEventCreate(&ev[0]));
+    BSPAI_HIP(hipEventCreate(&ev[1]));
+    BSPAI_HIP(hipEventRecord(ev[0], s));
+  }
+  BSPAI_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kSolveThreads), args, (unsigned)lds, s));
+  if (g_profile) BSPAI_HIP(hipEventRecord(ev[1], s));
+  gmres_ir_stats hs;
+  unsigned aborted = 0;
+  BSPAI_HIP(hipMemcpyAsync(&hs, p.stats, sizeof(hs), hipMemcpyDeviceToHost, s));
+  BSPAI_HIP(hipMemcpyAsync(&aborted, p.grid.abortf, 4, hipMemcpyDeviceToHost, s));
+  BSPAI_HIP(hipStreamSynchronize(s));
+  if (g_profile) {
+    float ms = 0.f;
+    BSPAI_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    g_last_ms = ms;
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+  }
+  if (aborted) return fail(BSPAI_EHIP, "gmres_ir_solve: grid synchronisation timed out");
+  if (st_host) *st_host = hs;
+  if (hs.status == BSPAI_ENOCONV)
+    return fail(BSPAI_ENOCONV, "gmres_ir_solve: %d refinement steps without meeting a tolerance", hs.steps);
+  if (hs.status == BSPAI_ENAN) return fail(BSPAI_ENAN, "gmres_ir_solve: NaN or infinity in the residual");
+  return hs.status;
+}
+
+}  // namespace bspai
+
+using namespace bspai;
+
+extern "C" void bspai_set_profiling(int on) { g_profile = on ? 1 : 0; }
+extern "C" double bspai_last_solve_kernel_ms(void) { return g_last_ms; }
+
+extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
+                              double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
+  if (!A || !M || !tol) return fail(BSPAI_EINVAL, "gmres_ir_solve: null argument");
+  if (A->n != M->n) return fail(BSPAI_EINVAL, "gmres_ir_solve: A is %d x %d but M is %d x %d", A->n, A->n, M->n, M->n);
+  if (A->n < 1) return fail(BSPAI_EINVAL, "gmres_ir_solve: empty system");
+  if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val)) || !b || !x)
+    return fail(BSPAI_EINVAL, "gmres_ir_solve: null device pointer");
+  if (nrhs != 1) return fail(BSPAI_EINVAL, "gmres_ir_solve: this entry point takes nrhs = 1 (got %d)", nrhs);
+  if (tol->u_g != BSPAI_FP32 && tol->u_g != BSPAI_FP64) return fail(BSPAI_EINVAL, "gmres_ir_solve: u_g must be FP32 or FP64");
+  if (tol->x0_mode < 0 || tol->x0_mode > 3) return fail(BSPAI_EINVAL, "gmres_ir_solve: x0_mode must be 0..3");
+  if (tol->i_max < 0) return fail(BSPAI_EINVAL, "gmres_ir_solve: i_max < 0");
+  if (tol->trans && !M->has_T) return fail(BSPAI_EINVAL, "gmres_ir_solve: trans needs a handle built with build_T");
+  if (tol->x0_mode == 0 && !M->has_fp64) return fail(BSPAI_EINVAL, "gmres_ir_solve: x0_mode 0 needs keep_fp64_M");
+  int dev = 0;
+  BSPAI_HIP(hipGetDevice(&dev));
+  if (dev != M->device) return fail(BSPAI_EINVAL, "gmres_ir_solve: handle lives on device %d", M->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (tol->u_g == BSPAI_FP64) return solve_typed<double>(A, b, M, tol, x, st_host, s);
+  return solve_typed<float>(A, b, M, tol, x, st_host, s);
+}

@@ -1,0 +1,397 @@
+"""Parity of the HIP path (through the C interface) with the CPU oracle.
+
+Bar: bit-exact for bucket ids, stored values and everything integer; floating
+point within the bounds derived in each test from the arithmetic (FP32 or FP64
+accumulation of exactly decoded values).  Sizes span several workgroups and
+ragged tails; full-size workloads are checked on sampled rows.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    import paper_2307_03914_amd as B
+
+    torch.cuda.set_device(0)
+    return B
+
+
+def _dev(a, dtype=None):
+    import torch
+
+    t = torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    return t if dtype is None else t.to(dtype)
+
+
+def _spai_oracle(A, P, rows=None):
+    st, Mv, bad = O.spai(A, P, rows=rows)
+    assert st == O.OK, (st, bad)
+    return W.CSR(A.n, P.row_ptr, P.col, Mv)
+
+
+# ---------------------------------------------------------------- formats
+
+@pytest.mark.parametrize("prec,pin", [(O.FP16, 32768.0), (O.FP8, 256.0), (O.BF16, None), (O.FP32, None)])
+def test_device_encoders_match_oracle(B, prec, pin):
+    # A diagonal M whose largest entry pins the bucket scale to 1: the stored
+    # values are then exactly the format's rounding of each entry.
+    _say("encoders", prec)
+    rng = np.random.default_rng(100 + prec)
+    if prec == O.FP16:
+        codes = np.arange(1 << 16, dtype=np.uint32)
+        base = O.decode(O.FP16, codes)
+        lo, hi = -26, 15
+    elif prec == O.FP8:
+        base = O.decode(O.FP8, np.arange(256, dtype=np.uint32))
+        lo, hi = -11, 8
+    else:
+        base = np.zeros(0)
+        lo, hi = -140, 100
+    base = base[np.isfinite(base)]
+    # exact codes, midpoints between neighbours (ties), and random doubles
+    srt = np.unique(np.abs(base))
+    mids = 0.5 * (srt[1:] + srt[:-1])
+    rnd = np.exp2(rng.uniform(lo, hi, 200000)) * np.where(rng.random(200000) < 0.5, -1, 1)
+    vals = np.concatenate([base, mids, -mids, mids * (1 + 2.0 ** -40), rnd])
+    if pin is not None:
+        vals = vals[np.abs(vals) <= pin]
+        vals = np.concatenate([[pin], vals])
+    else:
+        vals = vals[np.abs(vals) < 1e30]
+    vals = vals[vals != 0]
+    n = vals.size
+    M = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), vals)
+    Md = B.CSRMatrix.from_host(M)
+    h = B.import_m(Md, 1e-3, [prec], build_T=False)
+    ex = h.export()
+    s = h.stats()
+    assert s["scale"][0] == 1.0
+    ref = O.round_to(prec, vals)
+    assert np.array_equal(ex["stored"], ref), np.flatnonzero(ex["stored"] != ref)[:10]
+    h.free()
+
+
+# ---------------------------------------------------------------- build
+
+def _workloads_small():
+    out = []
+    c = W.config("1")
+    out.append(("cfg1", c["A"], c["P"], c["precs"], 2.0 ** -53))
+    c = W.config("2", small=True)
+    for eps in c["eps"]:
+        out.append((f"cfg2s_eps{eps}", c["A"], c["P"], c["precs"], eps))
+    c = W.config("5", small=True)
+    out.append(("cfg5s", c["A"], c["P"], c["precs"], c["eps"][0]))
+    c = W.config("4a", small=True)
+    out.append(("cfg4as", c["A"], c["P"], c["precs"], c["eps"][0]))
+    rng = np.random.default_rng(7)
+    A = W.random_sparse(333, 0.02, rng, dominance=0.8)
+    out.append(("rand333_A2", A, W.pattern_power(A, 2), [O.FP64, O.FP32, O.FP16, O.BF16, O.FP8], 1e-3))
+    out.append(("rand333_drop", A, A.pattern(), [O.FP32, O.FP16, O.DROP], 2.0 ** -18))
+    return out
+
+
+@pytest.mark.parametrize("case", _workloads_small(), ids=lambda c: c[0])
+def test_import_bucketing_bit_exact(B, case):
+    name, A, P, precs, eps = case
+    _say("import/bucketing", name)
+    M = _spai_oracle(A, P)
+    ref = O.Bucketed(M, eps, precs)
+    h = B.import_m(B.CSRMatrix.from_host(M), eps, precs)
+    ex = h.export()
+    st = h.stats()
+    assert st["norm_inf"] == ref.normM
+    assert st["threshold"] == list(ref.t)
+    assert st["scale"] == list(ref.s)
+    assert st["count"] == list(ref.counts)
+    assert np.array_equal(ex["bucket"], ref.bucket)
+    assert np.array_equal(ex["stored"], ref.mt)
+    assert np.array_equal(ex["m64"], M.val)
+    h.free()
+
+
+@pytest.mark.parametrize("case", _workloads_small(), ids=lambda c: c[0])
+def test_build_spai_matches_oracle(B, case):
+    name, A, P, precs, eps = case
+    _say("build", name)
+    M = _spai_oracle(A, P)
+    h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), eps=eps, precs=precs)
+    ex = h.export()
+    # FP64 least squares in a different summation order: rows agree to a few
+    # units of roundoff times the conditioning of the small problems.
+    for i in range(A.n):
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        scale = np.abs(M.val[s]).max()
+        assert np.abs(ex["m64"][s] - M.val[s]).max() <= 1e-11 * scale, (name, i)
+    # bucket ids may differ only for entries within a few ulps of a threshold
+    ref = O.Bucketed(M, eps, precs)
+    diff = ex["bucket"] != ref.bucket
+    if diff.any():
+        t = np.array(ref.t)
+        a = np.abs(M.val[diff])
+        near = np.min(np.abs(a[:, None] - t[None, :]) / t[None, :], axis=1)
+        assert np.all(near <= 1e-12), (name, int(diff.sum()))
+    h.free()
+
+
+def test_build_zero_row_and_rank_errors(B):
+    _say("build errors")
+    D = np.array([[2.0, 1.0, 0.0], [1.0, 0.0, 1.0], [0.0, 1.0, 3.0]])
+    A = W.from_dense(D)
+    with pytest.raises(B.BSPAIError) as e:
+        B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(W.identity_pattern(3)), precs=["fp64"])
+    assert e.value.code == B.EZEROROW and "row 1" in str(e.value)
+
+
+def test_build_scaling_matches_unscaled(B):
+    _say("build scaling")
+    rng = np.random.default_rng(23)
+    A = W.random_sparse(300, 0.02, rng)
+    A.val *= np.exp(3 * rng.standard_normal(A.nnz))
+    P = W.pattern_power(A, 2)
+    M = _spai_oracle(A, P)
+    h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), precs=["fp64"], scale=True)
+    m = h.export()["m64"]
+    assert np.allclose(m, M.val, rtol=1e-8, atol=1e-11 * np.abs(M.val).max())
+
+
+# ---------------------------------------------------------------- apply
+
+def _apply_bound(Mb, x, acc_u, transpose=False):
+    """Per-row bound for |y_gpu - y_oracle| with accumulation unit acc_u:
+    (p + 2) acc_u sum_j |mt_ij x_j| + acc_u |y| (one output rounding)."""
+    Mt = Mb.transpose() if transpose else Mb
+    rows = np.repeat(np.arange(Mt.n), np.diff(Mt.row_ptr))
+    absy = np.zeros(Mt.n)
+    np.add.at(absy, rows, np.abs(Mt.mt) * np.abs(x[Mt.col]))
+    p = np.diff(Mt.row_ptr)
+    return (p + 2) * acc_u * absy
+
+
+@pytest.mark.parametrize("case", _workloads_small(), ids=lambda c: c[0])
+@pytest.mark.parametrize("mode", ["fp32", "fp64"])
+@pytest.mark.parametrize("trans", [False, True])
+def test_apply_matches_oracle(B, case, mode, trans):
+    import torch
+
+    name, A, P, precs, eps = case
+    _say("apply", name, mode, trans)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, eps, precs)
+    h = B.import_m(B.CSRMatrix.from_host(M), eps, precs)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(A.n)
+    if mode == "fp32":
+        x = x.astype(np.float32).astype(np.float64)
+    xd = _dev(x, torch.float32 if mode == "fp32" else torch.float64)
+    y = (B.apply_T if trans else B.apply)(h, xd).double().cpu().numpy()
+    ref = (O.apply_T if trans else O.apply)(Mb, x, O.FP64)
+    u = U32 if mode == "fp32" else U64
+    bound = _apply_bound(Mb, x, u, transpose=trans) + u * np.abs(ref)
+    err = np.abs(y - ref)
+    assert np.all(err <= bound + 1e-300), (name, np.flatnonzero(err > bound)[:5])
+    if mode == "fp64":  # the FP64-mode bar: 1e-12 relative
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+    h.free()
+
+
+@pytest.mark.parametrize("nrhs", [2, 8, 64, 70])
+def test_apply_multi_rhs_matches_columns(B, nrhs):
+    import torch
+
+    _say("spmm", nrhs)
+    c = W.config("2", small=True)
+    M = _spai_oracle(c["A"], c["P"])
+    Mb = O.Bucketed(M, 1e-4, c["precs"])
+    h = B.import_m(B.CSRMatrix.from_host(M), 1e-4, c["precs"])
+    X = np.random.default_rng(9).standard_normal((M.n, nrhs)).astype(np.float32).astype(np.float64)
+    Y = B.apply(h, _dev(X, torch.float32)).double().cpu().numpy()
+    YT = B.apply_T(h, _dev(X, torch.float32)).double().cpu().numpy()
+    for j in range(nrhs):
+        ref = O.apply(Mb, X[:, j])
+        assert np.all(np.abs(Y[:, j] - ref) <= _apply_bound(Mb, X[:, j], U32) + U32 * np.abs(ref) + 1e-300)
+        refT = O.apply_T(Mb, X[:, j])
+        assert np.all(np.abs(YT[:, j] - refT) <= _apply_bound(Mb, X[:, j], U32, True) + U32 * np.abs(refT) + 1e-300)
+    h.free()
+
+
+def test_apply_full_size_sampled_rows(B):
+    """Config 4a's operator at full size (n = 2,097,152, all entries bf16 at
+    eps = 1e-2): the HIP product checked on 2000 sampled rows against the
+    oracle's product of the same stored values."""
+    import torch
+
+    _say("apply full size 4a")
+    c = W.config("4a")
+    A, P = c["A"], c["P"]
+    h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), eps=1e-2, precs=c["precs"])
+    ex = h.export()
+    rows = np.sort(np.random.default_rng(3).choice(A.n, 2000, replace=False)).astype(np.int32)
+    Ms = _spai_oracle(A, P, rows=rows)
+    for i in rows[:200]:
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        assert np.abs(ex["m64"][s] - Ms.val[s]).max() <= 1e-11 * np.abs(Ms.val[s]).max()
+    x = np.random.default_rng(4).standard_normal(A.n).astype(np.float32)
+    y = B.apply(h, _dev(x)).double().cpu().numpy()
+    xd = x.astype(np.float64)
+    for i in rows:
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        ref = float(np.dot(ex["stored"][s], xd[P.col[s]]))
+        tol = (P.row_ptr[i + 1] - P.row_ptr[i] + 2) * U32 * float(np.abs(ex["stored"][s]) @ np.abs(xd[P.col[s]]))
+        assert abs(y[i] - ref) <= tol + U32 * abs(ref)
+    st = h.stats()
+    assert st["count"][-1] == A.nnz  # every entry lands in the bf16 bucket at eps = 1e-2
+    h.free()
+
+
+# ---------------------------------------------------------------- solve
+
+def _solve_case(B, A, P, b, precs, eps, **kw):
+    import torch
+
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=precs)
+    x, st = B.solve(Ad, _dev(b), h, **kw)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), st, h
+
+
+@pytest.mark.parametrize("key,eps_i", [("1", 0), ("2s", 0), ("2s", 1), ("2s", 2), ("5s", 0), ("4as", 0)])
+def test_solve_matches_oracle(B, key, eps_i):
+    small = key.endswith("s")
+    c = W.config(key[:-1] if small else key, small=small)
+    A, P = c["A"], c["P"]
+    b = c["b"] if c["b"].ndim == 1 else c["b"][:, 0].copy()
+    eps = c["eps"][eps_i]
+    _say("solve", key, eps)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    xg, st, h = _solve_case(B, A, P, b, c["precs"], eps, **kw)
+    M = _spai_oracle(A, P)
+    ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, **kw)
+    eta_g = O.backward_error(A, b, xg)
+    assert st["status"] == ref["status"] == 0
+    assert st["stop_reason"] == ref["stop_reason"] == 1
+    assert eta_g <= 10 * ref["eta"][-1] + 1e-17
+    assert abs(st["steps"] - ref["steps"]) <= 1
+    assert abs(st["its_total"] - ref["its_total"]) <= max(3, 0.15 * ref["its_total"]), (st["its"], ref["its"])
+    if c["x_true"] is not None:
+        fe_g = np.abs(xg - c["x_true"]).max() / np.abs(c["x_true"]).max()
+        fe_r = np.abs(ref["x"] - c["x_true"]).max() / np.abs(c["x_true"]).max()
+        assert fe_g <= 10 * fe_r + 1e-15
+    # the library's own eta for its final x equals the oracle's formula on it
+    assert np.isclose(st["eta"][-1], eta_g, rtol=1e-12, atol=0)
+    h.free()
+
+
+def test_solve_fp64_working_precision(B):
+    c = W.config("2", small=True)
+    _say("solve fp64")
+    xg, st, h = _solve_case(B, c["A"], c["P"], c["b"], [O.FP64], 2.0 ** -53, u_g="fp64", tau=1e-8, tol_rr=1e-12,
+                            gmres_max=150)
+    assert st["status"] == 0 and st["relres"][-1] <= 1e-12
+    assert O.backward_error(c["A"], c["b"], xg) <= 1e-15
+    h.free()
+
+
+def test_solve_noconvergence_and_zero_rhs(B):
+    import torch
+
+    c = W.config("1", small=True)
+    _say("solve edge cases")
+    Ad = B.CSRMatrix.from_host(c["A"])
+    h = B.build(Ad, B.CSRMatrix.from_host(c["P"]), precs=["fp64"])
+    x, st = B.solve(Ad, _dev(c["b"]), h, tol_rr=1e-30, i_max=1)
+    assert st["status"] == B.ENOCONV and st["steps"] == 1 and st["stop_reason"] == 4
+    with pytest.raises(B.BSPAIError):
+        B.solve(Ad, _dev(c["b"]), h, tol_rr=1e-30, i_max=1, raise_noconv=True)
+    x, st = B.solve(Ad, torch.zeros(c["A"].n, dtype=torch.float64, device="cuda"), h)
+    assert st["steps"] == 0 and float(x.abs().max()) == 0.0
+    h.free()
+
+
+def test_solve_n1_and_tiny(B):
+    _say("solve n=1, n=5")
+    for n in (1, 5):
+        D = np.diag(np.arange(1.0, n + 1.0)) + np.diag(np.full(max(n - 1, 0), 0.3), 1)
+        A = W.from_dense(D)
+        b = np.ones(n)
+        xg, st, h = _solve_case(B, A, A.pattern(), b, [O.FP64, O.FP32], 1e-6, tol_rr=1e-12)
+        assert np.allclose(xg, np.linalg.solve(D, b), rtol=1e-12)
+        h.free()
+
+
+def test_adjoint_solve_and_gradient(B):
+    import torch
+
+    c = W.config("5", small=True)
+    A, P = c["A"], c["P"]
+    _say("adjoint")
+    kw = dict(tau=1e-4, tol_rr=1e-13, gmres_max=150, i_max=30)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=c["eps"][0], precs=c["precs"])
+    g = np.random.default_rng(11).standard_normal(A.n)
+    lam, st = B.solve(Ad, _dev(g), h, trans=True, **kw)
+    lam = lam.cpu().numpy()
+    D = A.dense()
+    ref = np.linalg.solve(D.T, g)
+    assert st["status"] == 0
+    assert np.abs(lam - ref).max() <= 1e-9 * np.abs(ref).max()
+    M = _spai_oracle(A, P)
+    x = np.linalg.solve(D, c["b"])
+    og = O.gradient(A, M, O.Bucketed(M, c["eps"][0], c["precs"]), x, g, **kw)
+    assert np.abs(lam - og["grad_b"]).max() <= 1e-6 * np.abs(og["grad_b"]).max()
+    h.free()
+
+
+def test_autograd_matches_oracle_and_fd(B):
+    import torch
+
+    c = W.config("5", small=True)
+    A, P = c["A"], c["P"]
+    _say("autograd")
+    kw = dict(tau=1e-4, tol_rr=1e-13, gmres_max=150, i_max=30)
+    Ap = B.CSRMatrix.from_host(A)
+    h = B.build(Ap, B.CSRMatrix.from_host(P), eps=c["eps"][0], precs=c["precs"])
+    vals = torch.tensor(A.val, device="cuda", requires_grad=True)
+    b = torch.tensor(c["b"], device="cuda", requires_grad=True)
+    xobs = torch.tensor(np.linalg.solve(A.dense(), c["b"]) * 1.01, device="cuda")
+    x = B.BSPAISolve.apply(vals, b, Ap, h, kw)
+    loss = ((x - xobs) ** 2).sum()
+    loss.backward()
+    gv, gb = vals.grad.cpu().numpy(), b.grad.cpu().numpy()
+    M = _spai_oracle(A, P)
+    xx = x.detach().cpu().numpy()
+    og = O.gradient(A, M, O.Bucketed(M, c["eps"][0], c["precs"]), xx, 2 * (xx - xobs.cpu().numpy()), **kw)
+    assert np.abs(gb - og["grad_b"]).max() <= 1e-6 * np.abs(og["grad_b"]).max()
+    assert np.abs(gv - og["grad_vals"]).max() <= 1e-6 * np.abs(og["grad_vals"]).max()
+    # central finite differences of the loss along random directions in b
+    rng = np.random.default_rng(12)
+    D = A.dense()
+    xo = xobs.cpu().numpy()
+    for _ in range(8):
+        d = rng.standard_normal(A.n)
+        hstep = 1e-3
+        f = lambda bb: float(((np.linalg.solve(D, bb) - xo) ** 2).sum())
+        fd = (-f(c["b"] + 2 * hstep * d) + 8 * f(c["b"] + hstep * d) - 8 * f(c["b"] - hstep * d)
+              + f(c["b"] - 2 * hstep * d)) / (12 * hstep)
+        assert abs(fd - gb @ d) <= 1e-6 * abs(fd) + 1e-12
+    h.free()
