@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-apply-bench", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--only-apply", action="store_true", help="run only the cold bucketed-apply measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --only-apply: also run one 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -102,6 +105,18 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
+    if args.only_apply:
+        res = apply_bench(B, W, torch, np)
+        if args.copy_calibration:
+            # a plain device copy of known size, for scaling hardware byte counters
+            a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+            b2 = torch.empty_like(a)
+            torch.cuda.synchronize()
+            b2.copy_(a)
+            torch.cuda.synchronize()
+            res["copy_calibration_bytes"] = {"read": a.numel() * 4, "write": a.numel() * 4}
+        print(json.dumps({"m_apply": res}), flush=True)
+        return
     _log("generating workload")
     c = W.config("2")
     A, P = c["A"], c["P"]
@@ -219,20 +234,42 @@ def apply_bench(B, W, torch, np):
     for i in range(copies):
         B.apply(hs[i], xs[i], ys[i])
     torch.cuda.synchronize()
-    reps = 200
+    reps = int(os.environ.get("BSPAI_APPLY_REPS", "200"))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # launches captured in a graph: the replay times the kernels, not the
+    # Python-side call overhead of each apply
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        for i in range(copies):
+            B.apply(hs[i], xs[i], ys[i])
+    torch.cuda.current_stream().wait_stream(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for r in range(reps):
+            B.apply(hs[r % copies], xs[r % copies], ys[r % copies])
+    graph.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    # the same launches issued one by one from Python, for reference
     e0.record()
     for r in range(reps):
         B.apply(hs[r % copies], xs[r % copies], ys[r % copies])
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms_eager = e0.elapsed_time(e1) / reps
     for hh in hs:
         hh.free()
     gbs = bytes_per / (ms * 1e-3) / 1e9
-    _log(f"apply: {ms * 1e3:.1f} us per launch, {gbs:.0f} GB/s")
+    _log(f"apply: {ms * 1e3:.1f} us per launch, {gbs:.0f} GB/s (issued from Python one by one: {ms_eager * 1e3:.1f} us)")
     return {"workload": "aniso3d 128^3 7-point (n=2097152), M on pattern(A), bf16 bucket (eps=1e-2), fp32 x/y, "
-                        "8 rotating copies (cold HBM)", "bucket_counts": st["count"], "us_per_launch": ms * 1e3,
+                        "8 rotating copies (cold HBM), launches replayed from a captured graph", "bucket_counts": st["count"],
+            "us_per_launch": ms * 1e3, "us_per_launch_python_issued": ms_eager * 1e3,
             "algorithmic_bytes": bytes_per, "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
             "bytes_per_nnz": bytes_per / max(1, sum(st["count"]))}
 

@@ -339,6 +339,9 @@ static void free_handle_memory(bspai_handle *h) {
   for (int k = 0; k < kMaxBuckets; k++) {
     dfree(h->b[k].rp), dfree(h->b[k].col), dfree(h->b[k].val);
     dfree(h->b[k].rpT), dfree(h->b[k].colT), dfree(h->b[k].valT);
+    dfree(h->b[k].sptr), dfree(h->b[k].scol), dfree(h->b[k].sval);
+    dfree(h->b[k].sptrT), dfree(h->b[k].scolT), dfree(h->b[k].svalT);
+    dfree(h->b[k].ecol), dfree(h->b[k].eval), dfree(h->b[k].ecolT), dfree(h->b[k].evalT);
   }
   dfree(h->m_rp), dfree(h->m_col), dfree(h->m_val);
   dfree(h->mT_rp), dfree(h->mT_col), dfree(h->mT_val);
@@ -448,6 +451,26 @@ static int bucketize(bspai_handle *h, const bspai_prec *precs, int q, double eps
     M.nb++;
   }
   M.lanes = pick_lanes(M, M.nnz);
+  M.aligned = bmat_aligned(M);
+  {  // SELL-64 copies of the stored buckets for the products
+    int j = 0;
+    for (int k = q - 1; k >= 0; k--) {
+      if (precs[k] == BSPAI_DROP || h->b[k].nnz == 0) continue;
+      Bucket &B = h->b[k];
+      int32_t w = 0;
+      int r = csr_to_sell(n, B.rp, B.col, B.val, value_bytes(B.prec), &B.sptr, &B.scol, &B.sval, &w, s);
+      if (r) return r;
+      M.sell_w[j] = w;
+      if ((r = csr_to_ell(n, B.rp, B.col, B.val, value_bytes(B.prec), &B.ecol, &B.eval, &w, s))) return r;
+      M.ell_w[j] = w;
+      M.ell_col[j] = B.ecol;
+      M.ell_val[j] = B.eval;
+      M.sell_ptr[j] = B.sptr;
+      M.sell_col[j] = B.scol;
+      M.sell_val[j] = B.sval;
+      j++;
+    }
+  }
   if (o.build_T) {
     BMat &T = h->matT;
     T = M;
@@ -463,8 +486,20 @@ static int bucketize(bspai_handle *h, const bspai_prec *precs, int q, double eps
       T.rp[j] = B.rpT;
       T.col[j] = B.colT;
       T.val[j] = B.valT;
+      int32_t w = 0;
+      if ((r = csr_to_sell(n, B.rpT, B.colT, B.valT, value_bytes(B.prec), &B.sptrT, &B.scolT, &B.svalT, &w, s)))
+        return r;
+      T.sell_w[j] = w;
+      if ((r = csr_to_ell(n, B.rpT, B.colT, B.valT, value_bytes(B.prec), &B.ecolT, &B.evalT, &w, s))) return r;
+      T.ell_w[j] = w;
+      T.ell_col[j] = B.ecolT;
+      T.ell_val[j] = B.evalT;
+      T.sell_ptr[j] = B.sptrT;
+      T.sell_col[j] = B.scolT;
+      T.sell_val[j] = B.svalT;
       j++;
     }
+    T.aligned = bmat_aligned(T);
     if (h->has_fp64) {
       int r;
       if ((r = dalloc_t(&h->mT_rp, (size_t)n + 1)) || (r = dalloc_t(&h->mT_col, (size_t)nnz + 1)) ||

@@ -43,14 +43,31 @@ inline int value_bytes(int p) {
 struct BMat {
   int32_t n;
   int32_t nb;
-  int32_t lanes;  // lanes per row chosen for the single-vector product
-  int64_t nnz;    // stored entries (all buckets)
+  int32_t lanes;    // lanes per row chosen for the single-vector product
+  int32_t aligned;  // every col / val array is 16-byte aligned (tile product allowed)
+  int64_t nnz;      // stored entries (all buckets)
   int32_t prec[kMaxBuckets];
   double scale[kMaxBuckets];
   const int32_t *rp[kMaxBuckets];
   const int32_t *col[kMaxBuckets];
   const void *val[kMaxBuckets];
+  // the same buckets in SELL-64 form (64-row slices stored column by column,
+  // short rows padded with zero values): entry u of row 64 s + r of bucket k
+  // is at sell_ptr[k][s] + 64 u + r.  sell_ptr null: not available.
+  const int32_t *sell_ptr[kMaxBuckets];
+  const int32_t *sell_col[kMaxBuckets];
+  const void *sell_val[kMaxBuckets];
+  // > 0: every slice of the bucket has this width (ELL), so slice s starts at
+  // 64 s w and the kernels need not load sell_ptr
+  int32_t sell_w[kMaxBuckets];
+  // row-major padded copy (ELL): row i's entries at i W .. i W + W - 1, W in
+  // {4, 8, 16}, padding entries with value 0; ell_w 0: not available
+  const int32_t *ell_col[kMaxBuckets];
+  const void *ell_val[kMaxBuckets];
+  int32_t ell_w[kMaxBuckets];
 };
+
+constexpr int kSlice = 64;
 
 struct Bucket {
   int prec = BSPAI_FP64;
@@ -60,6 +77,10 @@ struct Bucket {
   void *val = nullptr;
   int32_t *rpT = nullptr, *colT = nullptr;
   void *valT = nullptr;
+  int32_t *sptr = nullptr, *scol = nullptr, *sptrT = nullptr, *scolT = nullptr;
+  void *sval = nullptr, *svalT = nullptr;
+  int32_t *ecol = nullptr, *ecolT = nullptr;
+  void *eval = nullptr, *evalT = nullptr;
 };
 
 }  // namespace bspai
@@ -116,8 +137,23 @@ int exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *tmp, hipStr
 int csr_transpose(int n, int64_t nnz, const int32_t *rp, const int32_t *col, const void *val, int vbytes,
                   int32_t *trp, int32_t *tcol, void *tval, hipStream_t s);
 
+// SELL-64 copy of one CSR (values of vbytes bytes); allocates *sptr (n/64+1),
+// *scol and *sval (padded length).
+// *width gets the common slice width when all slices are padded to the
+// widest one (chosen when that pads at most 15% more than per-slice widths),
+// else 0.
+int csr_to_sell(int n, const int32_t *rp, const int32_t *col, const void *val, int vbytes, int32_t **sptr,
+                int32_t **scol, void **sval, int32_t *width, hipStream_t s);
+
+// Row-major padded (ELL) copy of one CSR when every row has at most 16
+// entries and padding to W in {4, 8, 16} adds at most 25% entries; *width
+// gets W, or 0 (and nothing allocated) otherwise.
+int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, int vbytes, int32_t **ecol,
+               void **evalp, int32_t *width, hipStream_t s);
+
 // Bucketed product kernels (apply.hip), used by the public apply and the build.
 int pick_lanes(const BMat &M, int64_t nnz);
+int bmat_aligned(const BMat &M);
 int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s);
 
 }  // namespace bspai

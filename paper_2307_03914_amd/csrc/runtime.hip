@@ -1,6 +1,9 @@
 // Error reporting, device allocation, prefix sums and CSR transposition.
 #include <cstdarg>
+#include <algorithm>
+#include <climits>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 
@@ -212,6 +215,160 @@ int csr_transpose(int n, int64_t nnz, const int32_t *rp, const int32_t *col, con
   rc = body();
   dfree(cnt), dfree(fill), dfree(tsrc), dfree(tmp);
   return rc;
+}
+
+// ------------------------------------------------------------------ SELL-64
+
+__global__ void k_slice_len(int n, const int32_t *rp, int32_t *len) {
+  int sl = blockIdx.x * blockDim.x + threadIdx.x;
+  int ns = (n + kSlice - 1) / kSlice;
+  if (sl >= ns) return;
+  int mx = 0;
+  for (int r = sl * kSlice; r < min(n, (sl + 1) * kSlice); r++) mx = max(mx, rp[r + 1] - rp[r]);
+  len[sl] = mx * kSlice;
+}
+
+__global__ void k_sell_fill(int n, const int32_t *rp, const int32_t *col, const uint8_t *val, int vbytes,
+                            const int32_t *sptr, int32_t *scol, uint8_t *sval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int ns = (n + kSlice - 1) / kSlice;
+  if (i >= ns * kSlice) return;
+  int sl = i / kSlice, r = i % kSlice;
+  int len = (sptr[sl + 1] - sptr[sl]) / kSlice;
+  int s = i < n ? rp[i] : 0, e = i < n ? rp[i + 1] : 0;
+  int pad_col = i < n ? i : 0;
+  for (int u = 0; u < len; u++) {
+    int64_t dst = (int64_t)sptr[sl] + (int64_t)u * kSlice + r;
+    if (s + u < e) {
+      scol[dst] = col[s + u];
+      for (int b = 0; b < vbytes; b++) sval[dst * vbytes + b] = val[(int64_t)(s + u) * vbytes + b];
+    } else {
+      scol[dst] = pad_col;
+      for (int b = 0; b < vbytes; b++) sval[dst * vbytes + b] = 0;  // +0 in every format
+    }
+  }
+}
+
+__global__ void k_fill_value(int32_t *a, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+int csr_to_sell(int n, const int32_t *rp, const int32_t *col, const void *val, int vbytes, int32_t **sptr,
+                int32_t **scol, void **sval, int32_t *width, hipStream_t s) {
+  *sptr = nullptr, *scol = nullptr, *sval = nullptr;
+  *width = 0;
+  int ns = (n + kSlice - 1) / kSlice;
+  int32_t *len = nullptr;
+  void *tmp = nullptr;
+  int rc;
+  if ((rc = dalloc_t(&len, (size_t)ns + 1)) || (rc = dalloc(&tmp, scan_tmp_bytes(ns))) ||
+      (rc = dalloc_t(sptr, (size_t)ns + 1))) {
+    dfree(len), dfree(tmp), dfree(*sptr);
+    *sptr = nullptr;
+    return rc;
+  }
+  auto body = [&]() -> int {
+    if (ns > 0) {
+      hipLaunchKernelGGL(k_slice_len, dim3((ns + 255) / 256), dim3(256), 0, s, n, rp, len);
+      BSPAI_CHECK_LAUNCH();
+    }
+    int32_t total = 0, wmax = 0;
+    if (ns > 0) {
+      std::vector<int32_t> hl((size_t)ns);
+      BSPAI_HIP(hipMemcpyAsync(hl.data(), len, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipStreamSynchronize(s));
+      int64_t tot = 0;
+      for (int32_t v : hl) {
+        tot += v;
+        wmax = std::max(wmax, v / kSlice);
+      }
+      if ((double)ns * kSlice * wmax <= 1.15 * (double)tot && (int64_t)ns * kSlice * wmax < INT32_MAX) {
+        *width = wmax;  // one width for all slices
+        hipLaunchKernelGGL(k_fill_value, dim3((ns + 255) / 256), dim3(256), 0, s, len, (int64_t)ns, wmax * kSlice);
+        BSPAI_CHECK_LAUNCH();
+      }
+    }
+    int r = exclusive_scan(len, *sptr, ns, tmp, s);
+    if (r) return r;
+    BSPAI_HIP(hipMemcpyAsync(&total, *sptr + ns, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    if ((r = dalloc_t(scol, (size_t)total + kSlice)) || (r = dalloc(sval, (size_t)vbytes * (total + kSlice))))
+      return r;
+    if (ns > 0) {
+      hipLaunchKernelGGL(k_sell_fill, dim3((ns * kSlice + 255) / 256), dim3(256), 0, s, n, rp, col,
+                         static_cast<const uint8_t *>(val), vbytes, *sptr, *scol, static_cast<uint8_t *>(*sval));
+      BSPAI_CHECK_LAUNCH();
+    }
+    BSPAI_HIP(hipStreamSynchronize(s));
+    return BSPAI_OK;
+  };
+  rc = body();
+  dfree(len), dfree(tmp);
+  if (rc) {
+    dfree(*sptr), dfree(*scol), dfree(*sval);
+    *sptr = nullptr, *scol = nullptr, *sval = nullptr;
+  }
+  return rc;
+}
+
+// ------------------------------------------------------------------ ELL
+
+__global__ void k_row_len_max(int n, const int32_t *rp, int32_t *mx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicMax(mx, rp[i + 1] - rp[i]);
+}
+
+__global__ void k_ell_fill(int n, const int32_t *rp, const int32_t *col, const uint8_t *val, int vbytes, int w,
+                           int32_t *ecol, uint8_t *eval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1];
+  for (int u = 0; u < w; u++) {
+    int64_t dst = (int64_t)i * w + u;
+    if (s + u < e) {
+      ecol[dst] = col[s + u];
+      for (int b = 0; b < vbytes; b++) eval[dst * vbytes + b] = val[(int64_t)(s + u) * vbytes + b];
+    } else {
+      ecol[dst] = i;
+      for (int b = 0; b < vbytes; b++) eval[dst * vbytes + b] = 0;
+    }
+  }
+}
+
+int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, int vbytes, int32_t **ecol,
+               void **evalp, int32_t *width, hipStream_t s) {
+  *ecol = nullptr, *evalp = nullptr, *width = 0;
+  if (n == 0) return BSPAI_OK;
+  int32_t *mx = nullptr;
+  int rc;
+  if ((rc = dalloc_t(&mx, 1))) return rc;
+  int32_t hmx = 0, nnz = 0;
+  auto body = [&]() -> int {
+    BSPAI_HIP(hipMemsetAsync(mx, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_row_len_max, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, mx);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipMemcpyAsync(&hmx, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    return BSPAI_OK;
+  };
+  rc = body();
+  dfree(mx);
+  if (rc) return rc;
+  int w = hmx <= 4 ? 4 : (hmx <= 8 ? 8 : (hmx <= 16 ? 16 : 0));
+  if (w == 0 || (double)n * w > 1.25 * (double)std::max(nnz, 1) || (int64_t)n * w >= INT32_MAX) return BSPAI_OK;
+  if ((rc = dalloc_t(ecol, (size_t)n * w)) || (rc = dalloc(evalp, (size_t)n * w * vbytes))) {
+    dfree(*ecol), dfree(*evalp);
+    *ecol = nullptr, *evalp = nullptr;
+    return rc;
+  }
+  hipLaunchKernelGGL(k_ell_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, col, static_cast<const uint8_t *>(val),
+                     vbytes, w, *ecol, static_cast<uint8_t *>(*evalp));
+  BSPAI_CHECK_LAUNCH();
+  BSPAI_HIP(hipStreamSynchronize(s));
+  *width = w;
+  return BSPAI_OK;
 }
 
 }  // namespace bspai

@@ -29,14 +29,16 @@ constexpr int kWaves = kSolveThreads / 64;
 constexpr int kNumSlots = 4;
 constexpr int kMaxBlocks = 256;
 constexpr int kMaxSlotWidth = 2;
-// Largest GMRES cap whose packed triangular R and rotation state fit in LDS.
-constexpr int kMaxGmres = 184;
+// Largest GMRES cap whose packed triangular R and rotation state fit in LDS
+// next to the product tile.
+constexpr int kMaxGmres = 160;
+constexpr int kTileBytes = 49152;  // LDS for the products of one sub-range of rows
 constexpr unsigned kSpinLimit = 1u << 27;  // ~ seconds: a bound, never reached by a healthy run
 
 struct Grid {
   unsigned *flags;  // [G] epoch reached by each block
   unsigned *abortf; // set when a wait exceeds the spin bound
-  double *slots;    // [kNumSlots][kMaxBlocks][kMaxSlotWidth]
+  double *slots;    // [kNumSlots][kMaxBlocks][kMaxSlotWidth][2] tagged 64-bit words
   int G;
 };
 
@@ -44,6 +46,7 @@ template <typename VT>
 struct SolveParams {
   int n, G, rows_per_block, m_max;
   int lanes_a, lanes_m;
+  int rows_a, rows_m;  // rows per sub-range of the tile products
   const int32_t *a_rp, *a_col;
   const double *a_val;  // A (A^T for trans) in FP64, for the residual and ||A||_inf
   BMat Ap;              // the same matrix with values rounded to u_p = u_g
@@ -93,34 +96,97 @@ __device__ __forceinline__ double wave_red(double v) {
   return v;
 }
 
-// every thread gets the block total (fixed tree: deterministic)
-template <bool MAX>
-__device__ double block_red(double v, double *sh) {
-  v = wave_red<MAX>(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = (threadIdx.x & 63) < kWaves ? sh[threadIdx.x & 63] : (MAX ? 0.0 : 0.0);
-  return wave_red<MAX>(t);
+// A scalar exchange needs no fences: every block publishes its FP64 partial as
+// two 64-bit words (payload in the upper 48 bits, the low 16 bits carry the
+// exchange's sequence tag) with relaxed agent-scope atomic stores, and readers
+// poll the words with relaxed atomic loads until both tags match.  Atomicity of
+// each word is all the protocol relies on; no cache is written back or
+// invalidated, so the blocks keep their basis slices in L2.
+__device__ __forceinline__ void publish_partial(unsigned long long *w, double v, unsigned tag) {
+  unsigned long long b = __double_as_longlong(v);
+  unsigned long long t = tag & 0xFFFFull;
+  __hip_atomic_store(&w[0], (b & ~0xFFFFull) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&w[1], ((b & 0xFFFFull) << 16) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// all-reduction of W values over the grid; all blocks obtain identical results
+// returns false when the wait exceeds the bound or another block aborted
+__device__ __forceinline__ bool collect_partial(unsigned long long *w, unsigned tag, const unsigned *abortf,
+                                                double *out) {
+  const unsigned long long t = tag & 0xFFFFull;
+  unsigned long long a, b;
+  unsigned spins = 0;
+  for (;;) {
+    a = __hip_atomic_load(&w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b = __hip_atomic_load(&w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((a & 0xFFFFull) == t && (b & 0xFFFFull) == t) break;
+    if (++spins > kSpinLimit || __hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+  }
+  *out = __longlong_as_double((long long)((a & ~0xFFFFull) | ((b >> 16) & 0xFFFFull)));
+  return true;
+}
+
+// All-reduction of W values over the grid (sum or max).  Every block combines
+// the same G partials in the same order, so all blocks obtain identical
+// results.  Two workgroup barriers; data other than the scalars is not
+// published (use grid_sync for that).
 template <int W, bool MAX>
-__device__ bool grid_reduce(const Grid &g, unsigned &epoch, double (&v)[W], double *sh) {
+__device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], double *sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double part[W];
 #pragma unroll
-  for (int c = 0; c < W; c++) v[c] = block_red<MAX>(v[c], sh);
-  if (g.G == 1) return true;
-  double *slot = g.slots + (size_t)((epoch + 1) % kNumSlots) * kMaxBlocks * kMaxSlotWidth;
-  if (threadIdx.x == 0) {
+  for (int c = 0; c < W; c++) part[c] = wave_red<MAX>(v[c]);
+  if (lane == 0) {
 #pragma unroll
-    for (int c = 0; c < W; c++) slot[blockIdx.x * kMaxSlotWidth + c] = v[c];
+    for (int c = 0; c < W; c++) sh[wv * W + c] = part[c];
   }
-  if (!grid_sync(g, epoch)) return false;
+  __syncthreads();
+  double *res = sh + kWaves * W;
+  int bad = 0;
+  rtag++;
+  if (g.G == 1) {
+    if (threadIdx.x == 0) {
 #pragma unroll
-  for (int c = 0; c < W; c++) {
-    double t = (int)threadIdx.x < g.G ? slot[threadIdx.x * kMaxSlotWidth + c] : 0.0;
-    v[c] = block_red<MAX>(t, sh);
+      for (int c = 0; c < W; c++) {
+        double a = sh[c];
+        for (int k = 1; k < kWaves; k++) a = MAX ? fmax(a, sh[k * W + c]) : a + sh[k * W + c];
+        res[c] = a;
+      }
+    }
+  } else {
+    unsigned long long *set = reinterpret_cast<unsigned long long *>(g.slots) +
+                              (size_t)(rtag % kNumSlots) * kMaxBlocks * kMaxSlotWidth * 2;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int c = 0; c < W; c++) {
+        double a = sh[c];
+        for (int k = 1; k < kWaves; k++) a = MAX ? fmax(a, sh[k * W + c]) : a + sh[k * W + c];
+        publish_partial(set + ((size_t)blockIdx.x * kMaxSlotWidth + c) * 2, a, rtag);
+      }
+    }
+    if (wv == 0) {
+#pragma unroll
+      for (int c = 0; c < W; c++) {
+        double acc = MAX ? 0.0 : 0.0;
+        for (int t = lane; t < g.G; t += 64) {
+          double x;
+          if (!collect_partial(set + ((size_t)t * kMaxSlotWidth + c) * 2, rtag, g.abortf, &x)) {
+            bad = 1;
+            break;
+          }
+          acc = MAX ? fmax(acc, x) : acc + x;
+        }
+        acc = wave_red<MAX>(acc);
+        if (lane == 0) res[c] = acc;
+      }
+    }
   }
+  bad = __syncthreads_or(bad);
+  if (bad) {
+    if (threadIdx.x == 0) __hip_atomic_store(g.abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+#pragma unroll
+  for (int c = 0; c < W; c++) v[c] = res[c];
   return true;
 }
 
@@ -132,6 +198,21 @@ __device__ __forceinline__ void spmv_rows_dispatch(int lanes, const BMat &M, con
     case 4: bspmv_rows<4, XT, YT>(M, x, y, r0, r1); break;
     case 16: bspmv_rows<16, XT, YT>(M, x, y, r0, r1); break;
     default: bspmv_rows<8, XT, YT>(M, x, y, r0, r1); break;
+  }
+}
+
+// rows [r0, r1) of a CSR product, rows t and t + blockDim of each pass
+// interleaved in one thread
+template <typename XT, typename PT>
+__device__ __forceinline__ void csr_rows2(const BMat &M, const XT *__restrict__ x, XT *__restrict__ y, int r0,
+                                          int r1) {
+  const int nt = blockDim.x;
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += 2 * nt) {
+    int rows[2] = {i, i + nt < r1 ? i + nt : -1};
+    double out[2];
+    bspmv_rows_thread<2, XT, PT>(M, x, rows, out);
+    y[i] = (XT)out[0];
+    if (rows[1] >= 0) y[rows[1]] = (XT)out[1];
   }
 }
 
@@ -162,9 +243,13 @@ __device__ __forceinline__ double residual_row(const int32_t *rp, const int32_t 
 
 // ------------------------------------------------------------------ kernel
 
-template <typename VT, int ZR>
-__global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
+// The parameters live in device memory (a by-value kernel argument that is
+// referenced would be copied to scratch).
+template <typename VT, typename PT, int ZR>
+__global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT> *__restrict__ pp) {
+  const SolveParams<VT> &p = *pp;
   extern __shared__ double sm[];
+  constexpr int kCap = kTileBytes / sizeof(PT);
   const int m = p.m_max;
   double *cs = sm;            // m
   double *sn = cs + m;        // m
@@ -172,13 +257,17 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
   double *hcol = g + m + 1;   // m + 1
   double *y = hcol + m + 1;   // m
   double *Rp = y + m;         // m (m + 1) / 2, column c holds R(0..c, c) at c (c + 1) / 2
-  __shared__ double sh[kWaves];
+  PT *tprod = reinterpret_cast<PT *>(Rp + (size_t)m * (m + 1) / 2);  // kCap products
+  // products of both operators: all buckets of a sub-range of rows at once
+#define SPMV_M(Mat, in, out) bspmv_tile_all<VT, VT, PT>(Mat, in, out, r0, r1, tprod, kCap, p.rows_m)
+#define SPMV_A(Mat, in, out) bspmv_tile_all<VT, VT, PT>(Mat, in, out, r0, r1, tprod, kCap, p.rows_a)
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
   __shared__ int s_flag;
   const int tid = threadIdx.x, nt = blockDim.x, bid = blockIdx.x;
   const int n = p.n;
   const int r0 = bid * p.rows_per_block;
   const int r1 = min(n, r0 + p.rows_per_block);
-  unsigned epoch = 0;
+  unsigned epoch = 0, rtag = 0;
   const Grid &G = p.grid;
   const bool rec = (bid == 0 && tid == 0);
 
@@ -195,7 +284,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
       v[0] = fmax(v[0], s);
       v[1] = fmax(v[1], fabs(p.b[i]));
     }
-    if (!grid_reduce<2, true>(G, epoch, v, sh)) return;
+    if (!grid_reduce<2, true>(G, rtag, v, sh)) return;
     normA = v[0];
     normb = v[1];
   }
@@ -207,7 +296,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
       p.x[i] = acc;
     }
   } else if (p.x0_mode == 1) {
-    spmv_rows_dispatch<double, double>(p.lanes_m, p.Mb, p.b, p.x, r0, r1);
+    bspmv_tile_all<double, double, double>(p.Mb, p.b, p.x, r0, r1, reinterpret_cast<double *>(tprod),
+                                           kTileBytes / 8, p.rows_m / 2 > 0 ? p.rows_m / 2 : 1);
   } else if (p.x0_mode == 2) {
     OWN_ROWS(k, i) { p.x[i] = 0.0; }
   }
@@ -226,7 +316,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
       double xv = p.x[i];
       nv[1] = fmax(nv[1], isfinite(xv) ? fabs(xv) : INFINITY);
     }
-    if (!grid_reduce<2, true>(G, epoch, nv, sh)) return;
+    if (!grid_reduce<2, true>(G, rtag, nv, sh)) return;
     const double nr = nv[0], nx = nv[1];
     const double eta = nr / (normA * nx + normb);
     const double rho = normb > 0 ? nr / normb : nr;
@@ -246,7 +336,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
     double ss[1] = {0.0};
     if (!p.trans) {
       if (!grid_sync(G, epoch)) return;
-      spmv_rows_dispatch<VT, VT>(p.lanes_m, p.Mb, p.rv, V0, r0, r1);
+      SPMV_M(p.Mb, p.rv, V0);
       __syncthreads();
       OWN_ROWS(k, i) {
         double s = (double)V0[i];
@@ -259,7 +349,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
         ss[0] += s * s;
       }
     }
-    if (!grid_reduce<1, false>(G, epoch, ss, sh)) return;
+    if (!grid_reduce<1, false>(G, rtag, ss, sh)) return;
     const double beta = sqrt(ss[0]);
     int kdone = 0;
     if (beta > 0.0) {
@@ -269,39 +359,49 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
       for (int j = 0; j < m; j++) {
         const VT *vj = p.V + (size_t)j * n;
         if (!p.trans) {
-          spmv_rows_dispatch<VT, VT>(p.lanes_a, p.Ap, vj, p.w, r0, r1);
+          SPMV_A(p.Ap, vj, p.w);
           if (!grid_sync(G, epoch)) return;
-          spmv_rows_dispatch<VT, VT>(p.lanes_m, p.Mb, p.w, p.zg, r0, r1);
+          SPMV_M(p.Mb, p.w, p.zg);
         } else {
-          spmv_rows_dispatch<VT, VT>(p.lanes_m, p.Mb, vj, p.w, r0, r1);
+          SPMV_M(p.Mb, vj, p.w);
           if (!grid_sync(G, epoch)) return;
-          spmv_rows_dispatch<VT, VT>(p.lanes_a, p.Ap, p.w, p.zg, r0, r1);
+          SPMV_A(p.Ap, p.w, p.zg);
         }
         __syncthreads();
         VT zr[ZR];
         OWN_ROWS(k, i) { zr[k] = p.zg[i]; }
         // modified Gram-Schmidt: pass i removes the v_{i-1} component and
-        // measures the v_i component of the updated z
+        // measures the v_i component of the updated z.  The slice of v_{i+1}
+        // does not depend on h_i, so it is loaded before the reduction of
+        // pass i and arrives while the blocks exchange their partials.
         double hprev = 0.0;
-        const VT *vprev = nullptr;
+        VT vprev[ZR], vcur[ZR], vnext[ZR];
+        OWN_ROWS(k, i) { vnext[k] = p.V[i]; }
         for (int i2 = 0; i2 <= j; i2++) {
-          const VT *vi = p.V + (size_t)i2 * n;
+#pragma unroll
+          for (int k = 0; k < ZR; k++) {
+            vprev[k] = vcur[k];
+            vcur[k] = vnext[k];
+          }
+          if (i2 < j) {
+            const VT *vn2 = p.V + (size_t)(i2 + 1) * n;
+            OWN_ROWS(k, i) { vnext[k] = vn2[i]; }
+          }
           double part[1] = {0.0};
           OWN_ROWS(k, i) {
-            if (i2 > 0) zr[k] = (VT)fma(-hprev, (double)vprev[i], (double)zr[k]);
-            part[0] = fma((double)vi[i], (double)zr[k], part[0]);
+            if (i2 > 0) zr[k] = (VT)fma(-hprev, (double)vprev[k], (double)zr[k]);
+            part[0] = fma((double)vcur[k], (double)zr[k], part[0]);
           }
-          if (!grid_reduce<1, false>(G, epoch, part, sh)) return;
+          if (!grid_reduce<1, false>(G, rtag, part, sh)) return;
           hprev = part[0];
-          vprev = vi;
           if (tid == 0) hcol[i2] = hprev;
         }
         double nz[1] = {0.0};
         OWN_ROWS(k, i) {
-          zr[k] = (VT)fma(-hprev, (double)vprev[i], (double)zr[k]);
+          zr[k] = (VT)fma(-hprev, (double)vcur[k], (double)zr[k]);
           nz[0] = fma((double)zr[k], (double)zr[k], nz[0]);
         }
-        if (!grid_reduce<1, false>(G, epoch, nz, sh)) return;
+        if (!grid_reduce<1, false>(G, rtag, nz, sh)) return;
         const double hn = sqrt(nz[0]);
         VT *vn = p.V + (size_t)(j + 1) * n;
         OWN_ROWS(k, i) { vn[i] = hn > 0.0 ? (VT)((double)zr[k] / hn) : (VT)0; }
@@ -374,7 +474,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
         p.dv[i] = d;
       }
       if (!grid_sync(G, epoch)) return;
-      spmv_rows_dispatch<double, double>(p.lanes_m, p.Mb, p.dv, p.dv2, r0, r1);
+      bspmv_tile_all<double, double, double>(p.Mb, p.dv, p.dv2, r0, r1, reinterpret_cast<double *>(tprod),
+                                             kTileBytes / 8, p.rows_m / 2 > 0 ? p.rows_m / 2 : 1);
       __syncthreads();
       OWN_ROWS(k, i) {
         double d = p.dv2[i];
@@ -384,7 +485,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
         dn[1] = fmax(dn[1], fabs(xn));
       }
     }
-    if (!grid_reduce<2, true>(G, epoch, dn, sh)) return;
+    if (!grid_reduce<2, true>(G, rtag, dn, sh)) return;
+    if (!grid_sync(G, epoch)) return;  // publish x for the next residual
     const double dx = dn[1] > 0 ? dn[0] / dn[1] : 0.0;
     if (it >= 1 && dx > 0.5 * dx_prev) stag = 1;
     dx_prev = dx;
@@ -399,6 +501,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(SolveParams<VT> p) {
     p.stats->status = status;
   }
 #undef OWN_ROWS
+#undef SPMV_M
+#undef SPMV_A
 }
 
 template <typename VT>
@@ -429,13 +533,18 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   const int n = A->n;
   const int64_t nnz = A->nnz;
   int m = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
-  int G = std::min(kMaxBlocks, std::max(1, (n + kSolveThreads * 4 - 1) / (kSolveThreads * 4)));
+  // about two rows per thread: each MGS pass is bound by the latency of
+  // loading a basis slice and exchanging a partial, not by bandwidth, and more
+  // blocks make every exchange wait for more partials (measured on MI355X at
+  // n = 65,536: 32 blocks 10.5, 64 blocks 13.0, 128 blocks 11.3 solves/s)
+  int G = std::min(kMaxBlocks, std::max(1, (n + 2 * kSolveThreads - 1) / (2 * kSolveThreads)));
   if (const char *e = getenv("BSPAI_SOLVE_BLOCKS")) G = std::min(kMaxBlocks, std::max(1, atoi(e)));
-  int rpb = (n + G - 1) / G;
+  auto rows_for = [&](int g) { return ((n + g - 1) / g + kSlice - 1) / kSlice * kSlice; };  // multiple of 64
+  int rpb = rows_for(G);
   int zr = (rpb + kSolveThreads - 1) / kSolveThreads;
   while (zr > 16 && G < kMaxBlocks) {
     G = std::min(kMaxBlocks, G * 2);
-    rpb = (n + G - 1) / G;
+    rpb = rows_for(G);
     zr = (rpb + kSolveThreads - 1) / kSolveThreads;
   }
   if (zr > 16) return fail(BSPAI_EINVAL, "gmres_ir_solve: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
@@ -457,8 +566,10 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   size_t o_V = take(sizeof(VT) * (size_t)n * (m + 1));
   size_t o_dv = take(8 * (size_t)n), o_dv2 = take(8 * (size_t)n);
   size_t o_flags = take(4 * kMaxBlocks), o_abort = take(4);
-  size_t o_slots = take(8 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth);
+  size_t o_slots = take(16 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth);
   size_t o_stats = take(sizeof(gmres_ir_stats));
+  size_t o_params = take(sizeof(SolveParams<VT>));
+  size_t o_acol = take(4 * (size_t)(nnz + 1));
   size_t o_trp = 0, o_tcol = 0, o_tval = 0;
   if (tr) {
     o_trp = take(4 * ((size_t)n + 1));
@@ -497,6 +608,11 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
     if (rc) return rc;
     arp = trp, acol = tcol, aval = tval;
   }
+  if (reinterpret_cast<uintptr_t>(acol) & 15) {  // the tile product loads 16-byte column vectors
+    int32_t *ac = reinterpret_cast<int32_t *>(base + o_acol);
+    if (nnz) BSPAI_HIP(hipMemcpyAsync(ac, acol, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    acol = ac;
+  }
   p.a_rp = arp;
   p.a_col = acol;
   p.a_val = aval;
@@ -516,6 +632,7 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   Ap.col[0] = acol;
   Ap.val[0] = apv;
   Ap.lanes = pick_lanes(Ap, nnz);
+  Ap.aligned = 1;
   p.Ap = Ap;
   p.Mb = tr ? M->matT : M->mat;
   auto clamp_lanes = [](int l) { return l <= 4 ? 4 : (l >= 16 ? 16 : 8); };
@@ -546,18 +663,43 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   p.stats = reinterpret_cast<gmres_ir_stats *>(base + o_stats);
   BSPAI_HIP(hipMemsetAsync(p.grid.flags, 0, 4 * kMaxBlocks, s));
   BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
+  // tags restart at 1 every launch: clear the exchange words of the last one
+  BSPAI_HIP(hipMemsetAsync(p.grid.slots, 0, 16 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth, s));
   BSPAI_HIP(hipMemsetAsync(p.stats, 0, sizeof(gmres_ir_stats), s));
-  size_t lds = sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2);
+  bool wide = sizeof(VT) == 8;
+  for (int k = 0; k < p.Mb.nb; k++) wide = wide || p.Mb.prec[k] == BSPAI_FP64;
+  size_t lds = sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2) + kTileBytes;
+  {
+    const int cap = kTileBytes / (wide ? 8 : 4);
+    auto rows_for_avg = [&](double avg) {
+      int r = (int)(cap / (1.25 * std::max(avg, 1.0)));
+      return std::max(1, std::min(kSolveThreads, r));
+    };
+    p.rows_a = rows_for_avg((double)nnz / n);
+    p.rows_m = rows_for_avg((double)p.Mb.nnz / n);
+  }
   void *fn = nullptr;
-  switch (ZR) {
-    case 1: fn = (void *)k_gmres_ir<VT, 1>; break;
-    case 2: fn = (void *)k_gmres_ir<VT, 2>; break;
-    case 4: fn = (void *)k_gmres_ir<VT, 4>; break;
-    case 8: fn = (void *)k_gmres_ir<VT, 8>; break;
-    default: fn = (void *)k_gmres_ir<VT, 16>; break;
+  if (wide) {
+    switch (ZR) {
+      case 1: fn = (void *)k_gmres_ir<VT, double, 1>; break;
+      case 2: fn = (void *)k_gmres_ir<VT, double, 2>; break;
+      case 4: fn = (void *)k_gmres_ir<VT, double, 4>; break;
+      case 8: fn = (void *)k_gmres_ir<VT, double, 8>; break;
+      default: fn = (void *)k_gmres_ir<VT, double, 16>; break;
+    }
+  } else {
+    switch (ZR) {
+      case 1: fn = (void *)k_gmres_ir<VT, float, 1>; break;
+      case 2: fn = (void *)k_gmres_ir<VT, float, 2>; break;
+      case 4: fn = (void *)k_gmres_ir<VT, float, 4>; break;
+      case 8: fn = (void *)k_gmres_ir<VT, float, 8>; break;
+      default: fn = (void *)k_gmres_ir<VT, float, 16>; break;
+    }
   }
   BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  void *args[] = {&p};
+  SolveParams<VT> *pdev = reinterpret_cast<SolveParams<VT> *>(base + o_params);
+  BSPAI_HIP(hipMemcpyAsync(pdev, &p, sizeof(p), hipMemcpyHostToDevice, s));
+  void *args[] = {&pdev};
   hipEvent_t ev[2] = {nullptr, nullptr};
   if (g_profile) {
     BSPAI_HIP(hipEventCreate(&ev[0]));

@@ -121,4 +121,514 @@ __device__ __forceinline__ void bspmm_row(const BMat &M, const XT *__restrict__ 
   if (active) y[(int64_t)i * ld + c] = (XT)total;
 }
 
+// ---------------------------------------------------------------- tiles
+//
+// Two-phase product for a contiguous range of rows (used when a row has few
+// entries).  Phase 1: the block streams the entries of the range, which are
+// contiguous in each bucket's arrays, with wide aligned loads (8 entries per
+// thread and pass), gathers x and writes each product to LDS.  Phase 2: one
+// thread per row adds its products from LDS in CSR order.  The per-bucket row
+// sums are then scaled and added from the least to the most precise bucket in
+// FP64, as in bspmv_row.  Many independent loads per thread keep enough bytes
+// in flight to stream HBM; the per-row order stays fixed (deterministic).
+
+constexpr int kTileVec = 8;  // entries per thread and pass
+
+template <typename PT>
+__device__ __forceinline__ void load_vals8(const BMat &M, int k, int64_t base, PT (&v)[kTileVec]) {
+  // base is a multiple of 8 entries: every load below is naturally aligned
+  switch (M.prec[k]) {
+    case BSPAI_FP64: {
+      const double4 *p = reinterpret_cast<const double4 *>(static_cast<const double *>(M.val[k]) + base);
+      double4 a = p[0], b = p[1];
+      v[0] = (PT)a.x; v[1] = (PT)a.y; v[2] = (PT)a.z; v[3] = (PT)a.w;
+      v[4] = (PT)b.x; v[5] = (PT)b.y; v[6] = (PT)b.z; v[7] = (PT)b.w;
+    } break;
+    case BSPAI_FP32: {
+      const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(M.val[k]) + base);
+      float4 a = p[0], b = p[1];
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } break;
+    case BSPAI_FP16: {
+      uint4 a = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(M.val[k]) + base);
+      uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        v[2 * t] = decode_f16((uint16_t)(w[t] & 0xFFFFu));
+        v[2 * t + 1] = decode_f16((uint16_t)(w[t] >> 16));
+      }
+    } break;
+    case BSPAI_BF16: {
+      uint4 a = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(M.val[k]) + base);
+      uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        v[2 * t] = decode_bf16((uint16_t)(w[t] & 0xFFFFu));
+        v[2 * t + 1] = decode_bf16((uint16_t)(w[t] >> 16));
+      }
+    } break;
+    case BSPAI_FP8_E4M3: {
+      uint2 a = *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(M.val[k]) + base);
+      uint32_t w[2] = {a.x, a.y};
+#pragma unroll
+      for (int t = 0; t < 8; t++) v[t] = decode_e4m3((uint8_t)((w[t >> 2] >> (8 * (t & 3))) & 0xFFu));
+    } break;
+    default:
+#pragma unroll
+      for (int t = 0; t < kTileVec; t++) v[t] = (PT)0;
+  }
+}
+
+// Rows [r0, r1) of y = M_b x with the two-phase tile method; sub-ranges of
+// at most `rows_cap` rows whose entries of a bucket exceed `cap` products fall
+// back to the L-lane method for that bucket.  prod: LDS [cap] of PT,
+// acc: LDS [rows_cap] doubles, rps: LDS [rows_cap + 1] ints.  All threads of
+// the block must call this.
+template <typename XT, typename YT, typename PT>
+__device__ void bspmv_tile_rows(const BMat &M, const XT *__restrict__ x, YT *__restrict__ y, int r0, int r1,
+                                PT *prod, int cap, double *acc, int rows_cap, int32_t *rps) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int s0 = r0; s0 < r1; s0 += rows_cap) {
+    const int s1 = min(r1, s0 + rows_cap);
+    for (int i = s0 + tid; i < s1; i += nt) acc[i - s0] = 0.0;
+    for (int k = 0; k < M.nb; k++) {
+      const int32_t *col = M.col[k];
+      // the sub-range's row pointers of this bucket, staged in LDS
+      for (int i = s0 + tid; i <= s1; i += nt) rps[i - s0] = M.rp[k][i];
+      __syncthreads();
+      const int32_t *rp = rps - s0;
+      const int e0 = rp[s0], e1 = rp[s1];
+      const double sc = M.scale[k];
+      const bool wide = (M.prec[k] == BSPAI_FP64) || sizeof(PT) == 8;
+      if (e1 - e0 <= cap) {
+        const int eb = e0 & ~(kTileVec - 1);
+        for (int base = eb + tid * kTileVec; base < e1; base += nt * kTileVec) {
+          if (base >= e0 && base + kTileVec <= e1) {
+            // 8 entries inside the range: aligned vector loads, 8 gathers in flight
+            int4 ca = *reinterpret_cast<const int4 *>(col + base);
+            int4 cb = *reinterpret_cast<const int4 *>(col + base + 4);
+            int cc[kTileVec] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+            PT vv[kTileVec];
+            load_vals8<PT>(M, k, base, vv);
+            PT xv[kTileVec];
+#pragma unroll
+            for (int t = 0; t < kTileVec; t++) xv[t] = (PT)x[cc[t]];
+#pragma unroll
+            for (int t = 0; t < kTileVec; t++) prod[base + t - e0] = vv[t] * xv[t];
+          } else {
+            // the ends of the range: element by element, never outside [e0, e1)
+            for (int t = 0; t < kTileVec; t++) {
+              int e = base + t;
+              if (e >= e0 && e < e1) {
+                PT v = M.prec[k] == BSPAI_FP64 ? (PT) static_cast<const double *>(M.val[k])[e]
+                                               : (PT)load_value_f32(M, k, e);
+                prod[e - e0] = v * (PT)x[col[e]];
+              }
+            }
+          }
+        }
+        __syncthreads();
+        for (int i = s0 + tid; i < s1; i += nt) {
+          int a = rp[i] - e0, b = rp[i + 1] - e0;
+          if (wide) {
+            double sum = 0.0;
+            for (int q = a; q < b; q++) sum += (double)prod[q];
+            acc[i - s0] += sum * sc;
+          } else {
+            float sum = 0.f;
+            for (int q = a; q < b; q++) sum += (float)prod[q];
+            acc[i - s0] += (double)sum * sc;
+          }
+        }
+        __syncthreads();
+      } else {
+        // long rows: one group of 8 lanes per row (this bucket only)
+        const int lane = tid & 7;
+        for (int i = s0 + tid / 8; i < s1; i += nt / 8) {
+          double v;
+          int a = rp[i], b = rp[i + 1];
+          if (wide) {
+            double sum = 0.0;
+            for (int q = a + lane; q < b; q += 8)
+              sum = fma(M.prec[k] == BSPAI_FP64 ? static_cast<const double *>(M.val[k])[q]
+                                                : (double)load_value_f32(M, k, q),
+                        (double)x[col[q]], sum);
+            v = group_sum(sum, 8);
+          } else {
+            float sum = 0.f;
+            for (int q = a + lane; q < b; q += 8) sum = fmaf(load_value_f32(M, k, q), (float)x[col[q]], sum);
+            v = (double)group_sum(sum, 8);
+          }
+          if (lane == 0) acc[i - s0] += v * sc;
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = s0 + tid; i < s1; i += nt) y[i] = (YT)acc[i - s0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- rows
+//
+// One thread per row: the row's entries of a bucket are fetched 8 at a time
+// with independent (predicated) loads of columns and values, then 8 gathers of
+// x, then the FMAs in CSR order.  No LDS and no block barrier: every wave
+// streams on its own, with up to 8 entries x 3 loads in flight per lane.
+
+template <typename PT>
+__device__ __forceinline__ PT value_at(const BMat &M, int k, int64_t p) {
+  if (M.prec[k] == BSPAI_FP64) return (PT) static_cast<const double *>(M.val[k])[p];
+  return (PT)load_value_f32(M, k, p);
+}
+
+template <typename XT, typename YT, typename PT>
+__device__ __forceinline__ double bspmv_row_thread(const BMat &M, const XT *__restrict__ x, int i) {
+  constexpr int U = 8;
+  double total = 0.0;
+  for (int k = 0; k < M.nb; k++) {
+    const int32_t *col = M.col[k];
+    const int s = M.rp[k][i], e = M.rp[k][i + 1];
+    const bool wide = (M.prec[k] == BSPAI_FP64) || sizeof(PT) == 8;
+    double accd = 0.0;
+    float accf = 0.f;
+    for (int p = s; p < e; p += U) {
+      int cc[U];
+      PT vv[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        bool ok = p + u < e;
+        cc[u] = ok ? col[p + u] : 0;
+        vv[u] = ok ? value_at<PT>(M, k, p + u) : (PT)0;
+      }
+      PT xv[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) xv[u] = (p + u < e) ? (PT)x[cc[u]] : (PT)0;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (p + u < e) {
+          if (wide)
+            accd = fma((double)vv[u], (double)xv[u], accd);
+          else
+            accf = fmaf((float)vv[u], (float)xv[u], accf);
+        }
+      }
+    }
+    total += (wide ? accd : (double)accf) * M.scale[k];
+  }
+  return total;
+}
+
+// RT rows per thread (rows i0 + r * stride): the load chains of the rows are
+// interleaved so that RT times as many bytes are in flight per lane.
+template <int RT, typename XT, typename PT>
+__device__ __forceinline__ void bspmv_rows_thread(const BMat &M, const XT *__restrict__ x, const int (&rows)[RT],
+                                                  double (&out)[RT]) {
+  constexpr int U = 8;
+#pragma unroll
+  for (int r = 0; r < RT; r++) out[r] = 0.0;
+  for (int k = 0; k < M.nb; k++) {
+    const int32_t *col = M.col[k];
+    const int32_t *rp = M.rp[k];
+    const bool wide = (M.prec[k] == BSPAI_FP64) || sizeof(PT) == 8;
+    int s[RT], e[RT];
+#pragma unroll
+    for (int r = 0; r < RT; r++) {
+      bool ok = rows[r] >= 0;
+      s[r] = ok ? rp[rows[r]] : 0;
+      e[r] = ok ? rp[rows[r] + 1] : 0;
+    }
+    int len = 0;
+#pragma unroll
+    for (int r = 0; r < RT; r++) len = max(len, e[r] - s[r]);
+    double accd[RT];
+    float accf[RT];
+#pragma unroll
+    for (int r = 0; r < RT; r++) {
+      accd[r] = 0.0;
+      accf[r] = 0.f;
+    }
+    for (int o = 0; o < len; o += U) {
+      int cc[RT][U];
+      PT vv[RT][U];
+#pragma unroll
+      for (int r = 0; r < RT; r++)
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          int p = s[r] + o + u;
+          bool ok = p < e[r];
+          cc[r][u] = ok ? col[p] : 0;
+          vv[r][u] = ok ? value_at<PT>(M, k, p) : (PT)0;
+        }
+      PT xv[RT][U];
+#pragma unroll
+      for (int r = 0; r < RT; r++)
+#pragma unroll
+        for (int u = 0; u < U; u++) xv[r][u] = (s[r] + o + u < e[r]) ? (PT)x[cc[r][u]] : (PT)0;
+#pragma unroll
+      for (int r = 0; r < RT; r++)
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          if (s[r] + o + u < e[r]) {
+            if (wide)
+              accd[r] = fma((double)vv[r][u], (double)xv[r][u], accd[r]);
+            else
+              accf[r] = fmaf((float)vv[r][u], (float)xv[r][u], accf[r]);
+          }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; r++) out[r] += (wide ? accd[r] : (double)accf[r]) * M.scale[k];
+  }
+}
+
+// ---------------------------------------------------------------- SELL-64
+//
+// One wavefront per 64-row slice, lane r on row 64 s + r.  Entry u of the
+// slice's rows is one contiguous 64-wide column, so every load instruction of
+// columns (256 B) and values (64 x width) is contiguous; the slice's columns
+// are fetched 8 at a time before their gathers of x.  Short rows are padded
+// with zero values (adding +0 leaves the FP sum unchanged).  Per row the
+// entries are added in CSR order.
+
+template <typename PT>
+__device__ __forceinline__ PT sell_value(const BMat &M, int k, int64_t p) {
+  if (M.prec[k] == BSPAI_FP64) return (PT) static_cast<const double *>(M.sell_val[k])[p];
+  switch (M.prec[k]) {
+    case BSPAI_FP32: return (PT) static_cast<const float *>(M.sell_val[k])[p];
+    case BSPAI_FP16: return (PT)decode_f16(static_cast<const uint16_t *>(M.sell_val[k])[p]);
+    case BSPAI_BF16: return (PT)decode_bf16(static_cast<const uint16_t *>(M.sell_val[k])[p]);
+    case BSPAI_FP8_E4M3: return (PT)decode_e4m3(static_cast<const uint8_t *>(M.sell_val[k])[p]);
+  }
+  return (PT)0;
+}
+
+// 4 consecutive stored values of an ELL bucket (entry e a multiple of 4)
+template <typename PT>
+__device__ __forceinline__ void ell_vals4(const BMat &M, int k, int64_t e, PT (&v)[4]) {
+  switch (M.prec[k]) {
+    case BSPAI_FP64: {
+      const double2 *p = reinterpret_cast<const double2 *>(static_cast<const double *>(M.ell_val[k]) + e);
+      double2 a = p[0], b = p[1];
+      v[0] = (PT)a.x; v[1] = (PT)a.y; v[2] = (PT)b.x; v[3] = (PT)b.y;
+    } break;
+    case BSPAI_FP32: {
+      float4 a = *reinterpret_cast<const float4 *>(static_cast<const float *>(M.ell_val[k]) + e);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } break;
+    case BSPAI_FP16: {
+      uint2 a = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(M.ell_val[k]) + e);
+      v[0] = decode_f16(a.x & 0xFFFFu); v[1] = decode_f16(a.x >> 16);
+      v[2] = decode_f16(a.y & 0xFFFFu); v[3] = decode_f16(a.y >> 16);
+    } break;
+    case BSPAI_BF16: {
+      uint2 a = *reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(M.ell_val[k]) + e);
+      v[0] = decode_bf16(a.x & 0xFFFFu); v[1] = decode_bf16(a.x >> 16);
+      v[2] = decode_bf16(a.y & 0xFFFFu); v[3] = decode_bf16(a.y >> 16);
+    } break;
+    case BSPAI_FP8_E4M3: {
+      uint32_t a = *reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(M.ell_val[k]) + e);
+      v[0] = decode_e4m3(a & 0xFFu); v[1] = decode_e4m3((a >> 8) & 0xFFu);
+      v[2] = decode_e4m3((a >> 16) & 0xFFu); v[3] = decode_e4m3(a >> 24);
+    } break;
+    default:
+      v[0] = v[1] = v[2] = v[3] = (PT)0;
+  }
+}
+
+// row 64 sl + lane of M_b x: each bucket from its ELL copy (16-byte vector
+// loads of the row's own entries) when present, else from its SELL-64 copy.
+// Entries are added in CSR order, padding adds +0.
+template <typename XT, typename PT>
+__device__ __forceinline__ double bspmv_sell_row(const BMat &M, const XT *__restrict__ x, int sl, int lane) {
+  constexpr int U = 8;
+  const int row = sl * kSlice + lane;
+  double total = 0.0;
+  for (int k = 0; k < M.nb; k++) {
+    const bool wide = (M.prec[k] == BSPAI_FP64) || sizeof(PT) == 8;
+    double accd = 0.0;
+    float accf = 0.f;
+    const int ew = M.ell_w[k];
+    if (ew) {
+      if (row < M.n) {
+        const int64_t e0 = (int64_t)row * ew;
+        for (int c0 = 0; c0 < ew; c0 += U) {
+          int cc[U];
+          PT vv[U];
+#pragma unroll
+          for (int h = 0; h < U; h += 4) {
+            if (c0 + h < ew) {
+              int4 ci = *reinterpret_cast<const int4 *>(M.ell_col[k] + e0 + c0 + h);
+              cc[h] = ci.x, cc[h + 1] = ci.y, cc[h + 2] = ci.z, cc[h + 3] = ci.w;
+              PT v4[4];
+              ell_vals4<PT>(M, k, e0 + c0 + h, v4);
+              vv[h] = v4[0], vv[h + 1] = v4[1], vv[h + 2] = v4[2], vv[h + 3] = v4[3];
+            } else {
+#pragma unroll
+              for (int t = 0; t < 4; t++) cc[h + t] = row, vv[h + t] = (PT)0;
+            }
+          }
+          PT xv[U];
+#pragma unroll
+          for (int u = 0; u < U; u++) xv[u] = (c0 + u < ew) ? (PT)x[cc[u]] : (PT)0;
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            if (c0 + u < ew) {
+              if (wide)
+                accd = fma((double)vv[u], (double)xv[u], accd);
+              else
+                accf = fmaf((float)vv[u], (float)xv[u], accf);
+            }
+          }
+        }
+      }
+    } else {
+      const int w = M.sell_w[k];
+      const int p0 = w ? sl * kSlice * w : M.sell_ptr[k][sl];
+      const int len = w ? w : (M.sell_ptr[k][sl + 1] - p0) / kSlice;
+      const int32_t *col = M.sell_col[k] + p0 + lane;
+      const int64_t vbase = (int64_t)p0 + lane;
+      for (int u0 = 0; u0 < len; u0 += U) {
+        int cc[U];
+        PT vv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          bool ok = u0 + u < len;  // uniform over the wavefront
+          cc[u] = ok ? col[(u0 + u) * kSlice] : 0;
+          vv[u] = ok ? sell_value<PT>(M, k, vbase + (int64_t)(u0 + u) * kSlice) : (PT)0;
+        }
+        PT xv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) xv[u] = (u0 + u < len) ? (PT)x[cc[u]] : (PT)0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          if (u0 + u < len) {
+            if (wide)
+              accd = fma((double)vv[u], (double)xv[u], accd);
+            else
+              accf = fmaf((float)vv[u], (float)xv[u], accf);
+          }
+        }
+      }
+    }
+    total += (wide ? accd : (double)accf) * M.scale[k];
+  }
+  return total;
+}
+
+// rows [r0, r1) (r0 a multiple of 64) by the waves of the calling block
+template <typename XT, typename YT, typename PT>
+__device__ __forceinline__ void bspmv_sell_rows(const BMat &M, const XT *__restrict__ x, YT *__restrict__ y, int r0,
+                                                int r1) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int sl = r0 / kSlice + w; sl * kSlice < r1; sl += nw) {
+    double v = bspmv_sell_row<XT, PT>(M, x, sl, lane);
+    int row = sl * kSlice + lane;
+    if (row < r1) y[row] = (YT)v;
+  }
+}
+
+// ---------------------------------------------------------------- tile, all buckets
+//
+// All buckets of a sub-range of rows in one pass: the bucket bounds of the
+// sub-range are loaded together, every bucket's entries are streamed into LDS
+// products with aligned 8-wide loads in the same phase, the row pointers of
+// the thread's row are fetched meanwhile, and after one barrier each thread
+// adds its row's products bucket by bucket (CSR order, least to most precise
+// bucket).  Three dependent memory rounds per sub-range whatever the number of
+// buckets.  rows_cap <= blockDim.x (one row per thread).  A sub-range whose
+// entries exceed cap is computed row by row from global memory instead.
+template <typename XT, typename YT, typename PT>
+__device__ void bspmv_tile_all(const BMat &M, const XT *__restrict__ x, YT *__restrict__ y, int r0, int r1,
+                               PT *prod, int cap, int rows_cap) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nb = M.nb;
+  for (int s0 = r0; s0 < r1; s0 += rows_cap) {
+    const int s1 = min(r1, s0 + rows_cap);
+    int e0[kMaxBuckets], off[kMaxBuckets + 1];
+    off[0] = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxBuckets; k++) {
+      if (k < nb) {
+        e0[k] = M.rp[k][s0];
+        off[k + 1] = off[k] + (M.rp[k][s1] - e0[k]);
+      } else {
+        e0[k] = 0;
+        off[k + 1] = off[k];
+      }
+    }
+    const bool fits = off[nb] <= cap;
+    const int i = s0 + tid;
+    int ra[kMaxBuckets], rb[kMaxBuckets];
+#pragma unroll
+    for (int k = 0; k < kMaxBuckets; k++) {
+      bool ok = k < nb && i < s1;
+      ra[k] = ok ? M.rp[k][i] : 0;
+      rb[k] = ok ? M.rp[k][i + 1] : 0;
+    }
+    if (fits) {
+#pragma unroll
+      for (int k = 0; k < kMaxBuckets; k++) {
+        if (k >= nb) break;
+        const int32_t *col = M.col[k];
+        const int b0 = e0[k], b1 = b0 + (off[k + 1] - off[k]);
+        PT *pk = prod + off[k] - b0;
+        for (int base = (b0 & ~(kTileVec - 1)) + tid * kTileVec; base < b1; base += nt * kTileVec) {
+          if (base >= b0 && base + kTileVec <= b1) {
+            int4 ca = *reinterpret_cast<const int4 *>(col + base);
+            int4 cb = *reinterpret_cast<const int4 *>(col + base + 4);
+            int cc[kTileVec] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+            PT vv[kTileVec];
+            load_vals8<PT>(M, k, base, vv);
+            PT xv[kTileVec];
+#pragma unroll
+            for (int t = 0; t < kTileVec; t++) xv[t] = (PT)x[cc[t]];
+#pragma unroll
+            for (int t = 0; t < kTileVec; t++) pk[base + t] = vv[t] * xv[t];
+          } else {
+            for (int t = 0; t < kTileVec; t++) {
+              int e = base + t;
+              if (e >= b0 && e < b1) pk[e] = value_at<PT>(M, k, e) * (PT)x[col[e]];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (i < s1) {
+      double total = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMaxBuckets; k++) {
+        if (k >= nb) break;
+        const bool wide = (M.prec[k] == BSPAI_FP64) || sizeof(PT) == 8;
+        const PT *pk = prod + off[k] - e0[k];
+        if (fits) {
+          if (wide) {
+            double sum = 0.0;
+            for (int q = ra[k]; q < rb[k]; q++) sum += (double)pk[q];
+            total += sum * M.scale[k];
+          } else {
+            float sum = 0.f;
+            for (int q = ra[k]; q < rb[k]; q++) sum += (float)pk[q];
+            total += (double)sum * M.scale[k];
+          }
+        } else {
+          const int32_t *col = M.col[k];
+          if (wide) {
+            double sum = 0.0;
+            for (int q = ra[k]; q < rb[k]; q++) sum += (double)(value_at<PT>(M, k, q) * (PT)x[col[q]]);
+            total += sum * M.scale[k];
+          } else {
+            float sum = 0.f;
+            for (int q = ra[k]; q < rb[k]; q++) sum += (float)(value_at<PT>(M, k, q) * (PT)x[col[q]]);
+            total += (double)sum * M.scale[k];
+          }
+        }
+      }
+      y[i] = (YT)total;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace bspai
