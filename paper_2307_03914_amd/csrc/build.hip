@@ -34,15 +34,32 @@ __device__ __forceinline__ int lower_bound_i(const int32_t *a, int len, int key)
   return lo;
 }
 
-// per row k of the pattern: |J_k| and the number of candidate shadow indices
-__global__ void k_spai_sizes(int n, const int32_t *arp, const int32_t *prp, const int32_t *pcol, int32_t *out_max) {
+// Limits of the one-wavefront path (least-squares tile in LDS).
+constexpr int kSmallJ = 64;
+constexpr int kSmallCand = 1024;
+constexpr int kSmallTile = 8192;  // doubles
+
+// per row k of the pattern: |J_k| and the number of candidate shadow indices;
+// rows beyond the wavefront path's limits are appended to the block path list
+__global__ void k_spai_sizes(int n, const int32_t *arp, const int32_t *prp, const int32_t *pcol, int32_t *out_max,
+                             int8_t *is_big, int32_t *big_list, int32_t *big_count, int32_t *cand_of) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   int s = prp[k], e = prp[k + 1];
   int cand = 0;
   for (int p = s; p < e; p++) cand += arp[pcol[p] + 1] - arp[pcol[p]];
-  atomicMax(&out_max[0], e - s);
-  atomicMax(&out_max[1], cand);
+  int nJ = e - s;
+  cand_of[k] = cand;
+  bool big = nJ > kSmallJ || cand > kSmallCand || (int64_t)cand * nJ > kSmallTile;
+  is_big[k] = big ? 1 : 0;
+  if (big) {
+    big_list[atomicAdd(big_count, 1)] = k;
+    atomicMax(&out_max[2], nJ);
+    atomicMax(&out_max[3], cand);
+  } else {
+    atomicMax(&out_max[0], nJ);
+    atomicMax(&out_max[1], cand);
+  }
 }
 
 // d_j = 1 / max_l |a_jl|: scales column j of A^T to unit max (Section 4)
@@ -64,6 +81,7 @@ struct SpaiArgs {
   int cand_p2;  // capacity of the index lists (power of two)
   int tile_cap; // capacity of the dense tile in doubles
   int32_t *err; // [0] first zero row, [1] first rank-deficient row, [2] first oversized row
+  const int8_t *is_big;  // rows left to the block path
 };
 
 // One wavefront per row k of M:
@@ -74,6 +92,7 @@ __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
   extern __shared__ double lds_d[];
   const int k = blockIdx.x;
   const int lane = threadIdx.x;
+  if (a.is_big[k]) return;
   const int ps = a.prp[k], nJ = a.prp[k + 1] - ps;
   int32_t *cand = reinterpret_cast<int32_t *>(lds_d);  // cand_p2
   int32_t *I = cand + a.cand_p2;                        // cand_p2
@@ -202,6 +221,210 @@ __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
   for (int c = lane; c < nJ; c += 64) {
     double dj = a.dscale ? a.dscale[a.pcol[ps + c]] : 1.0;
     a.mval[ps + c] = mv[c] * dj;
+  }
+}
+
+
+// ------------------------------------------------------------------ block path
+//
+// One block per row k whose least-squares tile is too large for a wavefront.
+// The candidate shadow indices are sorted in LDS; a shadow row l with a single
+// nonzero (in column c) only enters the objective as (a_l m_c - e_l)^2, so all
+// such rows of column c are replaced by one row with entry ||a||_2 and right
+// side (sum_l a_l e_l) / ||a||_2 (an orthogonal reduction; the least-squares
+// solution is unchanged).  Rows with several nonzeros are kept.  The reduced
+// tile (multi rows, then one folded row per column) is factored by Householder
+// QR in global memory, columns spread over the waves.
+
+constexpr int kBigThreads = 256;
+constexpr int kBigCand = 16384;  // LDS capacity for the sorted candidates
+
+struct SpaiBigArgs {
+  const int32_t *arp, *acol;
+  const double *aval;
+  const int32_t *prp, *pcol;
+  const double *dscale;
+  double *mval;
+  const int32_t *rows;       // rows of this batch
+  const int64_t *tile_off;   // per row: offset of its tile in tiles (doubles)
+  const int64_t *rhs_off;    // per row: offset of its right side in rhs (doubles)
+  double *tiles, *rhs;
+  int32_t *err;
+};
+
+__device__ __forceinline__ double block_sum_big(double v, double *sh) {
+  v = wave_sum_d(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kBigThreads / 64; w++) t += sh[w];
+  return t;
+}
+
+__global__ void __launch_bounds__(kBigThreads) k_spai_big(SpaiBigArgs a) {
+  extern __shared__ double lds_b[];
+  int32_t *S = reinterpret_cast<int32_t *>(lds_b);  // kBigCand sorted candidates
+  int32_t *code = S + kBigCand;                       // per sorted position: multi row index, -1 single
+  double *diagR = lds_b + kBigCand;                   // after the two int arrays (8 * kBigCand bytes)
+  double *yv = diagR + 1024;
+  __shared__ double sh[kBigThreads / 64];
+  __shared__ int s_nc, s_nmulti, s_flag;
+  const int tid = threadIdx.x;
+  const int k = a.rows[blockIdx.x];
+  const int ps = a.prp[k], nJ = a.prp[k + 1] - ps;
+  const int *J = a.pcol + ps;
+  for (int c = tid; c < nJ; c += kBigThreads) a.mval[ps + c] = 0.0;
+  if (tid == 0) {
+    // candidate count (all entries of the rows J; zeros are marked below)
+    int nc = 0;
+    for (int c = 0; c < nJ; c++) nc += a.arp[J[c] + 1] - a.arp[J[c]];
+    s_nc = nc;
+  }
+  __syncthreads();
+  const int nc = s_nc;
+  if (nc > kBigCand || nJ > 1024) {
+    if (tid == 0) atomicMin(&a.err[2], k);
+    return;
+  }
+  // gather: segment offsets by one thread, then one thread per column copies
+  // its row's column indices (explicit zeros become INT_MAX, sorted last)
+  if (tid == 0) {
+    int off = 0;
+    for (int c = 0; c < nJ; c++) {
+      code[c] = off;
+      off += a.arp[J[c] + 1] - a.arp[J[c]];
+    }
+  }
+  __syncthreads();
+  for (int c = tid; c < nJ; c += kBigThreads) {
+    int j = J[c], off = code[c];
+    for (int p = a.arp[j]; p < a.arp[j + 1]; p++) S[off++] = a.aval[p] != 0.0 ? a.acol[p] : INT_MAX;
+  }
+  int P2 = 1;
+  while (P2 < nc) P2 <<= 1;
+  __syncthreads();
+  for (int p = nc + tid; p < P2; p += kBigThreads) S[p] = INT_MAX;
+  __syncthreads();
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < P2 / 2; t += kBigThreads) {
+        int lo = 2 * stride * (t / stride) + (t % stride);
+        int hi = lo + stride;
+        bool up = ((lo & size) == 0);
+        int x = S[lo], y = S[hi];
+        if ((x > y) == up) {
+          S[lo] = y;
+          S[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // runs of equal indices: multi rows get consecutive indices in sorted order
+  if (tid == 0) {
+    int nm = 0, found_k = 0;
+    for (int p = 0; p < nc && S[p] != INT_MAX;) {
+      int q = p + 1;
+      while (q < nc && S[q] == S[p]) q++;
+      int c = (q - p >= 2) ? nm++ : -1;
+      for (int t = p; t < q; t++) code[t] = c;
+      if (S[p] == k) found_k = 1;
+      p = q;
+    }
+    s_nmulti = nm;
+    s_flag = found_k;
+  }
+  __syncthreads();
+  if (!s_flag) {
+    if (tid == 0) atomicMin(&a.err[0], k);
+    return;
+  }
+  const int nm = s_nmulti;
+  const int T = nm + nJ;  // tile rows: multi rows, then one folded row per column
+  double *tile = a.tiles + a.tile_off[blockIdx.x];
+  double *rhs = a.rhs + a.rhs_off[blockIdx.x];
+  for (int64_t p = tid; p < (int64_t)T * nJ; p += kBigThreads) tile[p] = 0.0;
+  for (int p = tid; p < T; p += kBigThreads) rhs[p] = 0.0;
+  __syncthreads();
+  // scatter the entries: thread per column, entries in row order (deterministic)
+  int valid = nc;
+  while (valid > 0 && S[valid - 1] == INT_MAX) valid--;
+  for (int c = tid; c < nJ; c += kBigThreads) {
+    int j = J[c];
+    double dj = a.dscale ? a.dscale[j] : 1.0;
+    double f2 = 0.0, fk = 0.0;
+    for (int p = a.arp[j]; p < a.arp[j + 1]; p++) {
+      double v = a.aval[p];
+      if (v == 0.0) continue;
+      v *= dj;
+      int i = a.acol[p];
+      int lo = lower_bound_i(S, valid, i);
+      int cd = code[lo];
+      if (cd >= 0) {
+        tile[cd + (int64_t)c * T] = v;
+        if (i == k) rhs[cd] = 1.0;
+      } else {
+        f2 += v * v;
+        if (i == k) fk = v;
+      }
+    }
+    if (f2 > 0.0) {
+      double nrm = sqrt(f2);
+      tile[nm + c + (int64_t)c * T] = nrm;
+      rhs[nm + c] = fk / nrm;
+    }
+  }
+  __syncthreads();
+  // Frobenius norm for the rank test
+  double fl = 0.0;
+  for (int64_t p = tid; p < (int64_t)T * nJ; p += kBigThreads) fl += tile[p] * tile[p];
+  const double fro = sqrt(block_sum_big(fl, sh));
+  const int lane = tid & 63, w = tid >> 6;
+  for (int c = 0; c < nJ; c++) {
+    double *col = tile + (int64_t)c * T;
+    double s2 = 0.0;
+    for (int l = c + tid; l < T; l += kBigThreads) s2 += col[l] * col[l];
+    double nrm = sqrt(block_sum_big(s2, sh));
+    double alpha = col[c];
+    double beta = -copysign(nrm, alpha);
+    if (nrm == 0.0 || fabs(beta) <= (double)nJ * 0x1p-53 * fro) {
+      if (tid == 0) atomicMin(&a.err[1], k);
+      return;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      col[c] = alpha - beta;
+      diagR[c] = beta;
+    }
+    __syncthreads();
+    double vt = 0.0;
+    for (int l = c + tid; l < T; l += kBigThreads) vt += col[l] * col[l];
+    const double vtv = block_sum_big(vt, sh);
+    // trailing columns and the right side: one wave per column
+    for (int jj = c + 1 + w; jj <= nJ; jj += kBigThreads / 64) {
+      double *cj = (jj < nJ) ? tile + (int64_t)jj * T : rhs;
+      double d = 0.0;
+      for (int l = c + lane; l < T; l += 64) d += col[l] * cj[l];
+      double f = 2.0 * wave_sum_d(d) / vtv;
+      for (int l = c + lane; l < T; l += 64) cj[l] -= f * col[l];
+    }
+    __syncthreads();
+  }
+  // back substitution, column by column
+  for (int c = tid; c < nJ; c += kBigThreads) yv[c] = rhs[c];
+  __syncthreads();
+  for (int c = nJ - 1; c >= 0; c--) {
+    double yc = yv[c] / diagR[c];
+    __syncthreads();
+    if (tid == 0) yv[c] = yc;
+    const double *Rc = tile + (int64_t)c * T;
+    for (int i = tid; i < c; i += kBigThreads) yv[i] -= Rc[i] * yc;
+    __syncthreads();
+  }
+  for (int c = tid; c < nJ; c += kBigThreads) {
+    double dj = a.dscale ? a.dscale[J[c]] : 1.0;
+    a.mval[ps + c] = yv[c] * dj;
   }
 }
 
@@ -573,8 +796,12 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
   BSPAI_HIP(hipGetDevice(&h->device));
   h->n = n;
   h->nnz = Pd.nnz;
-  int32_t *mx = nullptr, *err = nullptr;
-  double *dsc = nullptr;
+  int32_t *mx = nullptr, *err = nullptr, *biglist = nullptr, *candof = nullptr;
+  int8_t *isbig = nullptr;
+  double *dsc = nullptr, *tiles = nullptr, *rhsb = nullptr;
+  int64_t *offs = nullptr;
+  int32_t *brows = nullptr;
+  int nbig = 0;
   auto body = [&]() -> int {
     int r;
     if ((r = dalloc_t(&h->m_rp, (size_t)n + 1)) || (r = dalloc_t(&h->m_col, (size_t)Pd.nnz + 1)) ||
@@ -583,23 +810,23 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
     BSPAI_HIP(hipMemcpyAsync(h->m_rp, Pd.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (Pd.nnz) BSPAI_HIP(hipMemcpyAsync(h->m_col, Pd.col, sizeof(int32_t) * Pd.nnz, hipMemcpyDeviceToDevice, s));
     if (n == 0) return BSPAI_OK;
-    if ((r = dalloc_t(&mx, 2)) || (r = dalloc_t(&err, 3))) return r;
-    int32_t hmx[2] = {0, 0};
+    if ((r = dalloc_t(&mx, 5)) || (r = dalloc_t(&err, 3)) || (r = dalloc_t(&isbig, (size_t)n)) ||
+        (r = dalloc_t(&biglist, (size_t)n)) || (r = dalloc_t(&candof, (size_t)n)))
+      return r;
+    int32_t hmx[5] = {0, 0, 0, 0, 0};
     BSPAI_HIP(hipMemsetAsync(mx, 0, sizeof(hmx), s));
     hipLaunchKernelGGL(k_spai_sizes, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_ptr, Pd.row_ptr, Pd.col,
-                       mx);
+                       mx, isbig, biglist, mx + 4, candof);
     BSPAI_CHECK_LAUNCH();
     BSPAI_HIP(hipMemcpyAsync(hmx, mx, sizeof(hmx), hipMemcpyDeviceToHost, s));
     BSPAI_HIP(hipStreamSynchronize(s));
     int nJmax = hmx[0], candmax = hmx[1];
+    nbig = hmx[4];
     int cand_p2 = 64;
     while (cand_p2 < candmax) cand_p2 <<= 1;
-    int64_t tile = (int64_t)std::max(candmax, 1) * std::max(nJmax, 1);
+    // the maxima may come from different rows; no row of this path exceeds kSmallTile
+    int64_t tile = std::min<int64_t>((int64_t)std::max(candmax, 1) * std::max(nJmax, 1), kSmallTile);
     size_t lds = sizeof(double) * ((size_t)cand_p2 /* two int lists */ + tile + cand_p2 + 64 + 64 + 64);
-    if (nJmax > 64 || lds > 160 * 1024)
-      return fail(BSPAI_EINVAL,
-                  "least-squares tile too large for the on-chip path (|J| max %d, shadow candidates max %d)", nJmax,
-                  candmax);
     if (o.scale) {
       if ((r = dalloc_t(&dsc, (size_t)n))) return r;
       hipLaunchKernelGGL(k_row_maxabs_inv, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_ptr, A->val, dsc);
@@ -619,9 +846,84 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
     sa.cand_p2 = cand_p2;
     sa.tile_cap = (int)tile;
     sa.err = err;
-    if (lds > 64 * 1024) BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_spai, dim3(n), dim3(64), lds, s, sa);
-    BSPAI_CHECK_LAUNCH();
+    sa.is_big = isbig;
+    if (nbig < n) {
+      if (lds > 64 * 1024)
+        BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      hipLaunchKernelGGL(k_spai, dim3(n), dim3(64), lds, s, sa);
+      BSPAI_CHECK_LAUNCH();
+    }
+    if (nbig > 0) {
+      // rows left to the block path, in batches whose tiles fit a scratch budget
+      std::vector<int32_t> hb(nbig), hcand(n), hprp(n + 1);
+      BSPAI_HIP(hipMemcpyAsync(hb.data(), biglist, sizeof(int32_t) * nbig, hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipMemcpyAsync(hcand.data(), candof, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipMemcpyAsync(hprp.data(), Pd.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipStreamSynchronize(s));
+      std::sort(hb.begin(), hb.end());
+      const int64_t budget = (int64_t)1 << 27;  // doubles of tile scratch per batch (1 GiB)
+      int64_t cap_tiles = 0, cap_rhs = 0;
+      std::vector<int64_t> toff, roff;
+      std::vector<std::pair<int, int>> batches;  // [first, last) into hb
+      {
+        int first = 0;
+        int64_t acc_t = 0, acc_r = 0;
+        for (int b = 0; b < nbig; b++) {
+          int k = hb[b];
+          int64_t nJ = hprp[k + 1] - hprp[k];
+          int64_t rows = hcand[k] / 2 + nJ + 1;  // multi rows <= candidates / 2, plus one folded row per column
+          int64_t t = rows * nJ, rr = rows;
+          if (b > first && (acc_t + t > budget || b - first >= 4096)) {
+            batches.push_back({first, b});
+            cap_tiles = std::max(cap_tiles, acc_t);
+            cap_rhs = std::max(cap_rhs, acc_r);
+            first = b;
+            acc_t = acc_r = 0;
+          }
+          toff.push_back(acc_t);
+          roff.push_back(acc_r);
+          acc_t += t;
+          acc_r += rr;
+        }
+        batches.push_back({first, nbig});
+        cap_tiles = std::max(cap_tiles, acc_t);
+        cap_rhs = std::max(cap_rhs, acc_r);
+      }
+      if ((r = dalloc_t(&tiles, (size_t)cap_tiles + 1)) || (r = dalloc_t(&rhsb, (size_t)cap_rhs + 1)) ||
+          (r = dalloc_t(&offs, 2 * (size_t)std::min(nbig, 4096) + 2)) ||
+          (r = dalloc_t(&brows, (size_t)std::min(nbig, 4096) + 1)))
+        return r;
+      const size_t lds_big = 8 * (size_t)kBigCand + 2 * 1024 * sizeof(double);
+      BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai_big, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_big));
+      for (auto &bt : batches) {
+        int cnt = bt.second - bt.first;
+        std::vector<int64_t> ho(2 * (size_t)cnt);
+        for (int t = 0; t < cnt; t++) {
+          ho[t] = toff[bt.first + t];
+          ho[cnt + t] = roff[bt.first + t];
+        }
+        BSPAI_HIP(hipMemcpyAsync(brows, hb.data() + bt.first, sizeof(int32_t) * cnt, hipMemcpyHostToDevice, s));
+        BSPAI_HIP(hipMemcpyAsync(offs, ho.data(), sizeof(int64_t) * 2 * cnt, hipMemcpyHostToDevice, s));
+        SpaiBigArgs ba;
+        ba.arp = A->row_ptr;
+        ba.acol = A->col;
+        ba.aval = A->val;
+        ba.prp = Pd.row_ptr;
+        ba.pcol = Pd.col;
+        ba.dscale = dsc;
+        ba.mval = h->m_val;
+        ba.rows = brows;
+        ba.tile_off = offs;
+        ba.rhs_off = offs + cnt;
+        ba.tiles = tiles;
+        ba.rhs = rhsb;
+        ba.err = err;
+        hipLaunchKernelGGL(k_spai_big, dim3(cnt), dim3(kBigThreads), lds_big, s, ba);
+        BSPAI_CHECK_LAUNCH();
+        BSPAI_HIP(hipStreamSynchronize(s));  // host arrays above are reused per batch
+      }
+    }
     BSPAI_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, s));
     BSPAI_HIP(hipStreamSynchronize(s));
     if (herr[2] != INT_MAX) return fail(BSPAI_EINVAL, "row %d: least-squares tile exceeds its capacity", herr[2]);
@@ -632,7 +934,8 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
     return BSPAI_OK;
   };
   rc = body();
-  dfree(mx), dfree(err), dfree(dsc);
+  dfree(mx), dfree(err), dfree(dsc), dfree(isbig), dfree(biglist), dfree(candof);
+  dfree(tiles), dfree(rhsb), dfree(offs), dfree(brows);
   if (rc) {
     free_handle_memory(h);
     delete h;

@@ -395,3 +395,42 @@ def test_autograd_matches_oracle_and_fd(B):
               + f(c["b"] - 2 * hstep * d)) / (12 * hstep)
         assert abs(fd - gb @ d) <= 1e-6 * abs(fd) + 1e-12
     h.free()
+
+
+# ---------------------------------------------------------------- block path
+
+def test_build_powerlaw_small_all_rows(B):
+    """Power-law rows (|J| up to ~120): the rows beyond the wavefront path go
+    through the block path with folded single-nonzero shadow rows."""
+    c = W.config("3", small=True)
+    A, P = c["A"], c["P"]
+    _say("build powerlaw small")
+    M = _spai_oracle(A, P)
+    h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), eps=c["eps"][0], precs=c["precs"])
+    m = h.export()["m64"]
+    lens = np.diff(P.row_ptr)
+    assert lens.max() > 64  # the block path is exercised
+    for i in range(A.n):
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        assert np.abs(m[s] - M.val[s]).max() <= 1e-10 * np.abs(M.val[s]).max(), i
+    h.free()
+
+
+def test_build_powerlaw_full_size_sampled_rows(B):
+    """n = 2^20 power-law matrix (rows up to 400 off-diagonals): sampled rows,
+    including the 12 longest patterns, against the oracle's least squares."""
+    c = W.config("3")
+    A, P = c["A"], c["P"]
+    _say("build powerlaw full")
+    h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), eps=c["eps"][0], precs=c["precs"])
+    m = h.export()["m64"]
+    lens = np.diff(P.row_ptr)
+    rng = np.random.default_rng(6)
+    rows = np.unique(np.concatenate([np.argsort(lens)[-12:], rng.choice(A.n, 60, replace=False)])).astype(np.int32)
+    Ms = _spai_oracle(A, P, rows=rows)
+    for i in rows:
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        assert np.abs(m[s] - Ms.val[s]).max() <= 1e-9 * np.abs(Ms.val[s]).max(), (i, lens[i])
+    st = h.stats()
+    assert sum(st["count"]) == P.nnz
+    h.free()
