@@ -129,7 +129,7 @@ typedef struct {
     double tol_rr;  /* stop when ||r||_inf / ||b||_inf <= tol_rr */
     double tol_be;  /* stop when ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) <= tol_be */
     int i_max;      /* at most this many refinement corrections (<= 64) */
-    int gmres_max;  /* at most this many GMRES iterations per correction; capped at min(n, 184),
+    int gmres_max;  /* at most this many GMRES iterations per correction; capped at min(n, 160),
                        the size whose rotated Hessenberg matrix stays on chip */
     int x0_mode;    /* 0: x_0 = M b with the FP64 M; 1: with M_b; 2: x_0 = 0; 3: x holds x_0 on entry */
     int trans;      /* 1: solve A^T x = b with (M_b)^T as a right preconditioner (adjoint solve) */
@@ -153,8 +153,13 @@ typedef struct {
  *   A^T M_b^T for trans = 1) to relative tolerance tau, x_{i+1} = x_i + d_i in FP64.
  *   Stops on tol_rr, tol_be, stagnation of ||d_i||/||x_{i+1}|| (more than half
  *   the previous ratio after the first correction) or i_max.
- *   A: device CSR; b, x: device FP64 arrays of n x nrhs, row-major (nrhs in
- *   {1, 2, 4, ..., 64}); st_host: host array of nrhs stats (or NULL).
+ *   A: device CSR; b, x: device FP64 arrays of n x nrhs, row-major (entry
+ *   (i, c) at i * nrhs + c), 1 <= nrhs <= 64; st_host: host array of nrhs
+ *   stats (or NULL).  nrhs = 1 runs as one persistent kernel; nrhs > 1 runs
+ *   every column's refinement together, each pass over the vectors and each
+ *   product with M_b and A serving all columns, every column stopping on its
+ *   own tests (a finished column takes no further corrections).  Needs
+ *   device workspace of about (gmres_max + 5) n nrhs values of u_g.
  *   M: handle from bspai_build / bspai_import (keep_fp64_M for x0_mode 0,
  *   build_T for trans).  Synchronises `stream`; returns ENOCONV / ENAN when
  *   some right-hand side ends that way (x is still written).

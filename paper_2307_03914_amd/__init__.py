@@ -256,21 +256,30 @@ def _stats_dict(s: _Stats) -> Dict:
 def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4,
           tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0,
           trans: bool = False, x: Optional[torch.Tensor] = None, stream=None, raise_noconv: bool = False):
-    """BSPAI-GMRES-IR.  Returns (x, stats dict).  ENOCONV is reported in stats
-    (status) unless raise_noconv."""
-    if b.dtype != torch.float64 or not b.is_cuda or b.dim() != 1:
-        raise ValueError("b must be a 1-D float64 CUDA tensor")
+    """BSPAI-GMRES-IR.  b: [n] or [n, nrhs] (1 <= nrhs <= 64, row-major)
+    float64 on the GPU.  Returns (x, stats): one stats dict for a 1-D b, a
+    list of them (one per column) for a 2-D b.  ENOCONV is reported in the
+    stats (status) unless raise_noconv."""
+    if b.dtype != torch.float64 or not b.is_cuda or b.dim() not in (1, 2):
+        raise ValueError("b must be a 1-D or 2-D float64 CUDA tensor")
     b = b.contiguous()
+    nrhs = 1 if b.dim() == 1 else b.shape[1]
+    if not 1 <= nrhs <= 64:
+        raise ValueError("b must have between 1 and 64 columns")
     if x is None:
         x = torch.zeros_like(b) if x0_mode == 3 else torch.empty_like(b)
+    elif x.shape != b.shape or x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 tensor shaped like b")
     tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), int(gmres_max),
                int(x0_mode), int(trans))
-    st = _Stats()
+    st = (_Stats * nrhs)()
     a = A._c()
     allow = () if raise_noconv else (ENOCONV,)
-    _check(_lib.gmres_ir_solve(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), 1, C.byref(st),
+    _check(_lib.gmres_ir_solve(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), nrhs, st,
                                _stream(stream)), allow=allow)
-    return x, _stats_dict(st)
+    if b.dim() == 1:
+        return x, _stats_dict(st[0])
+    return x, [_stats_dict(q) for q in st]
 
 
 from .autograd import BSPAISolve  # noqa: E402  (needs the names above)

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["runtime.hip", "apply.hip", "build.hip", "solve.hip"]
+SOURCES = ["runtime.hip", "apply.hip", "build.hip", "solve.hip", "solve_batched.hip"]
 OUT = os.path.join(HERE, "libbspai.so")
 ARCH = os.environ.get("BSPAI_OFFLOAD_ARCH", "gfx950")
 

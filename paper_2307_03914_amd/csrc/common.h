@@ -156,4 +156,10 @@ int pick_lanes(const BMat &M, int64_t nnz);
 int bmat_aligned(const BMat &M);
 int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s);
 
+// gmres_ir_solve for 2 <= R <= 64 right-hand sides (solve_batched.hip);
+// arguments already validated, m the GMRES cap.
+template <typename VT>
+int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
+                  int R, int m, gmres_ir_stats *st_host, hipStream_t s);
+
 }  // namespace bspai

@@ -742,7 +742,7 @@ extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_h
   if (A->n < 1) return fail(BSPAI_EINVAL, "gmres_ir_solve: empty system");
   if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val)) || !b || !x)
     return fail(BSPAI_EINVAL, "gmres_ir_solve: null device pointer");
-  if (nrhs != 1) return fail(BSPAI_EINVAL, "gmres_ir_solve: this entry point takes nrhs = 1 (got %d)", nrhs);
+  if (nrhs < 1 || nrhs > 64) return fail(BSPAI_EINVAL, "gmres_ir_solve: nrhs must be in 1..64 (got %d)", nrhs);
   if (tol->u_g != BSPAI_FP32 && tol->u_g != BSPAI_FP64) return fail(BSPAI_EINVAL, "gmres_ir_solve: u_g must be FP32 or FP64");
   if (tol->x0_mode < 0 || tol->x0_mode > 3) return fail(BSPAI_EINVAL, "gmres_ir_solve: x0_mode must be 0..3");
   if (tol->i_max < 0) return fail(BSPAI_EINVAL, "gmres_ir_solve: i_max < 0");
@@ -752,6 +752,11 @@ extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_h
   BSPAI_HIP(hipGetDevice(&dev));
   if (dev != M->device) return fail(BSPAI_EINVAL, "gmres_ir_solve: handle lives on device %d", M->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (nrhs > 1) {
+    const int m = std::min(std::max(tol->gmres_max, 1), std::min(A->n, kMaxGmres));
+    if (tol->u_g == BSPAI_FP64) return solve_batched<double>(A, b, M, tol, x, nrhs, m, st_host, s);
+    return solve_batched<float>(A, b, M, tol, x, nrhs, m, st_host, s);
+  }
   if (tol->u_g == BSPAI_FP64) return solve_typed<double>(A, b, M, tol, x, st_host, s);
   return solve_typed<float>(A, b, M, tol, x, st_host, s);
 }

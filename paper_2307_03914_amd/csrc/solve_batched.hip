@@ -1,0 +1,555 @@
+// gmres_ir_solve with several right-hand sides (Algorithm 4 for each column).
+//
+// The columns share every pass over the data: one bucketed product serves all
+// of them (M_b's bytes are read once per product, not once per column), and
+// each kernel below streams the n x R row-major vectors once.  At the sizes
+// where batching pays (n R of tens of millions) every MGS pass moves hundreds
+// of megabytes, so the passes are separate kernels driven from the host; the
+// per-column scalars (dots, norms, Givens state) stay on the device and are
+// reduced in a fixed order.  Each column keeps its own refinement state and
+// stops on its own; a column that is done contributes a zero right-hand side
+// to the remaining corrections.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "spmv_dev.h"
+
+namespace bspai {
+
+constexpr int kBT = 256;       // threads per block
+constexpr int kBGrid = 2048;   // blocks of the streaming kernels (grid-stride): 8 per CU
+
+// Thread t handles column t % Rp of rows t / Rp + g * (kBT / Rp) ...; Rp is R
+// rounded up to a power of two (<= 64), lanes c >= R idle.
+struct Cols {
+  int R, Rp;
+};
+
+__device__ __forceinline__ void col_mapping(const Cols &c, int &col, int64_t &row0, int64_t &stride) {
+  col = threadIdx.x % c.Rp;
+  int64_t groups = (int64_t)gridDim.x * (kBT / c.Rp);
+  row0 = (int64_t)blockIdx.x * (kBT / c.Rp) + threadIdx.x / c.Rp;
+  stride = groups;
+}
+
+// block partial per column (fixed order): part[blockIdx][col]
+template <bool MAX>
+__device__ __forceinline__ void block_cols(const Cols &c, double v, double *sh, double *part) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  if ((int)threadIdx.x < c.R) {
+    double a = sh[threadIdx.x];
+    for (int g = 1; g < kBT / c.Rp; g++) {
+      double t = sh[g * c.Rp + threadIdx.x];
+      a = MAX ? fmax(a, t) : a + t;
+    }
+    part[(int64_t)blockIdx.x * c.R + threadIdx.x] = a;
+  }
+}
+
+// out[c] = fixed-order reduction of the nblk block partials of column c (one
+// block per column: a strided sum per thread, then a tree in LDS); also stored
+// at out2[c * stride2] when out2 is given
+template <bool MAX>
+__global__ void __launch_bounds__(kBT) k_finish(int R, int nblk, const double *part, double *out, int sqrt_out,
+                                               double *out2, int64_t stride2) {
+  __shared__ double sh[kBT];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double a = 0.0;
+  for (int b = t; b < nblk; b += kBT) {
+    double v = part[(int64_t)b * R + c];
+    a = MAX ? fmax(a, v) : a + v;
+  }
+  sh[t] = a;
+  __syncthreads();
+  for (int o = kBT / 2; o > 0; o >>= 1) {
+    if (t < o) sh[t] = MAX ? fmax(sh[t], sh[t + o]) : sh[t] + sh[t + o];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double r = sqrt_out ? sqrt(sh[0]) : sh[0];
+    out[c] = r;
+    if (out2) out2[(int64_t)c * stride2] = r;
+  }
+}
+
+// residual r = b - A x (double-double or FP64) per column, max|r| and max|x|
+__global__ void __launch_bounds__(kBT) k_b_residual(Cols cc, int n, const int32_t *rp, const int32_t *col,
+                                                    const double *val, const double *b, const double *x, double *r,
+                                                    int dd, double *part_r, double *part_x) {
+  __shared__ double sh[kBT];
+  int c;
+  int64_t i, stride;
+  col_mapping(cc, c, i, stride);
+  double mr = 0.0, mx = 0.0;
+  const int R = cc.R;
+  for (; i < n; i += stride) {
+    if (c >= R) continue;
+    double s = b[i * R + c];
+    if (dd) {
+      double comp = 0.0;
+      for (int p = rp[i]; p < rp[i + 1]; p++) {
+        double a = -val[p], xv = x[(int64_t)col[p] * R + c];
+        double pr = __dmul_rn(a, xv);
+        double pe = fma(a, xv, -pr);
+        double t = __dadd_rn(s, pr);
+        double z = __dsub_rn(t, s);
+        double se = __dadd_rn(__dsub_rn(s, __dsub_rn(t, z)), __dsub_rn(pr, z));
+        s = t;
+        comp = __dadd_rn(comp, __dadd_rn(pe, se));
+      }
+      s = __dadd_rn(s, comp);
+    } else {
+      for (int p = rp[i]; p < rp[i + 1]; p++) s = __dsub_rn(s, __dmul_rn(val[p], x[(int64_t)col[p] * R + c]));
+    }
+    r[i * R + c] = s;
+    mr = fmax(mr, isfinite(s) ? fabs(s) : INFINITY);
+    double xv = x[i * R + c];
+    mx = fmax(mx, isfinite(xv) ? fabs(xv) : INFINITY);
+  }
+  block_cols<true>(cc, mr, sh, part_r);
+  __syncthreads();
+  block_cols<true>(cc, mx, sh, part_x);
+}
+
+// ||A||_inf (rows summed left to right) and max|b| per column
+__global__ void __launch_bounds__(kBT) k_b_norms(Cols cc, int n, const int32_t *rp, const double *val,
+                                                 const double *b, double *part_a, double *part_b) {
+  __shared__ double sh[kBT];
+  int c;
+  int64_t i, stride;
+  col_mapping(cc, c, i, stride);
+  double ma = 0.0, mb = 0.0;
+  for (; i < n; i += stride) {
+    if (c >= cc.R) continue;
+    if (c == 0) {
+      double s = 0.0;
+      for (int p = rp[i]; p < rp[i + 1]; p++) s += fabs(val[p]);
+      ma = fmax(ma, s);
+    }
+    mb = fmax(mb, fabs(b[i * cc.R + c]));
+  }
+  block_cols<true>(cc, ma, sh, part_a);
+  __syncthreads();
+  block_cols<true>(cc, mb, sh, part_b);
+}
+
+// x_0 = M b column by column with the FP64 M (rows in CSR order)
+__global__ void k_b_x0(int R, int n, const int32_t *rp, const int32_t *col, const double *val, const double *b,
+                       double *x) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * R) return;
+  int64_t i = t / R;
+  int c = (int)(t % R);
+  double acc = 0.0;
+  for (int p = rp[i]; p < rp[i + 1]; p++) acc = __dadd_rn(acc, __dmul_rn(val[p], b[(int64_t)col[p] * R + c]));
+  x[t] = acc;
+}
+
+// rv = (VT) r for active columns, 0 otherwise
+template <typename VT>
+__global__ void k_b_to_vt(int R, int64_t nr, const double *r, const int *active, VT *rv) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < nr) rv[t] = active[t % R] ? (VT)r[t] : (VT)0;
+}
+
+// sum of squares per column of a VT block
+template <typename VT>
+__global__ void __launch_bounds__(kBT) k_b_sumsq(Cols cc, int n, const VT *v, double *part) {
+  __shared__ double sh[kBT];
+  int c;
+  int64_t i, stride;
+  col_mapping(cc, c, i, stride);
+  double s = 0.0;
+  for (; i < n; i += stride)
+    if (c < cc.R) {
+      double t = (double)v[i * cc.R + c];
+      s = fma(t, t, s);
+    }
+  block_cols<false>(cc, s, sh, part);
+}
+
+// v = z / h per column (0 where h = 0); in place allowed
+template <typename VT>
+__global__ void k_b_scale(int R, int64_t nr, const VT *z, const double *h, VT *v) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nr) return;
+  double hh = h[t % R];
+  v[t] = hh > 0.0 ? (VT)((double)z[t] / hh) : (VT)0;
+}
+
+// MGS pass: z -= hprev * vprev (when vprev), then partial dots with vcur
+template <typename VT>
+__global__ void __launch_bounds__(kBT) k_b_mgs(Cols cc, int n, VT *z, const VT *vprev, const double *hprev,
+                                               const VT *vcur, double *part) {
+  __shared__ double sh[kBT];
+  int c;
+  int64_t i, stride;
+  col_mapping(cc, c, i, stride);
+  const int R = cc.R;
+  double hp = (vprev && c < R) ? hprev[c] : 0.0;
+  double s = 0.0;
+  for (; i < n; i += stride) {
+    if (c >= R) continue;
+    int64_t e = i * R + c;
+    double zz = (double)z[e];
+    if (vprev) {
+      zz = (double)(VT)fma(-hp, (double)vprev[e], zz);
+      z[e] = (VT)zz;
+    }
+    if (vcur) s = fma((double)vcur[e], zz, s);
+    else s = fma(zz, zz, s);
+  }
+  block_cols<false>(cc, s, sh, part);
+}
+
+// Givens step j for every column (one thread per column).  H column j holds
+// h_{0..j+1, j} on entry; rotated in place.  Writes res[c] = |g_{j+1}|.
+__global__ void k_b_givens(int R, int m, int j, double *H, double *cs, double *sn, double *g, const int *gm_active,
+                           double *res) {
+  int c = threadIdx.x;
+  if (c >= R) return;
+  double *h = H + ((int64_t)c * m + j) * (m + 1);
+  double *cc = cs + (int64_t)c * m, *ss = sn + (int64_t)c * m, *gg = g + (int64_t)c * (m + 1);
+  if (!gm_active[c]) {
+    res[c] = 0.0;
+    return;
+  }
+  for (int i = 0; i < j; i++) {
+    double a = h[i], b = h[i + 1];
+    h[i] = cc[i] * a + ss[i] * b;
+    h[i + 1] = -ss[i] * a + cc[i] * b;
+  }
+  double a = h[j], b = h[j + 1];
+  double rho = hypot(a, b);
+  cc[j] = rho == 0.0 ? 1.0 : a / rho;
+  ss[j] = rho == 0.0 ? 0.0 : b / rho;
+  h[j] = rho;
+  h[j + 1] = 0.0;
+  gg[j + 1] = -ss[j] * gg[j];
+  gg[j] = cc[j] * gg[j];
+  res[c] = fabs(gg[j + 1]);
+}
+
+// y = R^{-1} g for every column (k[c] iterations)
+__global__ void k_b_backsub(int R, int m, const double *H, const double *g, const int *kc, double *y) {
+  int c = threadIdx.x;
+  if (c >= R) return;
+  int k = kc[c];
+  const double *Hc = H + (int64_t)c * m * (m + 1);
+  const double *gg = g + (int64_t)c * (m + 1);
+  double *yy = y + (int64_t)c * m;
+  for (int i = k - 1; i >= 0; i--) {
+    double t = gg[i];
+    for (int j = i + 1; j < k; j++) t -= Hc[(int64_t)j * (m + 1) + i] * yy[j];
+    yy[i] = t / Hc[(int64_t)i * (m + 1) + i];
+  }
+}
+
+// d = V y per column (FP64); add mode: x += d, else out = d; max|d|, max|x|
+template <typename VT>
+__global__ void __launch_bounds__(kBT) k_b_update(Cols cc, int n, int m, const VT *V, int64_t vstride, const double *y,
+                                                  const int *kc, double *x, double *dout, double *part_d,
+                                                  double *part_x) {
+  __shared__ double sh[kBT];
+  int c;
+  int64_t i, stride;
+  col_mapping(cc, c, i, stride);
+  const int R = cc.R;
+  const int k = c < R ? kc[c] : 0;
+  const double *yy = y + (int64_t)(c < R ? c : 0) * m;
+  double md = 0.0, mx = 0.0;
+  for (; i < n; i += stride) {
+    if (c >= R) continue;
+    int64_t e = i * R + c;
+    double d = 0.0;
+    for (int t = 0; t < k; t++) d = fma((double)V[(int64_t)t * vstride + e], yy[t], d);
+    if (dout) {
+      dout[e] = d;
+    } else {
+      double xn = x[e] + d;
+      x[e] = xn;
+      md = fmax(md, fabs(d));
+      mx = fmax(mx, fabs(xn));
+    }
+  }
+  block_cols<true>(cc, md, sh, part_d);
+  __syncthreads();
+  block_cols<true>(cc, mx, sh, part_x);
+}
+
+// x += d (d FP64, computed by the transposed apply) with max|d|, max|x|
+__global__ void __launch_bounds__(kBT) k_b_add(Cols cc, int n, const double *d, double *x, double *part_d,
+                                               double *part_x) {
+  __shared__ double sh[kBT];
+  int c;
+  int64_t i, stride;
+  col_mapping(cc, c, i, stride);
+  double md = 0.0, mx = 0.0;
+  for (; i < n; i += stride) {
+    if (c >= cc.R) continue;
+    int64_t e = i * cc.R + c;
+    double xn = x[e] + d[e];
+    x[e] = xn;
+    md = fmax(md, fabs(d[e]));
+    mx = fmax(mx, fabs(xn));
+  }
+  block_cols<true>(cc, md, sh, part_d);
+  __syncthreads();
+  block_cols<true>(cc, mx, sh, part_x);
+}
+
+template <typename VT>
+__global__ void k_to_vt_vals(int64_t nnz, const double *a, VT *o) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) o[e] = (VT)a[e];
+}
+
+// ------------------------------------------------------------------ host
+
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() { dfree(p); }
+};
+
+template <typename VT>
+int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
+                  int R, int m, gmres_ir_stats *st_host, hipStream_t s) {
+  const int n = A->n;
+  const int64_t nnz = A->nnz, nr = (int64_t)n * R;
+  const bool tr = tol->trans != 0;
+  Cols cc{R, 1};
+  while (cc.Rp < R) cc.Rp <<= 1;
+  const int nblk = (int)std::min<int64_t>(kBGrid, (n + (kBT / cc.Rp) - 1) / (kBT / cc.Rp));
+  const unsigned eg = (unsigned)((nr + 255) / 256);
+
+  // operators: A (or A^T) in FP64 and in u_g, M_b (or M_b^T), FP64 M for x_0
+  DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb;
+  int rc;
+  const int32_t *arp = A->row_ptr, *acol = A->col;
+  const double *aval = A->val;
+  if (tr) {
+    if ((rc = dalloc(&trp.p, 4 * ((size_t)n + 1))) || (rc = dalloc(&tcol.p, 4 * (size_t)(nnz + 1))) ||
+        (rc = dalloc(&tval.p, 8 * (size_t)(nnz + 1))))
+      return rc;
+    if ((rc = csr_transpose(n, nnz, arp, acol, aval, 8, (int32_t *)trp.p, (int32_t *)tcol.p, tval.p, s))) return rc;
+    arp = (const int32_t *)trp.p, acol = (const int32_t *)tcol.p, aval = (const double *)tval.p;
+  }
+  if ((rc = dalloc(&apv.p, sizeof(VT) * (size_t)(nnz + 1))) || (rc = dalloc(&rbuf.p, 8 * (size_t)nr)) ||
+      (rc = dalloc(&rv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&wv.p, sizeof(VT) * (size_t)nr)) ||
+      (rc = dalloc(&zv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&Vb.p, sizeof(VT) * (size_t)nr * (m + 1))) ||
+      (rc = dalloc(&dtmp.p, 8 * (size_t)nr)) || (rc = dalloc(&parts.p, 2 * 8 * (size_t)kBGrid * R)) ||
+      (rc = dalloc(&scal.p, 8 * 8 * (size_t)R)) || (rc = dalloc(&Hb.p, 8 * (size_t)R * m * (m + 1))) ||
+      (rc = dalloc(&csb.p, 8 * (size_t)R * m)) || (rc = dalloc(&snb.p, 8 * (size_t)R * m)) ||
+      (rc = dalloc(&gb.p, 8 * (size_t)R * (m + 1))) || (rc = dalloc(&yb.p, 8 * (size_t)R * m)) ||
+      (rc = dalloc(&kcb.p, 4 * (size_t)R)) || (rc = dalloc(&actb.p, 4 * (size_t)R)))
+    return rc;
+  VT *Ap = (VT *)apv.p, *RV = (VT *)rv.p, *W = (VT *)wv.p, *Z = (VT *)zv.p, *V = (VT *)Vb.p;
+  double *r64 = (double *)rbuf.p, *D = (double *)dtmp.p, *P1 = (double *)parts.p, *P2 = P1 + (int64_t)kBGrid * R;
+  double *S = (double *)scal.p;  // 8 rows of R scalars
+  double *H = (double *)Hb.p, *CS = (double *)csb.p, *SN = (double *)snb.p, *G = (double *)gb.p, *Y = (double *)yb.p;
+  int *KC = (int *)kcb.p, *ACT = (int *)actb.p;
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_to_vt_vals<VT>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, aval, Ap);
+    BSPAI_CHECK_LAUNCH();
+  }
+  BMat Apm;
+  memset(&Apm, 0, sizeof(Apm));
+  Apm.n = n;
+  Apm.nb = 1;
+  Apm.nnz = nnz;
+  Apm.prec[0] = sizeof(VT) == 8 ? BSPAI_FP64 : BSPAI_FP32;
+  Apm.scale[0] = 1.0;
+  Apm.rp[0] = arp;
+  Apm.col[0] = acol;
+  Apm.val[0] = Ap;
+  const BMat &Mb = tr ? M->matT : M->mat;
+  const int fp64 = sizeof(VT) == 8;
+
+  auto finish = [&](bool mx, const double *part, double *out, int sq, double *out2 = nullptr,
+                    int64_t stride2 = 0) -> int {
+    if (mx)
+      hipLaunchKernelGGL(k_finish<true>, dim3(R), dim3(kBT), 0, s, R, nblk, part, out, sq, out2, stride2);
+    else
+      hipLaunchKernelGGL(k_finish<false>, dim3(R), dim3(kBT), 0, s, R, nblk, part, out, sq, out2, stride2);
+    BSPAI_CHECK_LAUNCH();
+    return BSPAI_OK;
+  };
+  auto to_host = [&](const double *d, std::vector<double> &h, int rows = 1) -> int {
+    h.resize((size_t)R * rows);
+    BSPAI_HIP(hipMemcpyAsync(h.data(), d, 8 * (size_t)R * rows, hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    return BSPAI_OK;
+  };
+
+  // norms of A and b, x_0
+  hipLaunchKernelGGL(k_b_norms, dim3(nblk), dim3(kBT), 0, s, cc, n, arp, aval, b, P1, P2);
+  BSPAI_CHECK_LAUNCH();
+  if ((rc = finish(true, P1, S + 0 * R, 0)) || (rc = finish(true, P2, S + 1 * R, 0))) return rc;
+  std::vector<double> hnA, hnb;
+  if ((rc = to_host(S + 0 * R, hnA)) || (rc = to_host(S + 1 * R, hnb))) return rc;
+  const double normA = hnA[0];
+  if (tol->x0_mode == 0) {
+    const int32_t *frp = tr ? M->mT_rp : M->m_rp, *fcol = tr ? M->mT_col : M->m_col;
+    const double *fval = tr ? M->mT_val : M->m_val;
+    hipLaunchKernelGGL(k_b_x0, dim3(eg), dim3(256), 0, s, R, n, frp, fcol, fval, b, x);
+    BSPAI_CHECK_LAUNCH();
+  } else if (tol->x0_mode == 1) {
+    if ((rc = launch_bspmv(Mb, b, x, R, R, 1, s))) return rc;
+  } else if (tol->x0_mode == 2) {
+    BSPAI_HIP(hipMemsetAsync(x, 0, 8 * (size_t)nr, s));
+  }
+
+  std::vector<gmres_ir_stats> st(R);
+  for (auto &q : st) memset(&q, 0, sizeof(q));
+  std::vector<int> active(R, 1), stag(R, 0), status(R, BSPAI_OK);
+  std::vector<double> dx_prev(R, 0.0), hr, hx, hbeta;
+  int it = 0;
+  for (;;) {
+    // residuals and stopping tests per column
+    hipLaunchKernelGGL(k_b_residual, dim3(nblk), dim3(kBT), 0, s, cc, n, arp, acol, aval, b, x, r64, tol->ur_dd, P1,
+                       P2);
+    BSPAI_CHECK_LAUNCH();
+    if ((rc = finish(true, P1, S + 2 * R, 0)) || (rc = finish(true, P2, S + 3 * R, 0))) return rc;
+    if ((rc = to_host(S + 2 * R, hr)) || (rc = to_host(S + 3 * R, hx))) return rc;
+    int nact = 0;
+    for (int c = 0; c < R; c++) {
+      if (!active[c]) continue;
+      double nr_ = hr[c], nx = hx[c], nb_ = hnb[c];
+      double eta = nr_ / (normA * nx + nb_);
+      double rho = nb_ > 0 ? nr_ / nb_ : nr_;
+      if (it <= 64) {
+        st[c].eta[it] = eta;
+        st[c].relres[it] = rho;
+      }
+      int reason = 0;
+      if (!std::isfinite(nr_) || !std::isfinite(nx)) {
+        reason = 5;
+        status[c] = BSPAI_ENAN;
+      } else if (rho <= tol->tol_rr) reason = 1;
+      else if (eta <= tol->tol_be) reason = 2;
+      else if (stag[c]) reason = 3;
+      else if (it >= tol->i_max || it >= 64) {
+        reason = 4;
+        status[c] = BSPAI_ENOCONV;
+      }
+      if (reason) {
+        active[c] = 0;
+        st[c].stop_reason = reason;
+        st[c].steps = it;
+      } else {
+        nact++;
+      }
+    }
+    if (nact == 0) break;
+    BSPAI_HIP(hipMemcpyAsync(ACT, active.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
+    // right-hand side of the Krylov solve
+    hipLaunchKernelGGL(k_b_to_vt<VT>, dim3(eg), dim3(256), 0, s, R, nr, r64, ACT, RV);
+    BSPAI_CHECK_LAUNCH();
+    if (!tr) {
+      if ((rc = launch_bspmv(Mb, RV, V, R, R, fp64, s))) return rc;
+    } else {
+      BSPAI_HIP(hipMemcpyAsync(V, RV, sizeof(VT) * (size_t)nr, hipMemcpyDeviceToDevice, s));
+    }
+    hipLaunchKernelGGL(k_b_sumsq<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, V, P1);
+    BSPAI_CHECK_LAUNCH();
+    if ((rc = finish(false, P1, S + 4 * R, 1))) return rc;  // beta
+    if ((rc = to_host(S + 4 * R, hbeta))) return rc;
+    hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, V, S + 4 * R, V);
+    BSPAI_CHECK_LAUNCH();
+    std::vector<int> gm_active(R), kc(R, 0);
+    std::vector<double> g0(R * (size_t)(m + 1), 0.0);
+    for (int c = 0; c < R; c++) {
+      gm_active[c] = active[c] && hbeta[c] > 0.0;
+      g0[(size_t)c * (m + 1)] = hbeta[c];
+    }
+    BSPAI_HIP(hipMemcpyAsync(G, g0.data(), 8 * g0.size(), hipMemcpyHostToDevice, s));
+    int *GMA = ACT;  // reuse: active GMRES columns
+    BSPAI_HIP(hipMemcpyAsync(GMA, gm_active.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
+    int nrun = 0;
+    for (int c = 0; c < R; c++) nrun += gm_active[c];
+    for (int j = 0; j < m && nrun > 0; j++) {
+      VT *vj = V + (int64_t)j * nr;
+      if (!tr) {
+        if ((rc = launch_bspmv(Apm, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Mb, W, Z, R, R, fp64, s))) return rc;
+      } else {
+        if ((rc = launch_bspmv(Mb, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Apm, W, Z, R, R, fp64, s))) return rc;
+      }
+      // MGS: pass i removes v_{i-1}, measures v_i; h_{i,j} lands in H column j
+      for (int i = 0; i <= j + 1; i++) {
+        const VT *vprev = i > 0 ? V + (int64_t)(i - 1) * nr : nullptr;
+        const VT *vcur = i <= j ? V + (int64_t)i * nr : nullptr;
+        const double *hprev = S + 5 * R;
+        hipLaunchKernelGGL(k_b_mgs<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, Z, vprev, hprev, vcur, P1);
+        BSPAI_CHECK_LAUNCH();
+        // the finished scalar goes to S row 5 (next pass) and into H column j
+        if ((rc = finish(false, P1, S + 5 * R, i > j, H + (int64_t)j * (m + 1) + i, (int64_t)m * (m + 1)))) return rc;
+      }
+      // v_{j+1} = z / h_{j+1,j}
+      hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, Z, S + 5 * R, V + (int64_t)(j + 1) * nr);
+      BSPAI_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_b_givens, dim3(1), dim3(64), 0, s, R, m, j, H, CS, SN, G, GMA, S + 6 * R);
+      BSPAI_CHECK_LAUNCH();
+      std::vector<double> hq;  // row 0: h_{j+1,j}, row 1: |g_{j+1}|
+      if ((rc = to_host(S + 5 * R, hq, 2))) return rc;
+      const double *hn = hq.data(), *hres = hq.data() + R;
+      bool changed = false;
+      for (int c = 0; c < R; c++) {
+        if (!gm_active[c]) continue;
+        kc[c] = j + 1;
+        if (hres[c] <= tol->tau * hbeta[c] || hn[c] == 0.0 || j + 1 == m) {
+          gm_active[c] = 0;
+          nrun--;
+          changed = true;
+        }
+      }
+      if (changed) BSPAI_HIP(hipMemcpyAsync(GMA, gm_active.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
+    }
+    BSPAI_HIP(hipMemcpyAsync(KC, kc.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_b_backsub, dim3(1), dim3(64), 0, s, R, m, H, G, KC, Y);
+    BSPAI_CHECK_LAUNCH();
+    if (!tr) {
+      hipLaunchKernelGGL(k_b_update<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, m, V, nr, Y, KC, x, nullptr, P1, P2);
+      BSPAI_CHECK_LAUNCH();
+    } else {
+      hipLaunchKernelGGL(k_b_update<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, m, V, nr, Y, KC, x, r64, P1, P2);
+      BSPAI_CHECK_LAUNCH();
+      if ((rc = launch_bspmv(Mb, r64, D, R, R, 1, s))) return rc;  // d = M_b^T (V y) in FP64
+      hipLaunchKernelGGL(k_b_add, dim3(nblk), dim3(kBT), 0, s, cc, n, D, x, P1, P2);
+      BSPAI_CHECK_LAUNCH();
+    }
+    if ((rc = finish(true, P1, S + 6 * R, 0)) || (rc = finish(true, P2, S + 7 * R, 0))) return rc;
+    std::vector<double> hdn, hxn;
+    if ((rc = to_host(S + 6 * R, hdn)) || (rc = to_host(S + 7 * R, hxn))) return rc;
+    for (int c = 0; c < R; c++) {
+      if (!active[c]) continue;
+      if (it < 64) st[c].its[it] = kc[c];
+      st[c].its_total += kc[c];
+      double dx = hxn[c] > 0 ? hdn[c] / hxn[c] : 0.0;
+      if (it >= 1 && dx > 0.5 * dx_prev[c]) stag[c] = 1;
+      dx_prev[c] = dx;
+    }
+    it++;
+  }
+  int worst = BSPAI_OK;
+  for (int c = 0; c < R; c++) {
+    st[c].status = status[c];
+    if (status[c] == BSPAI_ENAN) worst = BSPAI_ENAN;
+    else if (status[c] == BSPAI_ENOCONV && worst == BSPAI_OK) worst = BSPAI_ENOCONV;
+  }
+  if (st_host) memcpy(st_host, st.data(), sizeof(gmres_ir_stats) * R);
+  BSPAI_HIP(hipStreamSynchronize(s));
+  if (worst == BSPAI_ENOCONV) return fail(BSPAI_ENOCONV, "gmres_ir_solve: some right-hand side reached i_max");
+  if (worst == BSPAI_ENAN) return fail(BSPAI_ENAN, "gmres_ir_solve: NaN or infinity in a residual");
+  return BSPAI_OK;
+}
+
+template int solve_batched<float>(const bspai_csr *, const double *, const bspai_handle *, const gmres_ir_tol *,
+                                  double *, int, int, gmres_ir_stats *, hipStream_t);
+template int solve_batched<double>(const bspai_csr *, const double *, const bspai_handle *, const gmres_ir_tol *,
+                                   double *, int, int, gmres_ir_stats *, hipStream_t);
+
+}  // namespace bspai

@@ -302,6 +302,96 @@ def test_solve_matches_oracle(B, key, eps_i):
     h.free()
 
 
+def _check_column(st, ref, eta_g):
+    assert st["status"] == ref["status"] == 0
+    assert st["stop_reason"] == ref["stop_reason"] == 1
+    assert eta_g <= 10 * ref["eta"][-1] + 1e-17
+    assert abs(st["steps"] - ref["steps"]) <= 1
+    assert abs(st["its_total"] - ref["its_total"]) <= max(3, 0.15 * ref["its_total"]), (st["its"], ref["its"])
+    assert np.isclose(st["eta"][-1], eta_g, rtol=1e-12, atol=0)
+
+
+def test_solve_batched_matches_oracle(B):
+    """8 right-hand sides of the 16^3 anisotropic problem in one call: every
+    column against the oracle's single-RHS solve of that column."""
+    c = W.config("4a", small=True)
+    A, P, Bm = c["A"], c["P"], c["b"]
+    eps = c["eps"][0]
+    _say("solve batched 4a small", Bm.shape)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    xg, sts, h = _solve_case(B, A, P, Bm, c["precs"], eps, **kw)
+    assert xg.shape == Bm.shape and len(sts) == Bm.shape[1]
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, eps, c["precs"])
+    for col in range(Bm.shape[1]):
+        b = Bm[:, col].copy()
+        ref = O.gmres_ir(A, M, Mb, b, **kw)
+        _check_column(sts[col], ref, O.backward_error(A, b, xg[:, col]))
+    h.free()
+
+
+def test_solve_batched_columns_independent(B):
+    """Three columns (not a power of two): a repeated column gives the same
+    bits, a zero column stops at once, and each column agrees with the
+    single-RHS path."""
+    c = W.config("2", small=True)
+    A, P, b = c["A"], c["P"], c["b"]
+    _say("solve batched independence")
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    Bm = np.stack([b, np.zeros_like(b), b], axis=1)
+    xg, sts, h = _solve_case(B, A, P, Bm, c["precs"], c["eps"][1], **kw)
+    assert np.array_equal(xg[:, 0], xg[:, 2])
+    assert sts[0] == sts[2]
+    assert sts[1]["steps"] == 0 and sts[1]["status"] == 0 and np.abs(xg[:, 1]).max() == 0.0
+    x1, st1 = B.solve(B.CSRMatrix.from_host(A), _dev(b), h, **kw)
+    x1 = x1.cpu().numpy()
+    assert sts[0]["stop_reason"] == st1["stop_reason"] == 1
+    assert abs(sts[0]["its_total"] - st1["its_total"]) <= max(3, 0.15 * st1["its_total"])
+    assert O.backward_error(A, b, xg[:, 0]) <= 10 * O.backward_error(A, b, x1) + 1e-17
+    h.free()
+
+
+@pytest.mark.parametrize("x0_mode", [1, 2, 3])
+def test_solve_batched_x0_modes_fp64(B, x0_mode):
+    """FP64 working precision and the other starting vectors, two columns."""
+    import torch
+
+    c = W.config("2", small=True)
+    A, P, b = c["A"], c["P"], c["b"]
+    _say("solve batched fp64 x0", x0_mode)
+    Bm = np.stack([b, -0.5 * b + 1.0], axis=1)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=2.0 ** -53, precs=["fp64"])
+    x = _dev(0.25 * Bm) if x0_mode == 3 else None
+    xg, sts = B.solve(Ad, _dev(Bm), h, u_g="fp64", tau=1e-8, tol_rr=1e-12, gmres_max=150, x0_mode=x0_mode, x=x)
+    torch.cuda.synchronize()
+    xg = xg.cpu().numpy()
+    D = A.dense()
+    for col in range(2):
+        assert sts[col]["status"] == 0 and sts[col]["relres"][-1] <= 1e-12
+        assert O.backward_error(A, Bm[:, col], xg[:, col]) <= 1e-15
+        assert np.abs(xg[:, col] - np.linalg.solve(D, Bm[:, col])).max() <= 1e-9 * np.abs(xg[:, col]).max()
+    h.free()
+
+
+def test_solve_batched_adjoint(B):
+    """A^T Lambda = G for four columns with the right-preconditioned path."""
+    c = W.config("5", small=True)
+    A, P = c["A"], c["P"]
+    _say("solve batched adjoint")
+    kw = dict(tau=1e-4, tol_rr=1e-13, gmres_max=150, i_max=30)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=c["eps"][0], precs=c["precs"])
+    G = np.random.default_rng(13).standard_normal((A.n, 4))
+    lam, sts = B.solve(Ad, _dev(G), h, trans=True, **kw)
+    lam = lam.cpu().numpy()
+    ref = np.linalg.solve(A.dense().T, G)
+    for col in range(4):
+        assert sts[col]["status"] == 0
+        assert np.abs(lam[:, col] - ref[:, col]).max() <= 1e-9 * np.abs(ref[:, col]).max()
+    h.free()
+
+
 def test_solve_fp64_working_precision(B):
     c = W.config("2", small=True)
     _say("solve fp64")
