@@ -167,6 +167,47 @@ typedef struct {
 int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
                    double *x, int nrhs, gmres_ir_stats *st_host, void *stream);
 
+/*
+ * Many independent systems in one persistent launch (Algorithm 4 for each).
+ *
+ * bspai_multi_plan -- prepare the solve of systems A_k x_k = b_k, k < nsys,
+ *   each with its own preconditioner M_k and the tolerances `tol` (as for
+ *   gmres_ir_solve with nrhs = 1).  The plan copies A_k rounded to u_g (and
+ *   A_k^T for trans) into device memory it owns, so A_k's values are read
+ *   now; b_k and x_k are read and written at every launch and must stay
+ *   allocated until bspai_multi_free.  The grid is cut into groups of
+ *   group_blocks blocks (0: the smallest group that holds the largest system
+ *   at 16 rows per thread); each group takes the next system off a device
+ *   queue, largest first, until the queue is empty.  max_groups (0: as many
+ *   as the device keeps resident, at most nsys) caps the number of groups.
+ *   The launch is captured once into a HIP graph.  Synchronises `stream`.
+ *   Results do not depend on which group takes a system, so replays with the
+ *   same b_k give identical bits.  EINVAL when a group does not fit on the
+ *   device or a system fails gmres_ir_solve's checks.
+ * bspai_multi_launch -- replay the graph on `stream` (asynchronous, no
+ *   allocation).  Launches of one plan must not overlap.
+ * bspai_multi_poll -- 1 when the last launch has finished (reads one word of
+ *   host memory that the kernel writes when its last group leaves), else 0.
+ * bspai_multi_wait -- synchronise `stream`, copy the nsys stats to st_host (or
+ *   skip if NULL); ENOCONV / ENAN when some system ends that way.
+ * bspai_multi_free -- release the plan (NULL is ignored); waits for the device.
+ */
+typedef struct {
+    bspai_csr A;                /* device CSR of system k */
+    const double *b;            /* device FP64 [n] */
+    double *x;                  /* device FP64 [n]: x_0 on entry for x0_mode 3, the solution on exit */
+    const bspai_handle *M;      /* preconditioner of system k (same device) */
+} bspai_system;
+
+typedef struct bspai_multi bspai_multi;
+
+int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_ir_tol *tol, int group_blocks, int max_groups,
+                     bspai_multi **plan_out, void *stream);
+int bspai_multi_launch(bspai_multi *plan, void *stream);
+int bspai_multi_poll(const bspai_multi *plan);
+int bspai_multi_wait(bspai_multi *plan, gmres_ir_stats *st_host, void *stream);
+void bspai_multi_free(bspai_multi *plan);
+
 typedef struct {
     int32_t n;
     int32_t q;

@@ -8,7 +8,10 @@ functions mirror the C interface in ``include/bspai.h``:
   ``bspai_import``): SPAI of A on a pattern (FP64 Householder least squares,
   run on A^T and transposed), then bucketing of its entries by magnitude.
 * :func:`apply` / :func:`apply_T` (``bspai_apply`` / ``bspai_apply_T``).
-* :func:`solve` (``gmres_ir_solve``): GMRES-based iterative refinement.
+* :func:`solve` (``gmres_ir_solve``): GMRES-based iterative refinement, one
+  or up to 64 right-hand sides.
+* :class:`MultiPlan` (``bspai_multi_*``): many independent systems in one
+  persistent launch, replayed from a captured HIP graph.
 * :class:`BSPAISolve`: ``torch.autograd.Function`` whose backward solves the
   adjoint system with the transposed bucketed preconditioner.
 
@@ -19,7 +22,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
-from typing import Dict, Optional, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
 
@@ -68,6 +71,10 @@ class _BStats(C.Structure):
                 ("bytes_indices", C.c_int64), ("storage_pct", C.c_double)]
 
 
+class _System(C.Structure):
+    _fields_ = [("A", _CSR), ("b", C.c_void_p), ("x", C.c_void_p), ("M", C.c_void_p)]
+
+
 _lib = C.CDLL(LIBPATH)
 _vp = C.c_void_p
 _lib.bspai_build.argtypes = [C.POINTER(_CSR), C.POINTER(_Pattern), C.c_double, C.POINTER(C.c_int), C.c_int,
@@ -85,13 +92,21 @@ _lib.bspai_last_error.restype = C.c_char_p
 _lib.bspai_set_profiling.argtypes = [C.c_int]
 _lib.bspai_set_profiling.restype = None
 _lib.bspai_last_solve_kernel_ms.restype = C.c_double
+_lib.bspai_multi_plan.argtypes = [C.POINTER(_System), C.c_int, C.POINTER(_Tol), C.c_int, C.c_int, C.POINTER(_vp),
+                                  _vp]
+_lib.bspai_multi_launch.argtypes = [_vp, _vp]
+_lib.bspai_multi_poll.argtypes = [_vp]
+_lib.bspai_multi_wait.argtypes = [_vp, C.POINTER(_Stats), _vp]
+_lib.bspai_multi_free.argtypes = [_vp]
+_lib.bspai_multi_free.restype = None
 for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
-           "bspai_export"):
+           "bspai_export", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll", "bspai_multi_wait"):
     getattr(_lib, _f).restype = C.c_int
 
 SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
            "bspai_export", "bspai_free", "bspai_last_error", "bspai_grad_vals", "bspai_set_profiling",
-           "bspai_last_solve_kernel_ms")
+           "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
+           "bspai_multi_wait", "bspai_multi_free")
 
 
 def set_profiling(on: bool) -> None:
@@ -282,7 +297,65 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
     return x, [_stats_dict(q) for q in st]
 
 
+class MultiPlan:
+    """Independent systems solved in one persistent launch replayed from a
+    captured HIP graph (``bspai_multi_*``).  ``systems``: list of
+    (CSRMatrix A, b tensor, Handle M[, x tensor]); b and x are 1-D float64
+    CUDA tensors that the plan keeps referenced (each launch reads b and
+    writes x)."""
+
+    def __init__(self, systems, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4, tol_rr: float = 1e-10,
+                 tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0, trans: bool = False,
+                 group_blocks: int = 0, max_groups: int = 0, stream=None):
+        self._ptr = None
+        self.A, self.b, self.x, self.M = [], [], [], []
+        arr = (_System * len(systems))()
+        for k, item in enumerate(systems):
+            A, b, M = item[0], item[1], item[2]
+            x = item[3] if len(item) > 3 else None
+            if b.dtype != torch.float64 or not b.is_cuda or b.dim() != 1 or b.shape[0] != A.n:
+                raise ValueError("each b must be a 1-D float64 CUDA tensor of length n")
+            b = b.contiguous()
+            if x is None:
+                x = torch.zeros_like(b)
+            self.A.append(A), self.b.append(b), self.x.append(x), self.M.append(M)
+            arr[k].A = A._c()
+            arr[k].b = b.data_ptr()
+            arr[k].x = x.data_ptr()
+            arr[k].M = M.ptr
+        self.tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max),
+                        int(gmres_max), int(x0_mode), int(trans))
+        out = _vp()
+        _check(_lib.bspai_multi_plan(arr, len(systems), C.byref(self.tol), int(group_blocks), int(max_groups),
+                                     C.byref(out), _stream(stream)))
+        self._ptr = out.value
+        self.nsys = len(systems)
+
+    def launch(self, stream=None) -> None:
+        _check(_lib.bspai_multi_launch(self._ptr, _stream(stream)))
+
+    def poll(self) -> bool:
+        return bool(_lib.bspai_multi_poll(self._ptr))
+
+    def wait(self, stream=None, raise_noconv: bool = False) -> List[Dict]:
+        st = (_Stats * self.nsys)()
+        allow = () if raise_noconv else (ENOCONV,)
+        _check(_lib.bspai_multi_wait(self._ptr, st, _stream(stream)), allow=allow)
+        return [_stats_dict(q) for q in st]
+
+    def free(self) -> None:
+        if self._ptr:
+            _lib.bspai_multi_free(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 from .autograd import BSPAISolve  # noqa: E402  (needs the names above)
 
-__all__ = ["CSRMatrix", "Handle", "build", "import_m", "apply", "apply_T", "solve", "BSPAISolve", "BSPAIError",
-           "SYMBOLS", "PREC"]
+__all__ = ["CSRMatrix", "Handle", "build", "import_m", "apply", "apply_T", "solve", "MultiPlan", "BSPAISolve",
+           "BSPAIError", "SYMBOLS", "PREC"]

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "common.h"
 #include "spmv_dev.h"
@@ -65,11 +66,12 @@ struct SolveParams {
 
 // ------------------------------------------------------------------ sync
 
-__device__ bool grid_sync(const Grid &g, unsigned &epoch) {
+// bid: index of the calling block among the G blocks that share `g`
+__device__ bool grid_sync(const Grid &g, unsigned &epoch, int bid) {
   epoch++;
   __syncthreads();
   if (g.G == 1) return true;
-  if (threadIdx.x == 0) __hip_atomic_store(&g.flags[blockIdx.x], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) __hip_atomic_store(&g.flags[bid], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   int bad = 0;
   if ((int)threadIdx.x < g.G) {
     unsigned spins = 0;
@@ -130,7 +132,7 @@ __device__ __forceinline__ bool collect_partial(unsigned long long *w, unsigned 
 // results.  Two workgroup barriers; data other than the scalars is not
 // published (use grid_sync for that).
 template <int W, bool MAX>
-__device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], double *sh) {
+__device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], double *sh, int bid) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double part[W];
 #pragma unroll
@@ -160,7 +162,7 @@ __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], doubl
       for (int c = 0; c < W; c++) {
         double a = sh[c];
         for (int k = 1; k < kWaves; k++) a = MAX ? fmax(a, sh[k * W + c]) : a + sh[k * W + c];
-        publish_partial(set + ((size_t)blockIdx.x * kMaxSlotWidth + c) * 2, a, rtag);
+        publish_partial(set + ((size_t)bid * kMaxSlotWidth + c) * 2, a, rtag);
       }
     }
     if (wv == 0) {
@@ -243,12 +245,12 @@ __device__ __forceinline__ double residual_row(const int32_t *rp, const int32_t 
 
 // ------------------------------------------------------------------ kernel
 
-// The parameters live in device memory (a by-value kernel argument that is
-// referenced would be copied to scratch).
+// Algorithm 4 for one system by the G blocks of `G`; bid is the calling
+// block's index among them.  epoch and rtag carry on from earlier calls by
+// the same blocks.  Returns false when a wait timed out (G.abortf is set).
 template <typename VT, typename PT, int ZR>
-__global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT> *__restrict__ pp) {
-  const SolveParams<VT> &p = *pp;
-  extern __shared__ double sm[];
+__device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, unsigned &epoch, unsigned &rtag,
+                              double *sm, double *sh, int &s_flag) {
   constexpr int kCap = kTileBytes / sizeof(PT);
   const int m = p.m_max;
   double *cs = sm;            // m
@@ -261,14 +263,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
   // products of both operators: all buckets of a sub-range of rows at once
 #define SPMV_M(Mat, in, out) bspmv_tile_all<VT, VT, PT>(Mat, in, out, r0, r1, tprod, kCap, p.rows_m)
 #define SPMV_A(Mat, in, out) bspmv_tile_all<VT, VT, PT>(Mat, in, out, r0, r1, tprod, kCap, p.rows_a)
-  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
-  __shared__ int s_flag;
-  const int tid = threadIdx.x, nt = blockDim.x, bid = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int n = p.n;
-  const int r0 = bid * p.rows_per_block;
+  const int r0 = min(n, bid * p.rows_per_block);  // blocks past the last row own none
   const int r1 = min(n, r0 + p.rows_per_block);
-  unsigned epoch = 0, rtag = 0;
-  const Grid &G = p.grid;
   const bool rec = (bid == 0 && tid == 0);
 
 #define OWN_ROWS(k, i) \
@@ -284,7 +282,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
       v[0] = fmax(v[0], s);
       v[1] = fmax(v[1], fabs(p.b[i]));
     }
-    if (!grid_reduce<2, true>(G, rtag, v, sh)) return;
+    if (!grid_reduce<2, true>(G, rtag, v, sh, bid)) return false;
     normA = v[0];
     normb = v[1];
   }
@@ -301,7 +299,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
   } else if (p.x0_mode == 2) {
     OWN_ROWS(k, i) { p.x[i] = 0.0; }
   }
-  if (!grid_sync(G, epoch)) return;
+  if (!grid_sync(G, epoch, bid)) return false;
 
   int it = 0, stag = 0, status = BSPAI_OK, reason = 0, its_total = 0;
   double dx_prev = 0.0;
@@ -316,7 +314,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
       double xv = p.x[i];
       nv[1] = fmax(nv[1], isfinite(xv) ? fabs(xv) : INFINITY);
     }
-    if (!grid_reduce<2, true>(G, rtag, nv, sh)) return;
+    if (!grid_reduce<2, true>(G, rtag, nv, sh, bid)) return false;
     const double nr = nv[0], nx = nv[1];
     const double eta = nr / (normA * nx + normb);
     const double rho = normb > 0 ? nr / normb : nr;
@@ -335,7 +333,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
     VT *V0 = p.V;
     double ss[1] = {0.0};
     if (!p.trans) {
-      if (!grid_sync(G, epoch)) return;
+      if (!grid_sync(G, epoch, bid)) return false;
       SPMV_M(p.Mb, p.rv, V0);
       __syncthreads();
       OWN_ROWS(k, i) {
@@ -349,22 +347,22 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
         ss[0] += s * s;
       }
     }
-    if (!grid_reduce<1, false>(G, rtag, ss, sh)) return;
+    if (!grid_reduce<1, false>(G, rtag, ss, sh, bid)) return false;
     const double beta = sqrt(ss[0]);
     int kdone = 0;
     if (beta > 0.0) {
       OWN_ROWS(k, i) { V0[i] = (VT)((double)V0[i] / beta); }
       if (tid == 0) g[0] = beta;
-      if (!grid_sync(G, epoch)) return;
+      if (!grid_sync(G, epoch, bid)) return false;
       for (int j = 0; j < m; j++) {
         const VT *vj = p.V + (size_t)j * n;
         if (!p.trans) {
           SPMV_A(p.Ap, vj, p.w);
-          if (!grid_sync(G, epoch)) return;
+          if (!grid_sync(G, epoch, bid)) return false;
           SPMV_M(p.Mb, p.w, p.zg);
         } else {
           SPMV_M(p.Mb, vj, p.w);
-          if (!grid_sync(G, epoch)) return;
+          if (!grid_sync(G, epoch, bid)) return false;
           SPMV_A(p.Ap, p.w, p.zg);
         }
         __syncthreads();
@@ -392,7 +390,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
             if (i2 > 0) zr[k] = (VT)fma(-hprev, (double)vprev[k], (double)zr[k]);
             part[0] = fma((double)vcur[k], (double)zr[k], part[0]);
           }
-          if (!grid_reduce<1, false>(G, rtag, part, sh)) return;
+          if (!grid_reduce<1, false>(G, rtag, part, sh, bid)) return false;
           hprev = part[0];
           if (tid == 0) hcol[i2] = hprev;
         }
@@ -401,7 +399,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
           zr[k] = (VT)fma(-hprev, (double)vcur[k], (double)zr[k]);
           nz[0] = fma((double)zr[k], (double)zr[k], nz[0]);
         }
-        if (!grid_reduce<1, false>(G, rtag, nz, sh)) return;
+        if (!grid_reduce<1, false>(G, rtag, nz, sh, bid)) return false;
         const double hn = sqrt(nz[0]);
         VT *vn = p.V + (size_t)(j + 1) * n;
         OWN_ROWS(k, i) { vn[i] = hn > 0.0 ? (VT)((double)zr[k] / hn) : (VT)0; }
@@ -427,7 +425,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
         __syncthreads();
         kdone = j + 1;
         if (s_flag || kdone == m) break;
-        if (!grid_sync(G, epoch)) return;
+        if (!grid_sync(G, epoch, bid)) return false;
       }
       // y = R^{-1} g by one wavefront (column-oriented back substitution)
       if (tid < 64) {
@@ -473,7 +471,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
         for (int c = 0; c < kdone; c++) d = fma((double)p.V[(size_t)c * n + i], y[c], d);
         p.dv[i] = d;
       }
-      if (!grid_sync(G, epoch)) return;
+      if (!grid_sync(G, epoch, bid)) return false;
       bspmv_tile_all<double, double, double>(p.Mb, p.dv, p.dv2, r0, r1, reinterpret_cast<double *>(tprod),
                                              kTileBytes / 8, p.rows_m / 2 > 0 ? p.rows_m / 2 : 1);
       __syncthreads();
@@ -485,8 +483,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
         dn[1] = fmax(dn[1], fabs(xn));
       }
     }
-    if (!grid_reduce<2, true>(G, rtag, dn, sh)) return;
-    if (!grid_sync(G, epoch)) return;  // publish x for the next residual
+    if (!grid_reduce<2, true>(G, rtag, dn, sh, bid)) return false;
+    if (!grid_sync(G, epoch, bid)) return false;  // publish x for the next residual
     const double dx = dn[1] > 0 ? dn[0] / dn[1] : 0.0;
     if (it >= 1 && dx > 0.5 * dx_prev) stag = 1;
     dx_prev = dx;
@@ -500,9 +498,20 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT
     p.stats->stop_reason = reason;
     p.stats->status = status;
   }
+  return true;
 #undef OWN_ROWS
 #undef SPMV_M
 #undef SPMV_A
+}
+
+// one system on the whole grid
+template <typename VT, typename PT, int ZR>
+__global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT> *__restrict__ pp) {
+  extern __shared__ double sm[];
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
+  __shared__ int s_flag;
+  unsigned epoch = 0, rtag = 0;
+  (void)gmres_ir_body<VT, PT, ZR>(*pp, pp->grid, blockIdx.x, epoch, rtag, sm, sh, s_flag);
 }
 
 template <typename VT>
@@ -527,72 +536,56 @@ static Workspace g_ws;
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-template <typename VT>
-static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
-                       gmres_ir_stats *st_host, hipStream_t s) {
-  const int n = A->n;
-  const int64_t nnz = A->nnz;
-  int m = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
-  // about two rows per thread: each MGS pass is bound by the latency of
-  // loading a basis slice and exchanging a partial, not by bandwidth, and more
-  // blocks make every exchange wait for more partials (measured on MI355X at
-  // n = 65,536: 32 blocks 10.5, 64 blocks 13.0, 128 blocks 11.3 solves/s)
-  int G = std::min(kMaxBlocks, std::max(1, (n + 2 * kSolveThreads - 1) / (2 * kSolveThreads)));
-  if (const char *e = getenv("BSPAI_SOLVE_BLOCKS")) G = std::min(kMaxBlocks, std::max(1, atoi(e)));
-  auto rows_for = [&](int g) { return ((n + g - 1) / g + kSlice - 1) / kSlice * kSlice; };  // multiple of 64
-  int rpb = rows_for(G);
-  int zr = (rpb + kSolveThreads - 1) / kSolveThreads;
-  while (zr > 16 && G < kMaxBlocks) {
-    G = std::min(kMaxBlocks, G * 2);
-    rpb = rows_for(G);
-    zr = (rpb + kSolveThreads - 1) / kSolveThreads;
-  }
-  if (zr > 16) return fail(BSPAI_EINVAL, "gmres_ir_solve: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
-  int ZR = 1;
-  while (ZR < zr) ZR <<= 1;
-  G = (n + rpb - 1) / rpb;
-  if (G < 1) G = 1;
+constexpr size_t kSlotBytes = 16 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth;
 
-  // workspace layout
-  const bool tr = tol->trans != 0;
+// device memory of one system's solve, as offsets from a base address
+struct SysLayout {
+  size_t ap, rv, w, zg, V, dv, dv2, flags, abort, slots, stats, params, acol, trp, tcol, tval, total;
+};
+
+template <typename VT>
+static SysLayout sys_layout(int n, int64_t nnz, int m, bool tr) {
+  SysLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off += align256(bytes);
     return o;
   };
-  size_t o_ap = take(sizeof(VT) * (size_t)(nnz + 1));
-  size_t o_rv = take(sizeof(VT) * n), o_w = take(sizeof(VT) * n), o_zg = take(sizeof(VT) * n);
-  size_t o_V = take(sizeof(VT) * (size_t)n * (m + 1));
-  size_t o_dv = take(8 * (size_t)n), o_dv2 = take(8 * (size_t)n);
-  size_t o_flags = take(4 * kMaxBlocks), o_abort = take(4);
-  size_t o_slots = take(16 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth);
-  size_t o_stats = take(sizeof(gmres_ir_stats));
-  size_t o_params = take(sizeof(SolveParams<VT>));
-  size_t o_acol = take(4 * (size_t)(nnz + 1));
-  size_t o_trp = 0, o_tcol = 0, o_tval = 0;
+  L.ap = take(sizeof(VT) * (size_t)(nnz + 1));
+  L.rv = take(sizeof(VT) * n);
+  L.w = take(sizeof(VT) * n);
+  L.zg = take(sizeof(VT) * n);
+  L.V = take(sizeof(VT) * (size_t)n * (m + 1));
+  L.dv = take(8 * (size_t)n);
+  L.dv2 = take(8 * (size_t)n);
+  L.flags = take(4 * kMaxBlocks);
+  L.abort = take(4);
+  L.slots = take(kSlotBytes);
+  L.stats = take(sizeof(gmres_ir_stats));
+  L.params = take(sizeof(SolveParams<VT>));
+  L.acol = take(4 * (size_t)(nnz + 1));
   if (tr) {
-    o_trp = take(4 * ((size_t)n + 1));
-    o_tcol = take(4 * (size_t)(nnz + 1));
-    o_tval = take(8 * (size_t)(nnz + 1));
+    L.trp = take(4 * ((size_t)n + 1));
+    L.tcol = take(4 * (size_t)(nnz + 1));
+    L.tval = take(8 * (size_t)(nnz + 1));
   }
-  std::lock_guard<std::mutex> lock(g_ws.mu);
-  int dev = 0;
-  BSPAI_HIP(hipGetDevice(&dev));
-  if (g_ws.bytes < off || g_ws.device != dev) {
-    if (g_ws.ptr) {
-      (void)hipDeviceSynchronize();
-      dfree(g_ws.ptr);
-      g_ws.ptr = nullptr;
-      g_ws.bytes = 0;
-    }
-    int rc = dalloc(&g_ws.ptr, off);
-    if (rc) return rc;
-    g_ws.bytes = off;
-    g_ws.device = dev;
-  }
-  char *base = static_cast<char *>(g_ws.ptr);
-  SolveParams<VT> p;
+  L.total = off;
+  return L;
+}
+
+static size_t solve_lds(int m) { return sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2) + kTileBytes; }
+
+// Parameters of one system whose workspace starts at `base` (rows split into
+// blocks of rpb rows): A rounded to u_g, A^T and its copy for trans.  `wide`
+// is set when the products need FP64 partials.  Enqueues work on s.
+template <typename VT>
+static int sys_setup(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
+                     int m, int G, int rpb, char *base, const SysLayout &L, SolveParams<VT> &p, bool &wide,
+                     hipStream_t s) {
+  const int n = A->n;
+  const int64_t nnz = A->nnz;
+  const bool tr = tol->trans != 0;
   memset(&p, 0, sizeof(p));
   p.n = n;
   p.G = G;
@@ -601,22 +594,22 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   const int32_t *arp = A->row_ptr, *acol = A->col;
   const double *aval = A->val;
   if (tr) {
-    int32_t *trp = reinterpret_cast<int32_t *>(base + o_trp);
-    int32_t *tcol = reinterpret_cast<int32_t *>(base + o_tcol);
-    double *tval = reinterpret_cast<double *>(base + o_tval);
+    int32_t *trp = reinterpret_cast<int32_t *>(base + L.trp);
+    int32_t *tcol = reinterpret_cast<int32_t *>(base + L.tcol);
+    double *tval = reinterpret_cast<double *>(base + L.tval);
     int rc = csr_transpose(n, nnz, arp, acol, aval, 8, trp, tcol, tval, s);
     if (rc) return rc;
     arp = trp, acol = tcol, aval = tval;
   }
   if (reinterpret_cast<uintptr_t>(acol) & 15) {  // the tile product loads 16-byte column vectors
-    int32_t *ac = reinterpret_cast<int32_t *>(base + o_acol);
+    int32_t *ac = reinterpret_cast<int32_t *>(base + L.acol);
     if (nnz) BSPAI_HIP(hipMemcpyAsync(ac, acol, 4 * (size_t)nnz, hipMemcpyDeviceToDevice, s));
     acol = ac;
   }
   p.a_rp = arp;
   p.a_col = acol;
   p.a_val = aval;
-  VT *apv = reinterpret_cast<VT *>(base + o_ap);
+  VT *apv = reinterpret_cast<VT *>(base + L.ap);
   if (nnz > 0) {
     hipLaunchKernelGGL(k_to_prec<VT>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, aval, apv);
     BSPAI_CHECK_LAUNCH();
@@ -650,25 +643,19 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   p.tol_be = tol->tol_be;
   p.b = b;
   p.x = x;
-  p.rv = reinterpret_cast<VT *>(base + o_rv);
-  p.w = reinterpret_cast<VT *>(base + o_w);
-  p.zg = reinterpret_cast<VT *>(base + o_zg);
-  p.V = reinterpret_cast<VT *>(base + o_V);
-  p.dv = reinterpret_cast<double *>(base + o_dv);
-  p.dv2 = reinterpret_cast<double *>(base + o_dv2);
-  p.grid.flags = reinterpret_cast<unsigned *>(base + o_flags);
-  p.grid.abortf = reinterpret_cast<unsigned *>(base + o_abort);
-  p.grid.slots = reinterpret_cast<double *>(base + o_slots);
+  p.rv = reinterpret_cast<VT *>(base + L.rv);
+  p.w = reinterpret_cast<VT *>(base + L.w);
+  p.zg = reinterpret_cast<VT *>(base + L.zg);
+  p.V = reinterpret_cast<VT *>(base + L.V);
+  p.dv = reinterpret_cast<double *>(base + L.dv);
+  p.dv2 = reinterpret_cast<double *>(base + L.dv2);
+  p.grid.flags = reinterpret_cast<unsigned *>(base + L.flags);
+  p.grid.abortf = reinterpret_cast<unsigned *>(base + L.abort);
+  p.grid.slots = reinterpret_cast<double *>(base + L.slots);
   p.grid.G = G;
-  p.stats = reinterpret_cast<gmres_ir_stats *>(base + o_stats);
-  BSPAI_HIP(hipMemsetAsync(p.grid.flags, 0, 4 * kMaxBlocks, s));
-  BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
-  // tags restart at 1 every launch: clear the exchange words of the last one
-  BSPAI_HIP(hipMemsetAsync(p.grid.slots, 0, 16 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidth, s));
-  BSPAI_HIP(hipMemsetAsync(p.stats, 0, sizeof(gmres_ir_stats), s));
-  bool wide = sizeof(VT) == 8;
+  p.stats = reinterpret_cast<gmres_ir_stats *>(base + L.stats);
+  wide = sizeof(VT) == 8;
   for (int k = 0; k < p.Mb.nb; k++) wide = wide || p.Mb.prec[k] == BSPAI_FP64;
-  size_t lds = sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2) + kTileBytes;
   {
     const int cap = kTileBytes / (wide ? 8 : 4);
     auto rows_for_avg = [&](double avg) {
@@ -678,26 +665,87 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
     p.rows_a = rows_for_avg((double)nnz / n);
     p.rows_m = rows_for_avg((double)p.Mb.nnz / n);
   }
-  void *fn = nullptr;
+  return BSPAI_OK;
+}
+
+// rows per block (a multiple of 64) when n rows are split over g blocks
+static int rows_for(int n, int g) { return ((n + g - 1) / g + kSlice - 1) / kSlice * kSlice; }
+
+template <typename VT>
+static void *pick_single(bool wide, int ZR) {
   if (wide) {
     switch (ZR) {
-      case 1: fn = (void *)k_gmres_ir<VT, double, 1>; break;
-      case 2: fn = (void *)k_gmres_ir<VT, double, 2>; break;
-      case 4: fn = (void *)k_gmres_ir<VT, double, 4>; break;
-      case 8: fn = (void *)k_gmres_ir<VT, double, 8>; break;
-      default: fn = (void *)k_gmres_ir<VT, double, 16>; break;
-    }
-  } else {
-    switch (ZR) {
-      case 1: fn = (void *)k_gmres_ir<VT, float, 1>; break;
-      case 2: fn = (void *)k_gmres_ir<VT, float, 2>; break;
-      case 4: fn = (void *)k_gmres_ir<VT, float, 4>; break;
-      case 8: fn = (void *)k_gmres_ir<VT, float, 8>; break;
-      default: fn = (void *)k_gmres_ir<VT, float, 16>; break;
+      case 1: return (void *)k_gmres_ir<VT, double, 1>;
+      case 2: return (void *)k_gmres_ir<VT, double, 2>;
+      case 4: return (void *)k_gmres_ir<VT, double, 4>;
+      case 8: return (void *)k_gmres_ir<VT, double, 8>;
+      default: return (void *)k_gmres_ir<VT, double, 16>;
     }
   }
+  switch (ZR) {
+    case 1: return (void *)k_gmres_ir<VT, float, 1>;
+    case 2: return (void *)k_gmres_ir<VT, float, 2>;
+    case 4: return (void *)k_gmres_ir<VT, float, 4>;
+    case 8: return (void *)k_gmres_ir<VT, float, 8>;
+    default: return (void *)k_gmres_ir<VT, float, 16>;
+  }
+}
+
+template <typename VT>
+static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
+                       gmres_ir_stats *st_host, hipStream_t s) {
+  const int n = A->n;
+  const int64_t nnz = A->nnz;
+  int m = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
+  // about two rows per thread: each MGS pass is bound by the latency of
+  // loading a basis slice and exchanging a partial, not by bandwidth, and more
+  // blocks make every exchange wait for more partials (measured on MI355X at
+  // n = 65,536: 32 blocks 10.5, 64 blocks 13.0, 128 blocks 11.3 solves/s)
+  int G = std::min(kMaxBlocks, std::max(1, (n + 2 * kSolveThreads - 1) / (2 * kSolveThreads)));
+  if (const char *e = getenv("BSPAI_SOLVE_BLOCKS")) G = std::min(kMaxBlocks, std::max(1, atoi(e)));
+  int rpb = rows_for(n, G);
+  int zr = (rpb + kSolveThreads - 1) / kSolveThreads;
+  while (zr > 16 && G < kMaxBlocks) {
+    G = std::min(kMaxBlocks, G * 2);
+    rpb = rows_for(n, G);
+    zr = (rpb + kSolveThreads - 1) / kSolveThreads;
+  }
+  if (zr > 16) return fail(BSPAI_EINVAL, "gmres_ir_solve: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
+  int ZR = 1;
+  while (ZR < zr) ZR <<= 1;
+  G = (n + rpb - 1) / rpb;
+  if (G < 1) G = 1;
+
+  const SysLayout L = sys_layout<VT>(n, nnz, m, tol->trans != 0);
+  std::lock_guard<std::mutex> lock(g_ws.mu);
+  int dev = 0;
+  BSPAI_HIP(hipGetDevice(&dev));
+  if (g_ws.bytes < L.total || g_ws.device != dev) {
+    if (g_ws.ptr) {
+      (void)hipDeviceSynchronize();
+      dfree(g_ws.ptr);
+      g_ws.ptr = nullptr;
+      g_ws.bytes = 0;
+    }
+    int rc = dalloc(&g_ws.ptr, L.total);
+    if (rc) return rc;
+    g_ws.bytes = L.total;
+    g_ws.device = dev;
+  }
+  char *base = static_cast<char *>(g_ws.ptr);
+  SolveParams<VT> p;
+  bool wide = false;
+  int rc = sys_setup<VT>(A, b, M, tol, x, m, G, rpb, base, L, p, wide, s);
+  if (rc) return rc;
+  BSPAI_HIP(hipMemsetAsync(p.grid.flags, 0, 4 * kMaxBlocks, s));
+  BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
+  // tags restart at 1 every launch: clear the exchange words of the last one
+  BSPAI_HIP(hipMemsetAsync(p.grid.slots, 0, kSlotBytes, s));
+  BSPAI_HIP(hipMemsetAsync(p.stats, 0, sizeof(gmres_ir_stats), s));
+  const size_t lds = solve_lds(m);
+  void *fn = pick_single<VT>(wide, ZR);
   BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  SolveParams<VT> *pdev = reinterpret_cast<SolveParams<VT> *>(base + o_params);
+  SolveParams<VT> *pdev = reinterpret_cast<SolveParams<VT> *>(base + L.params);
   BSPAI_HIP(hipMemcpyAsync(pdev, &p, sizeof(p), hipMemcpyHostToDevice, s));
   void *args[] = {&pdev};
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -728,6 +776,264 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   return hs.status;
 }
 
+// ------------------------------------------------------------------ many systems
+
+// Several independent systems in one persistent launch.  The grid is cut into
+// groups of group_blocks blocks; each group takes the next system off a device
+// queue (largest systems first), solves it with the single-system body on its
+// own barrier and exchange words, and goes back to the queue until it is
+// empty.  Results do not depend on which group solves a system: every group
+// has the same size, so the row split and the reduction order of a system are
+// fixed by the plan.
+template <typename VT>
+struct MultiParams {
+  const SolveParams<VT> *sys;  // [nsys]
+  const int *order;            // queue position -> system
+  const Grid *grids;           // [ngroups]
+  unsigned *queue;             // next queue position (cleared per launch)
+  unsigned *groups_done;       // groups that have left the queue (cleared per launch)
+  const unsigned *seq;         // launches so far (advanced by the clear kernel)
+  unsigned *done_host;         // host word: seq of the last launch that has finished
+  int nsys, group_blocks, ngroups;
+};
+
+template <typename VT, typename PT, int ZR>
+__global__ void __launch_bounds__(kSolveThreads) k_gmres_multi(const MultiParams<VT> *__restrict__ mp) {
+  extern __shared__ double sm[];
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
+  __shared__ int s_flag;
+  const int group = blockIdx.x / mp->group_blocks, bid = blockIdx.x % mp->group_blocks;
+  const Grid G = mp->grids[group];
+  unsigned epoch = 0, rtag = 0;
+  for (;;) {
+    // the group's first block takes a queue position; the all-reduction (max
+    // of it and zeros) hands it to every block of the group
+    double q[1] = {0.0};
+    if (bid == 0 && threadIdx.x == 0) q[0] = (double)atomicAdd(mp->queue, 1u);
+    if (!grid_reduce<1, true>(G, rtag, q, sh, bid)) break;
+    const int k = (int)q[0];
+    if (k >= mp->nsys) break;
+    if (!gmres_ir_body<VT, PT, ZR>(mp->sys[mp->order[k]], G, bid, epoch, rtag, sm, sh, s_flag)) break;
+  }
+  if (bid == 0 && threadIdx.x == 0) {
+    unsigned d = atomicAdd(mp->groups_done, 1u);
+    if (d + 1 == (unsigned)mp->ngroups)
+      __hip_atomic_store(mp->done_host, *mp->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// zero the per-launch state (a kernel, not a memset node, so that graph
+// replays clear it reliably) and advance the launch counter
+__global__ void k_multi_clear(unsigned *words, int64_t nwords, unsigned *seq) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x)
+    words[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *seq += 1u;
+}
+
+template <typename VT>
+static void *pick_multi(bool wide, int ZR) {
+  if (wide) {
+    switch (ZR) {
+      case 1: return (void *)k_gmres_multi<VT, double, 1>;
+      case 2: return (void *)k_gmres_multi<VT, double, 2>;
+      case 4: return (void *)k_gmres_multi<VT, double, 4>;
+      case 8: return (void *)k_gmres_multi<VT, double, 8>;
+      default: return (void *)k_gmres_multi<VT, double, 16>;
+    }
+  }
+  switch (ZR) {
+    case 1: return (void *)k_gmres_multi<VT, float, 1>;
+    case 2: return (void *)k_gmres_multi<VT, float, 2>;
+    case 4: return (void *)k_gmres_multi<VT, float, 4>;
+    case 8: return (void *)k_gmres_multi<VT, float, 8>;
+    default: return (void *)k_gmres_multi<VT, float, 16>;
+  }
+}
+
+}  // namespace bspai
+
+struct bspai_multi {
+  int nsys = 0, ngroups = 0, group_blocks = 0, device = 0;
+  void *mem = nullptr;             // every system's workspace, the parameters and the per-launch state
+  unsigned *done_host = nullptr;   // pinned host word
+  unsigned launches = 0;
+  gmres_ir_stats *stats = nullptr; // [nsys], device
+  unsigned *aborts = nullptr;      // [ngroups], device
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace bspai {
+
+static void multi_release(bspai_multi *P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->mem) {
+    (void)hipDeviceSynchronize();
+    dfree(P->mem);
+  }
+  if (P->done_host) (void)hipHostFree(P->done_host);
+  delete P;
+}
+
+template <typename VT>
+static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_tol *tol, int group_blocks,
+                            int max_groups, bspai_multi **out, hipStream_t s) {
+  const bool tr = tol->trans != 0;
+  int nmax = 0;
+  for (int k = 0; k < nsys; k++) nmax = std::max(nmax, sys[k].A.n);
+  // smallest group that keeps every system within 16 rows per thread
+  const int gmin = (nmax + kSolveThreads * 16 - 1) / (kSolveThreads * 16);
+  int gb = group_blocks > 0 ? group_blocks : gmin;
+  if (gb < gmin || gb > kMaxBlocks)
+    return fail(BSPAI_EINVAL, "bspai_multi_plan: group_blocks must be in %d..%d for n up to %d", gmin, kMaxBlocks,
+                nmax);
+  int ZR = 1, mmax = 1;
+  std::vector<int> ms(nsys), rpbs(nsys);
+  bool wide = sizeof(VT) == 8;
+  for (int k = 0; k < nsys; k++) {
+    const int n = sys[k].A.n;
+    ms[k] = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
+    mmax = std::max(mmax, ms[k]);
+    rpbs[k] = rows_for(n, gb);
+    while (ZR * kSolveThreads < rpbs[k]) ZR <<= 1;
+    const BMat &Mb = tr ? sys[k].M->matT : sys[k].M->mat;
+    for (int q = 0; q < Mb.nb; q++) wide = wide || Mb.prec[q] == BSPAI_FP64;
+  }
+  const size_t lds = solve_lds(mmax);
+  void *fn = pick_multi<VT>(wide, ZR);
+  BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  BSPAI_HIP(hipGetDevice(&dev));
+  BSPAI_HIP(hipGetDeviceProperties(&prop, dev));
+  BSPAI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSolveThreads, lds));
+  // every block of the grid must be resident at once (the groups wait on each other's blocks)
+  const int resident = per_cu * prop.multiProcessorCount;
+  int ng = std::min(nsys, resident / gb);
+  if (max_groups > 0) ng = std::min(ng, max_groups);
+  if (ng < 1) return fail(BSPAI_EINVAL, "bspai_multi_plan: a group of %d blocks does not fit on the device", gb);
+
+  // memory: per-system workspaces, parameters, then the per-launch state
+  std::vector<SysLayout> L(nsys);
+  std::vector<size_t> base(nsys);
+  size_t off = 0;
+  for (int k = 0; k < nsys; k++) {
+    L[k] = sys_layout<VT>(sys[k].A.n, sys[k].A.nnz, ms[k], tr);
+    base[k] = off;
+    off += L[k].total;
+  }
+  const size_t o_params = off;
+  off += align256(sizeof(SolveParams<VT>) * nsys);
+  const size_t o_order = off;
+  off += align256(4 * (size_t)nsys);
+  const size_t o_grids = off;
+  off += align256(sizeof(Grid) * ng);
+  const size_t o_mp = off;
+  off += align256(sizeof(MultiParams<VT>));
+  const size_t o_seq = off;
+  off += 256;
+  // per-launch state, cleared by k_multi_clear: queue, groups_done, aborts, stats, flags, slots
+  const size_t o_state = off;
+  const size_t o_queue = off;
+  off += 256;
+  const size_t o_aborts = off;
+  off += align256(4 * (size_t)ng);
+  const size_t o_stats = off;
+  off += align256(sizeof(gmres_ir_stats) * nsys);
+  const size_t o_flags = off;
+  off += align256(4 * (size_t)kMaxBlocks * ng);
+  const size_t o_slots = off;
+  off += kSlotBytes * ng;
+  const size_t state_bytes = off - o_state;
+
+  bspai_multi *P = new bspai_multi;
+  P->nsys = nsys;
+  P->ngroups = ng;
+  P->group_blocks = gb;
+  P->device = dev;
+  int rc = dalloc(&P->mem, off);
+  if (rc) {
+    multi_release(P);
+    return rc;
+  }
+  char *mem = static_cast<char *>(P->mem);
+  auto bail = [&](int code) {
+    multi_release(P);
+    return code;
+  };
+  if (hipHostMalloc((void **)&P->done_host, 4, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess)
+    return bail(fail(BSPAI_EHIP, "bspai_multi_plan: hipHostMalloc failed"));
+  *P->done_host = 0u;
+  unsigned *done_dev = nullptr;
+  if (hipHostGetDevicePointer((void **)&done_dev, P->done_host, 0) != hipSuccess)
+    return bail(fail(BSPAI_EHIP, "bspai_multi_plan: hipHostGetDevicePointer failed"));
+
+  std::vector<SolveParams<VT>> ps(nsys);
+  gmres_ir_stats *stats = reinterpret_cast<gmres_ir_stats *>(mem + o_stats);
+  for (int k = 0; k < nsys; k++) {
+    bool w = false;
+    rc = sys_setup<VT>(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, ms[k], gb, rpbs[k], mem + base[k], L[k], ps[k],
+                       w, s);
+    if (rc) return bail(rc);
+    ps[k].stats = stats + k;
+  }
+  std::vector<int> order(nsys);
+  for (int k = 0; k < nsys; k++) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sys[a].A.n > sys[b].A.n; });
+  std::vector<Grid> grids(ng);
+  unsigned *aborts = reinterpret_cast<unsigned *>(mem + o_aborts);
+  for (int g = 0; g < ng; g++) {
+    grids[g].flags = reinterpret_cast<unsigned *>(mem + o_flags) + (size_t)kMaxBlocks * g;
+    grids[g].abortf = aborts + g;
+    grids[g].slots = reinterpret_cast<double *>(mem + o_slots + kSlotBytes * g);
+    grids[g].G = gb;
+  }
+  MultiParams<VT> mp;
+  memset(&mp, 0, sizeof(mp));
+  mp.sys = reinterpret_cast<const SolveParams<VT> *>(mem + o_params);
+  mp.order = reinterpret_cast<const int *>(mem + o_order);
+  mp.grids = reinterpret_cast<const Grid *>(mem + o_grids);
+  mp.queue = reinterpret_cast<unsigned *>(mem + o_queue);
+  mp.groups_done = mp.queue + 1;
+  mp.seq = reinterpret_cast<const unsigned *>(mem + o_seq);
+  mp.done_host = done_dev;
+  mp.nsys = nsys;
+  mp.group_blocks = gb;
+  mp.ngroups = ng;
+  // pageable host copies: synchronise before the vectors go out of scope
+  if (hipMemcpyAsync(mem + o_params, ps.data(), sizeof(SolveParams<VT>) * nsys, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_order, order.data(), 4 * (size_t)nsys, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_grids, grids.data(), sizeof(Grid) * ng, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_mp, &mp, sizeof(mp), hipMemcpyHostToDevice, s) ||
+      hipMemsetAsync(mem + o_seq, 0, 4, s) || hipStreamSynchronize(s))
+    return bail(fail(BSPAI_EHIP, "bspai_multi_plan: setting up the parameters failed"));
+  P->stats = stats;
+  P->aborts = aborts;
+
+  // capture clear + solve into a graph on a private stream
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(BSPAI_EHIP, "bspai_multi_plan: stream creation failed"));
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const int64_t nwords = (int64_t)(state_bytes / 4);
+    hipLaunchKernelGGL(k_multi_clear, dim3(256), dim3(256), 0, cs, reinterpret_cast<unsigned *>(mem + o_state),
+                       nwords, reinterpret_cast<unsigned *>(mem + o_seq));
+    const MultiParams<VT> *mpd = reinterpret_cast<const MultiParams<VT> *>(mem + o_mp);
+    void *args[] = {&mpd};
+    hipError_t el = hipLaunchKernel(fn, dim3(gb * ng), dim3(kSolveThreads), args, lds, cs);
+    hipError_t ee = hipStreamEndCapture(cs, &P->graph);
+    e = el != hipSuccess ? el : ee;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) return bail(fail(BSPAI_EHIP, "bspai_multi_plan: graph capture failed: %s", hipGetErrorString(e)));
+  *out = P;
+  return BSPAI_OK;
+}
+
 }  // namespace bspai
 
 using namespace bspai;
@@ -735,22 +1041,82 @@ using namespace bspai;
 extern "C" void bspai_set_profiling(int on) { g_profile = on ? 1 : 0; }
 extern "C" double bspai_last_solve_kernel_ms(void) { return g_last_ms; }
 
-extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
-                              double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
-  if (!A || !M || !tol) return fail(BSPAI_EINVAL, "gmres_ir_solve: null argument");
-  if (A->n != M->n) return fail(BSPAI_EINVAL, "gmres_ir_solve: A is %d x %d but M is %d x %d", A->n, A->n, M->n, M->n);
-  if (A->n < 1) return fail(BSPAI_EINVAL, "gmres_ir_solve: empty system");
+static int check_system(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
+                        const double *x, const char *who) {
+  if (!A || !M || !tol) return fail(BSPAI_EINVAL, "%s: null argument", who);
+  if (A->n != M->n) return fail(BSPAI_EINVAL, "%s: A is %d x %d but M is %d x %d", who, A->n, A->n, M->n, M->n);
+  if (A->n < 1) return fail(BSPAI_EINVAL, "%s: empty system", who);
   if (!A->row_ptr || (A->nnz > 0 && (!A->col || !A->val)) || !b || !x)
-    return fail(BSPAI_EINVAL, "gmres_ir_solve: null device pointer");
-  if (nrhs < 1 || nrhs > 64) return fail(BSPAI_EINVAL, "gmres_ir_solve: nrhs must be in 1..64 (got %d)", nrhs);
-  if (tol->u_g != BSPAI_FP32 && tol->u_g != BSPAI_FP64) return fail(BSPAI_EINVAL, "gmres_ir_solve: u_g must be FP32 or FP64");
-  if (tol->x0_mode < 0 || tol->x0_mode > 3) return fail(BSPAI_EINVAL, "gmres_ir_solve: x0_mode must be 0..3");
-  if (tol->i_max < 0) return fail(BSPAI_EINVAL, "gmres_ir_solve: i_max < 0");
-  if (tol->trans && !M->has_T) return fail(BSPAI_EINVAL, "gmres_ir_solve: trans needs a handle built with build_T");
-  if (tol->x0_mode == 0 && !M->has_fp64) return fail(BSPAI_EINVAL, "gmres_ir_solve: x0_mode 0 needs keep_fp64_M");
+    return fail(BSPAI_EINVAL, "%s: null device pointer", who);
+  if (tol->u_g != BSPAI_FP32 && tol->u_g != BSPAI_FP64) return fail(BSPAI_EINVAL, "%s: u_g must be FP32 or FP64", who);
+  if (tol->x0_mode < 0 || tol->x0_mode > 3) return fail(BSPAI_EINVAL, "%s: x0_mode must be 0..3", who);
+  if (tol->i_max < 0) return fail(BSPAI_EINVAL, "%s: i_max < 0", who);
+  if (tol->trans && !M->has_T) return fail(BSPAI_EINVAL, "%s: trans needs a handle built with build_T", who);
+  if (tol->x0_mode == 0 && !M->has_fp64) return fail(BSPAI_EINVAL, "%s: x0_mode 0 needs keep_fp64_M", who);
   int dev = 0;
   BSPAI_HIP(hipGetDevice(&dev));
-  if (dev != M->device) return fail(BSPAI_EINVAL, "gmres_ir_solve: handle lives on device %d", M->device);
+  if (dev != M->device) return fail(BSPAI_EINVAL, "%s: handle lives on device %d", who, M->device);
+  return BSPAI_OK;
+}
+
+extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_ir_tol *tol, int group_blocks,
+                                int max_groups, bspai_multi **plan_out, void *stream) {
+  if (!plan_out) return fail(BSPAI_EINVAL, "bspai_multi_plan: null plan_out");
+  *plan_out = nullptr;
+  if (!sys || nsys < 1 || !tol) return fail(BSPAI_EINVAL, "bspai_multi_plan: need at least one system and tolerances");
+  if (group_blocks < 0 || max_groups < 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: negative group size or count");
+  for (int k = 0; k < nsys; k++) {
+    int rc = check_system(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, "bspai_multi_plan");
+    if (rc) return rc;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (tol->u_g == BSPAI_FP64) return multi_plan_typed<double>(sys, nsys, tol, group_blocks, max_groups, plan_out, s);
+  return multi_plan_typed<float>(sys, nsys, tol, group_blocks, max_groups, plan_out, s);
+}
+
+extern "C" int bspai_multi_launch(bspai_multi *plan, void *stream) {
+  if (!plan || !plan->exec) return fail(BSPAI_EINVAL, "bspai_multi_launch: no plan");
+  int dev = 0;
+  BSPAI_HIP(hipGetDevice(&dev));
+  if (dev != plan->device) return fail(BSPAI_EINVAL, "bspai_multi_launch: plan lives on device %d", plan->device);
+  BSPAI_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+  plan->launches++;
+  return BSPAI_OK;
+}
+
+extern "C" int bspai_multi_poll(const bspai_multi *plan) {
+  if (!plan) return fail(BSPAI_EINVAL, "bspai_multi_poll: no plan");
+  return __atomic_load_n(plan->done_host, __ATOMIC_ACQUIRE) == plan->launches ? 1 : 0;
+}
+
+extern "C" int bspai_multi_wait(bspai_multi *plan, gmres_ir_stats *st_host, void *stream) {
+  if (!plan) return fail(BSPAI_EINVAL, "bspai_multi_wait: no plan");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<gmres_ir_stats> st(plan->nsys);
+  std::vector<unsigned> ab(plan->ngroups);
+  BSPAI_HIP(hipMemcpyAsync(st.data(), plan->stats, sizeof(gmres_ir_stats) * plan->nsys, hipMemcpyDeviceToHost, s));
+  BSPAI_HIP(hipMemcpyAsync(ab.data(), plan->aborts, 4 * (size_t)plan->ngroups, hipMemcpyDeviceToHost, s));
+  BSPAI_HIP(hipStreamSynchronize(s));
+  if (st_host) memcpy(st_host, st.data(), sizeof(gmres_ir_stats) * plan->nsys);
+  for (unsigned a : ab)
+    if (a) return fail(BSPAI_EHIP, "bspai_multi_wait: a group's synchronisation timed out");
+  int worst = BSPAI_OK;
+  for (const auto &q : st) {
+    if (q.status == BSPAI_ENAN) worst = BSPAI_ENAN;
+    else if (q.status == BSPAI_ENOCONV && worst == BSPAI_OK) worst = BSPAI_ENOCONV;
+  }
+  if (worst == BSPAI_ENOCONV) return fail(BSPAI_ENOCONV, "bspai_multi_wait: some system reached i_max");
+  if (worst == BSPAI_ENAN) return fail(BSPAI_ENAN, "bspai_multi_wait: NaN or infinity in a residual");
+  return BSPAI_OK;
+}
+
+extern "C" void bspai_multi_free(bspai_multi *plan) { multi_release(plan); }
+
+extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
+                              double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
+  if (nrhs < 1 || nrhs > 64) return fail(BSPAI_EINVAL, "gmres_ir_solve: nrhs must be in 1..64 (got %d)", nrhs);
+  int rc = check_system(A, b, M, tol, x, "gmres_ir_solve");
+  if (rc) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (nrhs > 1) {
     const int m = std::min(std::max(tol->gmres_max, 1), std::min(A->n, kMaxGmres));

@@ -392,6 +392,98 @@ def test_solve_batched_adjoint(B):
     h.free()
 
 
+def _multi_systems(B, c, eps):
+    out = []
+    for sy in c["systems"]:
+        Ad = B.CSRMatrix.from_host(sy["A"])
+        h = B.build(Ad, B.CSRMatrix.from_host(sy["P"]), eps=eps, precs=c["precs"])
+        out.append((Ad, _dev(sy["b"]), h))
+    return out
+
+
+def test_multi_system_matches_oracle_and_replays(B):
+    """Uneven systems in one persistent launch from a captured graph: each
+    against the oracle, and a replay gives the same bits."""
+    import torch
+
+    c = W.config("4b", small=True)
+    eps = c["eps"][0]
+    _say("multi-system", [sy["A"].n for sy in c["systems"]])
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    systems = _multi_systems(B, c, eps)
+    plan = B.MultiPlan(systems, **kw)
+    plan.launch()
+    sts = plan.wait()
+    assert plan.poll()
+    xs = [x.cpu().numpy().copy() for x in plan.x]
+    for k, sy in enumerate(c["systems"]):
+        A, P, b = sy["A"], sy["P"], sy["b"]
+        M = _spai_oracle(A, P)
+        ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, **kw)
+        _check_column(sts[k], ref, O.backward_error(A, b, xs[k]))
+    for x in plan.x:
+        x.fill_(float("nan"))
+    plan.launch()
+    plan.launch()
+    sts2 = plan.wait()
+    assert sts2 == sts
+    for k in range(len(xs)):
+        assert np.array_equal(plan.x[k].cpu().numpy(), xs[k])
+    torch.cuda.synchronize()
+    plan.free()
+    for _, _, h in systems:
+        h.free()
+
+
+def test_multi_system_queue_is_deterministic(B):
+    """More systems than groups (the queue hands out several systems per
+    group): the bits depend on the group size only, not on how many groups
+    share the queue."""
+    c = W.config("4b", small=True)
+    eps = c["eps"][0]
+    _say("multi-system queue")
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    systems = _multi_systems(B, c, eps)
+    res = []
+    for ng in (1, 2, 4):
+        sys_k = [(A, b, h, None) for A, b, h in systems]
+        plan = B.MultiPlan(sys_k, group_blocks=3, max_groups=ng, **kw)
+        plan.launch()
+        sts = plan.wait()
+        res.append((sts, [x.cpu().numpy() for x in plan.x]))
+        plan.free()
+    for sts, xs in res[1:]:
+        assert sts == res[0][0]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, res[0][1]))
+    for k, sy in enumerate(c["systems"]):
+        assert res[0][0][k]["status"] == 0
+        assert O.backward_error(sy["A"], sy["b"], res[0][1][k]) <= 1e-10
+    for _, _, h in systems:
+        h.free()
+
+
+def test_multi_system_adjoint_fp64(B):
+    """trans = 1 and FP64 working precision through the multi-system path."""
+    c = W.config("4b", small=True)
+    _say("multi-system adjoint fp64")
+    systems = []
+    for sy in c["systems"][:3]:
+        Ad = B.CSRMatrix.from_host(sy["A"])
+        h = B.build(Ad, B.CSRMatrix.from_host(sy["P"]), eps=2.0 ** -53, precs=["fp64"])
+        systems.append((Ad, _dev(sy["b"]), h))
+    plan = B.MultiPlan(systems, u_g="fp64", tau=1e-8, tol_rr=1e-12, trans=True)
+    plan.launch()
+    sts = plan.wait()
+    for k, sy in enumerate(c["systems"][:3]):
+        lam = plan.x[k].cpu().numpy()
+        ref = np.linalg.solve(sy["A"].dense().T, sy["b"])
+        assert sts[k]["status"] == 0
+        assert np.abs(lam - ref).max() <= 1e-9 * np.abs(ref).max()
+    plan.free()
+    for _, _, h in systems:
+        h.free()
+
+
 def test_solve_fp64_working_precision(B):
     c = W.config("2", small=True)
     _say("solve fp64")
