@@ -46,13 +46,14 @@ _i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
 
 
 class GmresOpts(C.Structure):
-    _fields_ = [("ug", C.c_int), ("up", C.c_int), ("tau", C.c_double), ("max_it", C.c_int), ("trans", C.c_int)]
+    _fields_ = [("ug", C.c_int), ("up", C.c_int), ("tau", C.c_double), ("max_it", C.c_int), ("trans", C.c_int),
+                ("dot64", C.c_int)]
 
 
 class IROpts(C.Structure):
     _fields_ = [("ug", C.c_int), ("up", C.c_int), ("ur_dd", C.c_int), ("tau", C.c_double),
                 ("tol_rr", C.c_double), ("tol_be", C.c_double), ("i_max", C.c_int),
-                ("gmres_max", C.c_int), ("x0_mode", C.c_int), ("trans", C.c_int)]
+                ("gmres_max", C.c_int), ("x0_mode", C.c_int), ("trans", C.c_int), ("dot64", C.c_int)]
 
 
 class IRStats(C.Structure):
@@ -277,11 +278,13 @@ def backward_error(A, b, x, dd: bool = True) -> float:
 # ---------------------------------------------------------------- Krylov
 
 def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32, max_it: Optional[int] = None,
-          trans: bool = False, want_basis: bool = False) -> Dict:
-    """One preconditioned MGS-GMRES solve (left: M A d = M r; trans: A^T M^T)."""
+          trans: bool = False, want_basis: bool = False, dot64: bool = False) -> Dict:
+    """One preconditioned MGS-GMRES solve (left: M A d = M r; trans: A^T M^T).
+    dot64: dots and norms accumulated in FP64 over u_g data (the default sums
+    sequentially in u_g)."""
     n = A.n
     m = min(n, max_it if max_it is not None else n)
-    o = GmresOpts(ug, up, float(tau), m, int(trans))
+    o = GmresOpts(ug, up, float(tau), m, int(trans), int(dot64))
     d = np.zeros(n)
     its = C.c_int(0)
     rel = C.c_double(0)
@@ -308,12 +311,13 @@ def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32,
 
 def gmres_ir(A, M, Mb: Bucketed, b, ug: int = FP32, up: int = FP32, ur_dd: bool = True, tau: float = 1e-4,
              tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: Optional[int] = None,
-             x0_mode: int = 0, trans: bool = False) -> Dict:
-    """BSPAI-GMRES-IR (Algorithm 4).  M: FP64 SPAI as workloads.CSR (for x_0)."""
+             x0_mode: int = 0, trans: bool = False, dot64: bool = False) -> Dict:
+    """BSPAI-GMRES-IR (Algorithm 4).  M: FP64 SPAI as workloads.CSR (for x_0).
+    dot64 as in :func:`gmres`."""
     n = A.n
     gm = min(n, gmres_max if gmres_max is not None else n)
     o = IROpts(ug, up, int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), gm, int(x0_mode),
-               int(trans))
+               int(trans), int(dot64))
     st = IRStats()
     x = np.zeros(n)
     if trans:

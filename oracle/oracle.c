@@ -548,6 +548,14 @@ static double vec_norm_inf(int n, const double *x) {
  * sequential.  The Hessenberg matrix, Givens rotations and the projected
  * right-hand side are FP64; d = V y is formed in FP64.
  *
+ * dot64 = 1 selects the other realisation of "vector operations in u_g" that
+ * keeps the vectors in u_g: each dot product and squared norm is a sum of the
+ * (exact) products of u_g numbers accumulated in FP64, h_ij, beta and
+ * h_{j+1,j} stay FP64, and each axpy z - h v is formed with one FMA in FP64
+ * and then rounded to u_g.  Sequential recursive summation in u_g has an
+ * error bound growing with n u_g; this one stays near u_g, which is what a
+ * reduction over FP64 partials gives.
+ *
  * Left preconditioning (trans = 0): solves M A d = M r,  stop when
  * |g_{j+1}| <= tau ||M r||_2.
  * Right preconditioning on the transposed system (trans = 1, used by the
@@ -564,6 +572,7 @@ typedef struct {
     double tau;       /* relative tolerance */
     int max_it;       /* iteration cap (<= n) */
     int trans;        /* 0: left-preconditioned M A, 1: right-preconditioned A^T M^T */
+    int dot64;        /* 1: dots and norms accumulated in FP64 (see above) */
 } orc_gmres_opts;
 
 static inline double wp(int prec, double x) {
@@ -597,9 +606,14 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
     } else {
         for (int i = 0; i < n; i++) s[i] = rr[i];
     }
+    const int d64 = o->dot64;
     double acc = 0;
-    for (int i = 0; i < n; i++) acc = wp(ug, acc + wp(ug, s[i] * s[i]));
-    double beta = wp(ug, sqrt(acc));
+    if (d64) {
+        for (int i = 0; i < n; i++) acc += s[i] * s[i];
+    } else {
+        for (int i = 0; i < n; i++) acc = wp(ug, acc + wp(ug, s[i] * s[i]));
+    }
+    double beta = d64 ? sqrt(acc) : wp(ug, sqrt(acc));
     for (int i = 0; i < n; i++) d[i] = 0.0;
     if (beta == 0.0) {
         *its_out = 0;
@@ -624,13 +638,23 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
         for (int i = 0; i <= j; i++) {                             /* modified Gram-Schmidt */
             const double *vi = V + (size_t)i * n;
             double h = 0;
-            for (int l = 0; l < n; l++) h = wp(ug, h + wp(ug, vi[l] * z[l]));
-            hj[i] = h;
-            for (int l = 0; l < n; l++) z[l] = wp(ug, z[l] - wp(ug, h * vi[l]));
+            if (d64) {
+                for (int l = 0; l < n; l++) h += vi[l] * z[l];
+                hj[i] = h;
+                for (int l = 0; l < n; l++) z[l] = wp(ug, fma(-h, vi[l], z[l]));
+            } else {
+                for (int l = 0; l < n; l++) h = wp(ug, h + wp(ug, vi[l] * z[l]));
+                hj[i] = h;
+                for (int l = 0; l < n; l++) z[l] = wp(ug, z[l] - wp(ug, h * vi[l]));
+            }
         }
         acc = 0;
-        for (int l = 0; l < n; l++) acc = wp(ug, acc + wp(ug, z[l] * z[l]));
-        double hn = wp(ug, sqrt(acc));
+        if (d64) {
+            for (int l = 0; l < n; l++) acc += z[l] * z[l];
+        } else {
+            for (int l = 0; l < n; l++) acc = wp(ug, acc + wp(ug, z[l] * z[l]));
+        }
+        double hn = d64 ? sqrt(acc) : wp(ug, sqrt(acc));
         hj[j + 1] = hn;
         if (H_out) for (int i = 0; i <= j + 1; i++) H_out[(size_t)j * ld + i] = hj[i];
         if (hn != 0.0) {
@@ -701,6 +725,7 @@ typedef struct {
     int ug, up, ur_dd;
     double tau, tol_rr, tol_be;
     int i_max, gmres_max, x0_mode, trans;
+    int dot64;  /* GMRES dot products accumulated in FP64 (orc_gmres) */
 } orc_ir_opts;
 
 typedef struct {
@@ -728,7 +753,7 @@ int orc_gmres_ir(int n, const int *rp, const int *ci, const double *v,
     } else {
         for (int i = 0; i < n; i++) x[i] = 0.0;
     }
-    orc_gmres_opts go = {o->ug, o->up, o->tau, o->gmres_max, o->trans};
+    orc_gmres_opts go = {o->ug, o->up, o->tau, o->gmres_max, o->trans, o->dot64};
     int status = ORC_OK, stagnated = 0;
     double dx_prev = 0;
     int i = 0;

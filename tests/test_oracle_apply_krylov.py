@@ -156,36 +156,39 @@ def test_residual_against_exact_rationals(orc, dd):
 
 # ---------------------------------------------------------------- GMRES
 
-def test_gmres_terminates_within_n_steps_in_fp64(orc):
+@pytest.mark.parametrize("dot64", [False, True])
+def test_gmres_terminates_within_n_steps_in_fp64(orc, dot64):
     rng = np.random.default_rng(47)
     n = 12
     A = W.random_sparse(n, 0.3, rng, dominance=0.3)
     Mb = O.Bucketed(W.from_dense(np.eye(n)), 1e-3, [O.FP64])
     r = rng.standard_normal(n)
-    res = orc.gmres(A, Mb, r, tau=0.0, ug=O.FP64, up=O.FP64)
+    res = orc.gmres(A, Mb, r, tau=0.0, ug=O.FP64, up=O.FP64, dot64=dot64)
     assert res["its"] <= n
     d_ref = np.linalg.solve(A.dense(), r)
     assert np.allclose(res["d"], d_ref, rtol=1e-9, atol=1e-10 * np.abs(d_ref).max())
 
 
-def test_gmres_distinct_eigenvalues_bound(orc):
+@pytest.mark.parametrize("dot64", [False, True])
+def test_gmres_distinct_eigenvalues_bound(orc, dot64):
     # M = I and A diagonal with 3 distinct values: the Krylov space of any
     # vector has dimension <= 3, so GMRES is exact after 3 steps.
     vals = np.array([1.0, 2.0, 5.0] * 10)
     A = W.from_dense(np.diag(vals))
     Mb = O.Bucketed(W.from_dense(np.eye(30)), 1e-3, [O.FP64])
     r = np.random.default_rng(48).standard_normal(30)
-    res = orc.gmres(A, Mb, r, tau=1e-12, ug=O.FP64, up=O.FP64)
+    res = orc.gmres(A, Mb, r, tau=1e-12, ug=O.FP64, up=O.FP64, dot64=dot64)
     assert res["its"] == 3
     assert np.allclose(res["d"], r / vals, rtol=1e-12)
 
 
-def test_arnoldi_relation_and_orthogonality(orc):
+@pytest.mark.parametrize("dot64", [False, True])
+def test_arnoldi_relation_and_orthogonality(orc, dot64):
     # M A V_k = V_{k+1} H_k with orthonormal V (MGS, FP64)
     A, M, rng = _random_spai(49, n=50)
     Mb = O.Bucketed(M, 1e-3, [O.FP64])
     r = rng.standard_normal(50)
-    res = orc.gmres(A, Mb, r, tau=1e-10, ug=O.FP64, up=O.FP64, want_basis=True)
+    res = orc.gmres(A, Mb, r, tau=1e-10, ug=O.FP64, up=O.FP64, want_basis=True, dot64=dot64)
     V, H = res["V"], res["H"]
     k = res["its"]
     MA = M.dense() @ A.dense()
@@ -198,13 +201,57 @@ def test_arnoldi_relation_and_orthogonality(orc):
     assert np.abs(V.T @ V - np.eye(k + 1)).max() <= 1e-3
 
 
-def test_gmres_matches_dense_preconditioned_solve(orc):
+@pytest.mark.parametrize("dot64", [False, True])
+def test_gmres_matches_dense_preconditioned_solve(orc, dot64):
     A, M, rng = _random_spai(50, n=60)
     Mb = O.Bucketed(M, 1e-3, [O.FP64])
     r = rng.standard_normal(60)
-    res = orc.gmres(A, Mb, r, tau=1e-13, ug=O.FP64, up=O.FP64)
+    res = orc.gmres(A, Mb, r, tau=1e-13, ug=O.FP64, up=O.FP64, dot64=dot64)
     d = np.linalg.solve(A.dense(), r)
     assert np.allclose(res["d"], d, rtol=1e-9, atol=1e-11 * np.abs(d).max())
+
+
+def _ulp32_close(a, b):
+    a32, b32 = a.astype(np.float32), b.astype(np.float32)
+    assert np.array_equal(a32.astype(np.float64), a) and np.array_equal(b32.astype(np.float64), b)
+    return np.abs(a - b).max() <= np.spacing(np.abs(b32)).max()
+
+
+@pytest.mark.parametrize("dot64", [False, True])
+def test_fp32_first_arnoldi_step_by_hand(orc, dot64):
+    """First Arnoldi step of fp32 GMRES recomputed with numpy from the pinned
+    apply and A_p products: v_1 = fl32(s / beta), z = fl32(M_b fl32(A_p v_1)),
+    h_11 = v_1 . z, v_2 = fl32((z - h_11 v_1) / h_21).  With dot64 the dot
+    products and norms are exact sums of fp32 products rounded once to FP64;
+    the literal mode sums in fp32 and gives h_11 only to about sqrt(n) u_32."""
+    import math
+
+    rng = np.random.default_rng(54)
+    A = W.random_sparse(3000, 8.0 / 3000, rng, dominance=0.8)
+    _, Mv, _ = O.spai(A, A.pattern())
+    M = W.CSR(A.n, A.row_ptr, A.col, Mv)
+    Mb = O.Bucketed(M, 1e-3, [O.FP64, O.FP32, O.FP16])
+    r = rng.standard_normal(3000)
+    res = orc.gmres(A, Mb, r, tau=0.5, ug=O.FP32, up=O.FP32, want_basis=True, dot64=dot64)
+    V, H = res["V"], res["H"]
+    s = orc.apply(Mb, r.astype(np.float32).astype(np.float64), O.FP32)
+    beta = math.sqrt(math.fsum(s * s))
+    v1 = (s / beta).astype(np.float32).astype(np.float64)
+    if dot64:
+        assert _ulp32_close(V[:, 0], v1)
+    else:  # beta is rounded to fp32 first
+        assert np.abs(V[:, 0] - v1).max() <= 4 * 2.0 ** -24 * np.abs(v1).max()
+    z = orc.apply(Mb, orc.spmv(A, V[:, 0], O.FP32, O.FP32), O.FP32)
+    h11 = math.fsum(V[:, 0] * z)
+    if dot64:
+        assert abs(H[0, 0] - h11) <= 1e-13 * abs(h11)
+        z2 = (z - H[0, 0] * V[:, 0]).astype(np.float32).astype(np.float64)
+        h21 = math.sqrt(math.fsum(z2 * z2))
+        assert abs(H[1, 0] - h21) <= 1e-13 * h21
+        assert _ulp32_close(V[:, 1], (z2 / H[1, 0]).astype(np.float32).astype(np.float64))
+    else:
+        assert H[0, 0] == float(np.float32(H[0, 0]))  # rounded to fp32
+        assert abs(H[0, 0] - h11) <= 3000 * 2.0 ** -24 * np.abs(V[:, 0] * z).sum()
 
 
 def test_fp32_gmres_with_exact_inverse_takes_one_step(orc):
@@ -219,11 +266,12 @@ def test_fp32_gmres_with_exact_inverse_takes_one_step(orc):
     assert res["its"] == 1
 
 
-def test_right_preconditioned_transposed_gmres(orc):
+@pytest.mark.parametrize("dot64", [False, True])
+def test_right_preconditioned_transposed_gmres(orc, dot64):
     A, M, rng = _random_spai(52, n=50)
     Mb = O.Bucketed(M, 1e-3, [O.FP64])
     r = rng.standard_normal(50)
-    res = orc.gmres(A, Mb, r, tau=1e-13, ug=O.FP64, up=O.FP64, trans=True)
+    res = orc.gmres(A, Mb, r, tau=1e-13, ug=O.FP64, up=O.FP64, trans=True, dot64=dot64)
     d = np.linalg.solve(A.dense().T, r)
     assert np.allclose(res["d"], d, rtol=1e-9, atol=1e-11 * np.abs(d).max())
 
