@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-apply-bench", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-RHS and the 32-system measurements")
     ap.add_argument("--only-apply", action="store_true", help="run only the cold bucketed-apply measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --only-apply: also run one 1 GiB device copy (counter calibration)")
@@ -203,10 +205,89 @@ def main():
     if not args.no_apply_bench:
         out["m_apply"] = apply_bench(B, W, torch, np)
 
+    if not args.no_batched:
+        out["multi_system"] = multi_bench(B, W, torch, np, kw)
+        out["batched_rhs"] = batched_bench(B, W, torch, np, kw)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.eps, kw)
 
     print(json.dumps(out), flush=True)
+
+
+def multi_bench(B, W, torch, np, kw, replays=3):
+    """32 uneven 2D variable-coefficient diffusion systems (grid sides 32..448,
+    GRF coefficients) in one persistent launch replayed from a captured graph,
+    against the same systems solved one gmres_ir_solve after another."""
+    c = W.config("4b")
+    eps = c["eps"][0]
+    systems = []
+    for sy in c["systems"]:
+        Ad = B.CSRMatrix.from_host(sy["A"])
+        h = B.build(Ad, B.CSRMatrix.from_host(sy["P"]), eps=eps, precs=c["precs"])
+        systems.append((Ad, torch.as_tensor(sy["b"], device="cuda"), h))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = B.MultiPlan(systems, group_blocks=-1, **kw)  # autotuned group size
+    tune_s = time.perf_counter() - t0
+    plan.launch()
+    plan.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        plan.launch()
+    sts = plan.wait()
+    el = (time.perf_counter() - t0) / replays
+    res = {"workload": "32 vardiff2d systems, sides 32..448 (n 4,489..191,844, sum 2,437,223), GRF(16) "
+                       "coefficients, buckets fp32/bf16/fp16 eps=1e-2, one persistent launch per replay",
+           "systems_per_s": len(systems) / el, "ms_per_replay": el * 1e3, "replays": replays,
+           "group_blocks": plan.group_blocks, "autotune_s": tune_s,
+           "its_total": [q["its_total"] for q in sts], "max_relres": max(q["relres"][-1] for q in sts),
+           "all_converged": all(q["status"] == 0 for q in sts)}
+    plan.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for A, b, h in systems:
+        B.solve(A, b, h, **kw)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    res["sequential_systems_per_s"] = len(systems) / seq
+    for _, _, h in systems:
+        h.free()
+    _log(f"multi-system: {res['systems_per_s']:.2f} systems/s (group {res['group_blocks']}), "
+         f"sequential {res['sequential_systems_per_s']:.2f}")
+    return res
+
+
+def batched_bench(B, W, torch, np, kw):
+    """64 right-hand sides of the 128^3 anisotropic diffusion operator in one
+    gmres_ir_solve call (one timed call), against column 0 alone."""
+    c = W.config("4a")
+    A = c["A"]
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(c["P"]), eps=c["eps"][0], precs=c["precs"])
+    Bm = torch.as_tensor(np.ascontiguousarray(c["b"]), device="cuda")
+    b0 = Bm[:, 0].contiguous()
+    B.solve(Ad, b0, h, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x1, s1 = B.solve(Ad, b0, h, **kw)
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, sts = B.solve(Ad, Bm, h, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nr = Bm.shape[1]
+    res = {"workload": f"aniso3d 128^3 (1:10:100, n={A.n}), {nr} RHS N(0,1), buckets fp32/bf16/fp16 eps=1e-2",
+           "rhs_per_s": nr / el, "s_per_call": el, "single_rhs_per_s": 1.0 / single,
+           "its_col0": sts[0]["its"], "max_steps": max(q["steps"] for q in sts),
+           "max_relres": max(q["relres"][-1] for q in sts), "all_converged": all(q["status"] == 0 for q in sts)}
+    del x, Bm
+    h.free()
+    torch.cuda.empty_cache()
+    _log(f"batched: {res['rhs_per_s']:.2f} rhs/s vs single {res['single_rhs_per_s']:.2f}")
+    return res
 
 
 def apply_bench(B, W, torch, np):
@@ -275,8 +356,9 @@ def apply_bench(B, W, torch, np):
 
 
 def cpu_baseline(c, eps, kw):
-    """The CPU oracle (plain C, OpenMP over rows, sequential dot products) on
-    the same workload: one full solve from the FP64 SPAI (SPAI build not timed)."""
+    """The CPU oracle (plain C, OpenMP over rows, sequential dot products
+    accumulated in FP64, the realisation the GPU computes) on the same
+    workload: one full solve from the FP64 SPAI (SPAI build not timed)."""
     import oracle as O
     import workloads as W
 
@@ -286,7 +368,7 @@ def cpu_baseline(c, eps, kw):
     M = W.CSR(A.n, P.row_ptr, P.col, Mv)
     Mb = O.Bucketed(M, eps, c["precs"])
     t0 = time.perf_counter()
-    res = O.gmres_ir(A, M, Mb, c["b"], **kw)
+    res = O.gmres_ir(A, M, Mb, c["b"], dot64=True, **kw)
     el = time.perf_counter() - t0
     _log(f"oracle: {el:.1f} s per solve on {threads} threads, its {res['its']}")
     return {"value": 1.0 / el, "unit": "solves/s", "cores": threads, "kind": "oracle",

@@ -97,16 +97,18 @@ _lib.bspai_multi_plan.argtypes = [C.POINTER(_System), C.c_int, C.POINTER(_Tol), 
 _lib.bspai_multi_launch.argtypes = [_vp, _vp]
 _lib.bspai_multi_poll.argtypes = [_vp]
 _lib.bspai_multi_wait.argtypes = [_vp, C.POINTER(_Stats), _vp]
+_lib.bspai_multi_group_blocks.argtypes = [_vp]
 _lib.bspai_multi_free.argtypes = [_vp]
 _lib.bspai_multi_free.restype = None
 for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
-           "bspai_export", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll", "bspai_multi_wait"):
+           "bspai_export", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll", "bspai_multi_wait",
+           "bspai_multi_group_blocks"):
     getattr(_lib, _f).restype = C.c_int
 
 SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
            "bspai_export", "bspai_free", "bspai_last_error", "bspai_grad_vals", "bspai_set_profiling",
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
-           "bspai_multi_wait", "bspai_multi_free")
+           "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks")
 
 
 def set_profiling(on: bool) -> None:
@@ -302,7 +304,8 @@ class MultiPlan:
     captured HIP graph (``bspai_multi_*``).  ``systems``: list of
     (CSRMatrix A, b tensor, Handle M[, x tensor]); b and x are 1-D float64
     CUDA tensors that the plan keeps referenced (each launch reads b and
-    writes x)."""
+    writes x).  group_blocks: blocks per group (0 automatic, -1 autotuned by
+    timing one launch per candidate size)."""
 
     def __init__(self, systems, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4, tol_rr: float = 1e-10,
                  tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0, trans: bool = False,
@@ -330,6 +333,7 @@ class MultiPlan:
                                      C.byref(out), _stream(stream)))
         self._ptr = out.value
         self.nsys = len(systems)
+        self.group_blocks = _lib.bspai_multi_group_blocks(self._ptr)
 
     def launch(self, stream=None) -> None:
         _check(_lib.bspai_multi_launch(self._ptr, _stream(stream)))

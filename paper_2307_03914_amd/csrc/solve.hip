@@ -1064,14 +1064,71 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
   if (!plan_out) return fail(BSPAI_EINVAL, "bspai_multi_plan: null plan_out");
   *plan_out = nullptr;
   if (!sys || nsys < 1 || !tol) return fail(BSPAI_EINVAL, "bspai_multi_plan: need at least one system and tolerances");
-  if (group_blocks < 0 || max_groups < 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: negative group size or count");
+  if (group_blocks < -1 || max_groups < 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: bad group size or count");
   for (int k = 0; k < nsys; k++) {
     int rc = check_system(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, "bspai_multi_plan");
     if (rc) return rc;
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (tol->u_g == BSPAI_FP64) return multi_plan_typed<double>(sys, nsys, tol, group_blocks, max_groups, plan_out, s);
-  return multi_plan_typed<float>(sys, nsys, tol, group_blocks, max_groups, plan_out, s);
+  auto plan = [&](int gb, bspai_multi **out) {
+    return tol->u_g == BSPAI_FP64 ? multi_plan_typed<double>(sys, nsys, tol, gb, max_groups, out, s)
+                                  : multi_plan_typed<float>(sys, nsys, tol, gb, max_groups, out, s);
+  };
+  if (group_blocks >= 0) return plan(group_blocks, plan_out);
+  // autotune: the smallest group that holds the largest system, then doubled
+  // sizes; one timed launch of each, keep the fastest plan
+  int nmax = 0;
+  for (int k = 0; k < nsys; k++) nmax = std::max(nmax, sys[k].A.n);
+  const int gmin = std::max(1, (nmax + kSolveThreads * 16 - 1) / (kSolveThreads * 16));
+  bspai_multi *best = nullptr;
+  float best_ms = 0.f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  BSPAI_HIP(hipEventCreate(&e0));
+  BSPAI_HIP(hipEventCreate(&e1));
+  int rc = BSPAI_OK;
+  for (int gb = gmin; gb <= kMaxBlocks; gb *= 2) {
+    bspai_multi *cand = nullptr;
+    rc = plan(gb, &cand);
+    if (rc) {
+      if (best) {  // a larger group no longer fits: keep what we have
+        rc = BSPAI_OK;
+        break;
+      }
+      break;
+    }
+    float ms = 0.f;
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = hipGraphLaunch(cand->exec, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    cand->launches++;
+    if (e != hipSuccess) {
+      multi_release(cand);
+      rc = fail(BSPAI_EHIP, "bspai_multi_plan: timing a candidate failed: %s", hipGetErrorString(e));
+      break;
+    }
+    if (!best || ms < best_ms) {
+      multi_release(best);
+      best = cand;
+      best_ms = ms;
+    } else {
+      multi_release(cand);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    multi_release(best);
+    return rc;
+  }
+  *plan_out = best;
+  return BSPAI_OK;
+}
+
+extern "C" int bspai_multi_group_blocks(const bspai_multi *plan) {
+  if (!plan) return fail(BSPAI_EINVAL, "bspai_multi_group_blocks: no plan");
+  return plan->group_blocks;
 }
 
 extern "C" int bspai_multi_launch(bspai_multi *plan, void *stream) {
