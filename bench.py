@@ -312,6 +312,13 @@ def apply_bench(B, W, torch, np):
     nb = sum(1 for cc, p in zip(st["count"], st["precs"]) if cc > 0 and p != 5)
     bytes_per = sum(cc * (VALUE_BYTES[p] + 4) for cc, p in zip(st["count"], st["precs"]) if p != 5)
     bytes_per += 4 * (n + 1) * nb + 4 * n + 4 * n
+    # bytes the product copies actually hold: ELL copies n W (value + column
+    # code) bytes, other buckets their CSR bytes
+    moved = 8 * n
+    for cc, p, w, cb in zip(st["count"], st["precs"], st["ell_width"], st["col_bytes"]):
+        if p == 5 or cc == 0:
+            continue
+        moved += n * w * (VALUE_BYTES[p] + cb) if w else cc * (VALUE_BYTES[p] + 4) + 4 * (n + 1)
     for i in range(copies):
         B.apply(hs[i], xs[i], ys[i])
     torch.cuda.synchronize()
@@ -352,7 +359,8 @@ def apply_bench(B, W, torch, np):
                         "8 rotating copies (cold HBM), launches replayed from a captured graph", "bucket_counts": st["count"],
             "us_per_launch": ms * 1e3, "us_per_launch_python_issued": ms_eager * 1e3,
             "algorithmic_bytes": bytes_per, "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
-            "bytes_per_nnz": bytes_per / max(1, sum(st["count"]))}
+            "bytes_per_nnz": bytes_per / max(1, sum(st["count"])), "ell_width": st["ell_width"],
+            "col_bytes": st["col_bytes"], "moved_bytes": moved, "moved_GBs": moved / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(c, eps, kw):

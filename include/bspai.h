@@ -225,6 +225,9 @@ typedef struct {
     int64_t bytes_values;    /* bytes of stored values */
     int64_t bytes_indices;   /* bytes of column indices and per-bucket row pointers */
     double storage_pct;      /* values of M_b as % of all nnz stored in u_1 (dropped: 0 B) */
+    int32_t ell_width[6];    /* width W of the bucket's row-major padded copy used by bspai_apply (0: none) */
+    int32_t col_bytes[6];    /* bytes per column index that bspai_apply reads for the bucket: 1 (index
+                                into 256 offsets col - row), 2 (int16 offset) or 4 */
 } bspai_bucket_stats;
 
 /* bspai_stats -- bucket occupancy and storage of a handle (host struct). */

@@ -68,7 +68,8 @@ class _BStats(C.Structure):
     _fields_ = [("n", C.c_int32), ("q", C.c_int32), ("nnz", C.c_int64), ("precs", C.c_int * 6),
                 ("count", C.c_int64 * 6), ("threshold", C.c_double * 6), ("scale", C.c_double * 6),
                 ("norm_inf", C.c_double), ("eps_b", C.c_double), ("bytes_values", C.c_int64),
-                ("bytes_indices", C.c_int64), ("storage_pct", C.c_double)]
+                ("bytes_indices", C.c_int64), ("storage_pct", C.c_double), ("ell_width", C.c_int32 * 6),
+                ("col_bytes", C.c_int32 * 6)]
 
 
 class _System(C.Structure):
@@ -203,7 +204,8 @@ class Handle:
         q = s.q
         return dict(n=s.n, q=q, nnz=s.nnz, precs=list(s.precs[:q]), count=list(s.count[:q]),
                     threshold=list(s.threshold[:q]), scale=list(s.scale[:q]), norm_inf=s.norm_inf, eps_b=s.eps_b,
-                    bytes_values=s.bytes_values, bytes_indices=s.bytes_indices, storage_pct=s.storage_pct)
+                    bytes_values=s.bytes_values, bytes_indices=s.bytes_indices, storage_pct=s.storage_pct,
+                    ell_width=list(s.ell_width[:q]), col_bytes=list(s.col_bytes[:q]))
 
     def export(self, fp64: bool = True) -> Dict:
         import numpy as np

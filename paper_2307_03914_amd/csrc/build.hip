@@ -565,6 +565,7 @@ static void free_handle_memory(bspai_handle *h) {
     dfree(h->b[k].sptr), dfree(h->b[k].scol), dfree(h->b[k].sval);
     dfree(h->b[k].sptrT), dfree(h->b[k].scolT), dfree(h->b[k].svalT);
     dfree(h->b[k].ecol), dfree(h->b[k].eval), dfree(h->b[k].ecolT), dfree(h->b[k].evalT);
+    dfree(h->b[k].ecode), dfree(h->b[k].ecodeT), dfree(h->b[k].edict), dfree(h->b[k].edictT);
   }
   dfree(h->m_rp), dfree(h->m_col), dfree(h->m_val);
   dfree(h->mT_rp), dfree(h->mT_col), dfree(h->mT_val);
@@ -685,9 +686,17 @@ static int bucketize(bspai_handle *h, const bspai_prec *precs, int q, double eps
       if (r) return r;
       M.sell_w[j] = w;
       if ((r = csr_to_ell(n, B.rp, B.col, B.val, value_bytes(B.prec), &B.ecol, &B.eval, &w, s))) return r;
+      if (w && (r = ell_codes(n, w, B.ecol, &B.ecode, &B.edict, &B.ecw, s))) return r;
+      if (B.ecw) {  // the codes replace the int32 columns
+        dfree(B.ecol);
+        B.ecol = nullptr;
+      }
       M.ell_w[j] = w;
       M.ell_col[j] = B.ecol;
       M.ell_val[j] = B.eval;
+      M.ell_code[j] = B.ecode;
+      M.ell_dict[j] = B.edict;
+      M.ell_cw[j] = B.ecw;
       M.sell_ptr[j] = B.sptr;
       M.sell_col[j] = B.scol;
       M.sell_val[j] = B.sval;
@@ -714,9 +723,17 @@ static int bucketize(bspai_handle *h, const bspai_prec *precs, int q, double eps
         return r;
       T.sell_w[j] = w;
       if ((r = csr_to_ell(n, B.rpT, B.colT, B.valT, value_bytes(B.prec), &B.ecolT, &B.evalT, &w, s))) return r;
+      if (w && (r = ell_codes(n, w, B.ecolT, &B.ecodeT, &B.edictT, &B.ecwT, s))) return r;
+      if (B.ecwT) {
+        dfree(B.ecolT);
+        B.ecolT = nullptr;
+      }
       T.ell_w[j] = w;
       T.ell_col[j] = B.ecolT;
       T.ell_val[j] = B.evalT;
+      T.ell_code[j] = B.ecodeT;
+      T.ell_dict[j] = B.edictT;
+      T.ell_cw[j] = B.ecwT;
       T.sell_ptr[j] = B.sptrT;
       T.sell_col[j] = B.scolT;
       T.sell_val[j] = B.svalT;
@@ -999,6 +1016,12 @@ extern "C" int bspai_stats(const bspai_handle *M, bspai_bucket_stats *o) {
     o->bytes_values += (int64_t)vb * M->b[k].nnz;
     if (M->precs[k] != BSPAI_DROP && M->b[k].nnz > 0) o->bytes_indices += 4 * M->b[k].nnz + 4 * ((int64_t)M->n + 1);
     num += (double)vb * M->b[k].nnz;
+    o->col_bytes[k] = M->b[k].ecw ? M->b[k].ecw : 4;
+  }
+  // ELL widths are kept in the kernel view (stored buckets, least precise first)
+  for (int k = M->q - 1, j = 0; k >= 0; k--) {
+    if (M->precs[k] == BSPAI_DROP || M->b[k].nnz == 0) continue;
+    o->ell_width[k] = M->mat.ell_w[j++];
   }
   o->storage_pct = M->nnz ? 100.0 * num / ((double)M->nnz * value_bytes(M->precs[0])) : 100.0;
   return BSPAI_OK;

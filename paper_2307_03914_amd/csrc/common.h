@@ -65,6 +65,12 @@ struct BMat {
   const int32_t *ell_col[kMaxBuckets];
   const void *ell_val[kMaxBuckets];
   int32_t ell_w[kMaxBuckets];
+  // narrow columns of the ELL copy (then ell_col is null): ell_cw 1: ell_code
+  // holds one byte per entry, an index into ell_dict (256 offsets col - row);
+  // 2: ell_code holds the int16 offset col - row; 0: int32 ell_col
+  const void *ell_code[kMaxBuckets];
+  const int32_t *ell_dict[kMaxBuckets];
+  int32_t ell_cw[kMaxBuckets];
 };
 
 constexpr int kSlice = 64;
@@ -81,6 +87,9 @@ struct Bucket {
   void *sval = nullptr, *svalT = nullptr;
   int32_t *ecol = nullptr, *ecolT = nullptr;
   void *eval = nullptr, *evalT = nullptr;
+  void *ecode = nullptr, *ecodeT = nullptr;
+  int32_t *edict = nullptr, *edictT = nullptr;
+  int32_t ecw = 0, ecwT = 0;
 };
 
 }  // namespace bspai
@@ -150,6 +159,12 @@ int csr_to_sell(int n, const int32_t *rp, const int32_t *col, const void *val, i
 // gets W, or 0 (and nothing allocated) otherwise.
 int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, int vbytes, int32_t **ecol,
                void **evalp, int32_t *width, hipStream_t s);
+
+// Narrow column codes of an ELL copy (n rows of width w): *cw = 1 with
+// *code one byte per entry and *dict 256 int32 offsets col - row when the
+// copy has at most 256 distinct offsets; *cw = 2 with *code int16 offsets
+// when they all fit; else *cw = 0 and nothing allocated.
+int ell_codes(int n, int w, const int32_t *ecol, void **code, int32_t **dict, int32_t *cw, hipStream_t s);
 
 // Bucketed product kernels (apply.hip), used by the public apply and the build.
 int pick_lanes(const BMat &M, int64_t nnz);

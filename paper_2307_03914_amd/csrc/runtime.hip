@@ -371,6 +371,113 @@ int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, in
   return BSPAI_OK;
 }
 
+// ------------------------------------------------------------------ ELL column codes
+//
+// Entry u of row i of an ELL copy sits at i W + u, so its column can be stored
+// as the offset col - i.  Structured operators have few distinct offsets (7
+// for a 3D 7-point stencil): with at most 256 of them the columns become one
+// byte each, an index into a per-bucket table of offsets; otherwise, when every
+// offset fits 16 bits, two bytes each.
+
+__global__ void k_delta_range(int64_t ne, int w, const int32_t *ecol, int32_t *mm) {
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t d = ecol[e] - (int32_t)(e / w);
+    lo = min(lo, d);
+    hi = max(hi, d);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[0], lo);
+    atomicMax(&mm[1], hi);
+  }
+}
+
+__global__ void k_delta_mark(int64_t ne, int w, const int32_t *ecol, int32_t lo, int32_t *flags) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x)
+    flags[ecol[e] - (int32_t)(e / w) - lo] = 1;
+}
+
+__global__ void k_dict_fill(int32_t range, const int32_t *flags, const int32_t *pos, int32_t lo, int32_t *dict) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < range && flags[i]) dict[pos[i]] = i + lo;
+}
+
+__global__ void k_code8(int64_t ne, int w, const int32_t *ecol, int32_t lo, const int32_t *pos, uint8_t *code) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x)
+    code[e] = (uint8_t)pos[ecol[e] - (int32_t)(e / w) - lo];
+}
+
+__global__ void k_code16(int64_t ne, int w, const int32_t *ecol, int16_t *code) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x)
+    code[e] = (int16_t)(ecol[e] - (int32_t)(e / w));
+}
+
+int ell_codes(int n, int w, const int32_t *ecol, void **code, int32_t **dict, int32_t *cw, hipStream_t s) {
+  *code = nullptr, *dict = nullptr, *cw = 0;
+  const int64_t ne = (int64_t)n * w;
+  if (ne == 0) return BSPAI_OK;
+  constexpr int64_t kMaxRange = 1 << 22;
+  const unsigned grid = (unsigned)std::min<int64_t>(4096, (ne + 255) / 256);
+  int32_t *mm = nullptr, *flags = nullptr, *pos = nullptr;
+  void *tmp = nullptr;
+  int rc = dalloc_t(&mm, 2);
+  if (rc) return rc;
+  auto body = [&]() -> int {
+    const int32_t init[2] = {INT32_MAX, INT32_MIN};
+    int32_t hm[2];
+    BSPAI_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_delta_range, dim3(grid), dim3(256), 0, s, ne, w, ecol, mm);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipMemcpyAsync(hm, mm, sizeof(hm), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    const int32_t lo = hm[0], hi = hm[1];
+    const int64_t range = (int64_t)hi - lo + 1;
+    if (range <= kMaxRange) {
+      int r;
+      if ((r = dalloc_t(&flags, (size_t)range)) || (r = dalloc_t(&pos, (size_t)range + 1)) ||
+          (r = dalloc(&tmp, scan_tmp_bytes(range))))
+        return r;
+      BSPAI_HIP(hipMemsetAsync(flags, 0, 4 * (size_t)range, s));
+      hipLaunchKernelGGL(k_delta_mark, dim3(grid), dim3(256), 0, s, ne, w, ecol, lo, flags);
+      BSPAI_CHECK_LAUNCH();
+      if ((r = exclusive_scan(flags, pos, range, tmp, s))) return r;
+      int32_t total = 0;
+      BSPAI_HIP(hipMemcpyAsync(&total, pos + range, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipStreamSynchronize(s));
+      if (total <= 256) {
+        if ((r = dalloc_t(dict, 256)) || (r = dalloc(code, (size_t)ne + 16))) return r;
+        BSPAI_HIP(hipMemsetAsync(*dict, 0, 4 * 256, s));
+        hipLaunchKernelGGL(k_dict_fill, dim3((unsigned)((range + 255) / 256)), dim3(256), 0, s, (int32_t)range, flags,
+                           pos, lo, *dict);
+        BSPAI_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_code8, dim3(grid), dim3(256), 0, s, ne, w, ecol, lo, pos, static_cast<uint8_t *>(*code));
+        BSPAI_CHECK_LAUNCH();
+        *cw = 1;
+      }
+    }
+    if (*cw == 0 && lo >= -32768 && hi <= 32767) {
+      int r;
+      if ((r = dalloc(code, 2 * (size_t)ne + 16))) return r;
+      hipLaunchKernelGGL(k_code16, dim3(grid), dim3(256), 0, s, ne, w, ecol, static_cast<int16_t *>(*code));
+      BSPAI_CHECK_LAUNCH();
+      *cw = 2;
+    }
+    BSPAI_HIP(hipStreamSynchronize(s));
+    return BSPAI_OK;
+  };
+  rc = body();
+  dfree(mm), dfree(flags), dfree(pos), dfree(tmp);
+  if (rc) {
+    dfree(*code), dfree(*dict);
+    *code = nullptr, *dict = nullptr, *cw = 0;
+  }
+  return rc;
+}
+
 }  // namespace bspai
 
 extern "C" const char *bspai_last_error(void) { return bspai::g_err; }

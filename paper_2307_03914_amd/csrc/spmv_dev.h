@@ -436,11 +436,95 @@ __device__ __forceinline__ void ell_vals4(const BMat &M, int k, int64_t e, PT (&
   }
 }
 
-// row 64 sl + lane of M_b x: each bucket from its ELL copy (16-byte vector
-// loads of the row's own entries) when present, else from its SELL-64 copy.
-// Entries are added in CSR order, padding adds +0.
+// entries e .. e + 7 of bucket k's ELL values (e a multiple of 8): one
+// 16-byte load for the 2-byte formats
+template <typename PT>
+__device__ __forceinline__ void ell_vals8(const BMat &M, int k, int64_t e, PT (&v)[8]) {
+  switch (M.prec[k]) {
+    case BSPAI_FP64: {
+      const double2 *p = reinterpret_cast<const double2 *>(static_cast<const double *>(M.ell_val[k]) + e);
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        double2 a = p[t];
+        v[2 * t] = (PT)a.x, v[2 * t + 1] = (PT)a.y;
+      }
+    } break;
+    case BSPAI_FP32: {
+      const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(M.ell_val[k]) + e);
+      float4 a = p[0], b = p[1];
+      v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    } break;
+    case BSPAI_FP16:
+    case BSPAI_BF16: {
+      uint4 a = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(M.ell_val[k]) + e);
+      const uint32_t w4[4] = {a.x, a.y, a.z, a.w};
+      const bool h = M.prec[k] == BSPAI_FP16;
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        v[2 * t] = h ? decode_f16(w4[t] & 0xFFFFu) : decode_bf16(w4[t] & 0xFFFFu);
+        v[2 * t + 1] = h ? decode_f16(w4[t] >> 16) : decode_bf16(w4[t] >> 16);
+      }
+    } break;
+    case BSPAI_FP8_E4M3: {
+      uint2 a = *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(M.ell_val[k]) + e);
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        v[t] = decode_e4m3((a.x >> (8 * t)) & 0xFFu);
+        v[4 + t] = decode_e4m3((a.y >> (8 * t)) & 0xFFu);
+      }
+    } break;
+    default:
+#pragma unroll
+      for (int t = 0; t < 8; t++) v[t] = (PT)0;
+  }
+}
+
+// columns of entries e .. e + N - 1 (N = 4 or 8, e a multiple of N) of row
+// `row` in bucket k's ELL copy, from its byte codes (dict: the 256 offsets),
+// int16 offsets or int32 columns
+template <int N>
+__device__ __forceinline__ void ell_cols(const BMat &M, int k, int64_t e, int row, const int32_t *dict, int (&c)[N]) {
+  const int cw = M.ell_cw[k];
+  if (cw == 1) {
+    const uint8_t *p = static_cast<const uint8_t *>(M.ell_code[k]) + e;
+    uint32_t q[2];
+    if (N == 8) {
+      uint2 t = *reinterpret_cast<const uint2 *>(p);
+      q[0] = t.x, q[1] = t.y;
+    } else {
+      q[0] = *reinterpret_cast<const uint32_t *>(p), q[1] = 0;
+    }
+#pragma unroll
+    for (int t = 0; t < N; t++) c[t] = row + dict[(q[t / 4] >> (8 * (t % 4))) & 0xFFu];
+  } else if (cw == 2) {
+    const int16_t *p = static_cast<const int16_t *>(M.ell_code[k]) + e;
+    int32_t q[4];
+    if (N == 8) {
+      int4 t = *reinterpret_cast<const int4 *>(p);
+      q[0] = t.x, q[1] = t.y, q[2] = t.z, q[3] = t.w;
+    } else {
+      int2 t = *reinterpret_cast<const int2 *>(p);
+      q[0] = t.x, q[1] = t.y, q[2] = 0, q[3] = 0;
+    }
+#pragma unroll
+    for (int t = 0; t < N; t++) c[t] = row + ((t & 1) ? (q[t / 2] >> 16) : (int32_t)(int16_t)(q[t / 2] & 0xFFFF));
+  } else {
+    const int4 *p = reinterpret_cast<const int4 *>(M.ell_col[k] + e);
+#pragma unroll
+    for (int t = 0; t < N / 4; t++) {
+      int4 a = p[t];
+      c[4 * t] = a.x, c[4 * t + 1] = a.y, c[4 * t + 2] = a.z, c[4 * t + 3] = a.w;
+    }
+  }
+}
+
+// row 64 sl + lane of M_b x: each bucket from its ELL copy (the row's own
+// entries with 16-byte vector loads, narrow column codes) when present, else
+// from its SELL-64 copy.  Entries are added in CSR order, padding adds +0.
+// sdict: the buckets' offset tables staged in LDS (256 per bucket), or null.
 template <typename XT, typename PT>
-__device__ __forceinline__ double bspmv_sell_row(const BMat &M, const XT *__restrict__ x, int sl, int lane) {
+__device__ __forceinline__ double bspmv_sell_row(const BMat &M, const XT *__restrict__ x, int sl, int lane,
+                                                 const int32_t *sdict) {
   constexpr int U = 8;
   const int row = sl * kSlice + lane;
   double total = 0.0;
@@ -452,28 +536,33 @@ __device__ __forceinline__ double bspmv_sell_row(const BMat &M, const XT *__rest
     if (ew) {
       if (row < M.n) {
         const int64_t e0 = (int64_t)row * ew;
-        for (int c0 = 0; c0 < ew; c0 += U) {
-          int cc[U];
-          PT vv[U];
+        const int32_t *dict = sdict ? sdict + 256 * k : M.ell_dict[k];
+        if (ew == 4) {
+          int cc[4];
+          PT vv[4];
+          ell_cols<4>(M, k, e0, row, dict, cc);
+          ell_vals4<PT>(M, k, e0, vv);
+          PT xv[4];
 #pragma unroll
-          for (int h = 0; h < U; h += 4) {
-            if (c0 + h < ew) {
-              int4 ci = *reinterpret_cast<const int4 *>(M.ell_col[k] + e0 + c0 + h);
-              cc[h] = ci.x, cc[h + 1] = ci.y, cc[h + 2] = ci.z, cc[h + 3] = ci.w;
-              PT v4[4];
-              ell_vals4<PT>(M, k, e0 + c0 + h, v4);
-              vv[h] = v4[0], vv[h + 1] = v4[1], vv[h + 2] = v4[2], vv[h + 3] = v4[3];
-            } else {
+          for (int u = 0; u < 4; u++) xv[u] = (PT)x[cc[u]];
 #pragma unroll
-              for (int t = 0; t < 4; t++) cc[h + t] = row, vv[h + t] = (PT)0;
-            }
+          for (int u = 0; u < 4; u++) {
+            if (wide)
+              accd = fma((double)vv[u], (double)xv[u], accd);
+            else
+              accf = fmaf((float)vv[u], (float)xv[u], accf);
           }
-          PT xv[U];
+        } else {
+          for (int c0 = 0; c0 < ew; c0 += U) {
+            int cc[U];
+            PT vv[U];
+            ell_cols<U>(M, k, e0 + c0, row, dict, cc);
+            ell_vals8<PT>(M, k, e0 + c0, vv);
+            PT xv[U];
 #pragma unroll
-          for (int u = 0; u < U; u++) xv[u] = (c0 + u < ew) ? (PT)x[cc[u]] : (PT)0;
+            for (int u = 0; u < U; u++) xv[u] = (PT)x[cc[u]];
 #pragma unroll
-          for (int u = 0; u < U; u++) {
-            if (c0 + u < ew) {
+            for (int u = 0; u < U; u++) {
               if (wide)
                 accd = fma((double)vv[u], (double)xv[u], accd);
               else
@@ -516,15 +605,75 @@ __device__ __forceinline__ double bspmv_sell_row(const BMat &M, const XT *__rest
   return total;
 }
 
-// rows [r0, r1) (r0 a multiple of 64) by the waves of the calling block
-template <typename XT, typename YT, typename PT>
-__device__ __forceinline__ void bspmv_sell_rows(const BMat &M, const XT *__restrict__ x, YT *__restrict__ y, int r0,
-                                                int r1) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int sl = r0 / kSlice + w; sl * kSlice < r1; sl += nw) {
-    double v = bspmv_sell_row<XT, PT>(M, x, sl, lane);
-    int row = sl * kSlice + lane;
-    if (row < r1) y[row] = (YT)v;
+// RT rows per thread when every stored bucket has an ELL copy: for each
+// bucket and each 8-entry chunk, the column codes and values of all RT rows
+// are loaded first, then their x entries, then the products are added, so a
+// thread keeps RT independent load chains in flight.  rows[r] < 0: no row.
+// Same order of operations per row as bspmv_sell_row.
+template <int RT, typename XT, typename PT>
+__device__ __forceinline__ void bspmv_ell_rows(const BMat &M, const XT *__restrict__ x, const int (&rows)[RT],
+                                               const int32_t *sdict, double (&out)[RT]) {
+#pragma unroll
+  for (int r = 0; r < RT; r++) out[r] = 0.0;
+  for (int k = 0; k < M.nb; k++) {
+    const bool wide = (M.prec[k] == BSPAI_FP64) || sizeof(PT) == 8;
+    const int ew = M.ell_w[k];
+    const int32_t *dict = sdict ? sdict + 256 * k : M.ell_dict[k];
+    double accd[RT];
+    float accf[RT];
+#pragma unroll
+    for (int r = 0; r < RT; r++) accd[r] = 0.0, accf[r] = 0.f;
+    if (ew == 4) {
+      int cc[RT][4];
+      PT vv[RT][4];
+#pragma unroll
+      for (int r = 0; r < RT; r++) {
+        const int row = rows[r] < 0 ? 0 : rows[r];
+        ell_cols<4>(M, k, (int64_t)row * 4, row, dict, cc[r]);
+        ell_vals4<PT>(M, k, (int64_t)row * 4, vv[r]);
+      }
+      PT xv[RT][4];
+#pragma unroll
+      for (int r = 0; r < RT; r++)
+#pragma unroll
+        for (int u = 0; u < 4; u++) xv[r][u] = (PT)x[cc[r][u]];
+#pragma unroll
+      for (int r = 0; r < RT; r++)
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          if (wide)
+            accd[r] = fma((double)vv[r][u], (double)xv[r][u], accd[r]);
+          else
+            accf[r] = fmaf((float)vv[r][u], (float)xv[r][u], accf[r]);
+        }
+    } else {
+      for (int c0 = 0; c0 < ew; c0 += 8) {
+        int cc[RT][8];
+        PT vv[RT][8];
+#pragma unroll
+        for (int r = 0; r < RT; r++) {
+          const int row = rows[r] < 0 ? 0 : rows[r];
+          ell_cols<8>(M, k, (int64_t)row * ew + c0, row, dict, cc[r]);
+          ell_vals8<PT>(M, k, (int64_t)row * ew + c0, vv[r]);
+        }
+        PT xv[RT][8];
+#pragma unroll
+        for (int r = 0; r < RT; r++)
+#pragma unroll
+          for (int u = 0; u < 8; u++) xv[r][u] = (PT)x[cc[r][u]];
+#pragma unroll
+        for (int r = 0; r < RT; r++)
+#pragma unroll
+          for (int u = 0; u < 8; u++) {
+            if (wide)
+              accd[r] = fma((double)vv[r][u], (double)xv[r][u], accd[r]);
+            else
+              accf[r] = fmaf((float)vv[r][u], (float)xv[r][u], accf[r]);
+          }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; r++) out[r] += (wide ? accd[r] : (double)accf[r]) * M.scale[k];
   }
 }
 

@@ -214,6 +214,63 @@ def test_apply_matches_oracle(B, case, mode, trans):
     h.free()
 
 
+def _k_per_row(n, span, seed, k=7):
+    """Diagonal plus k - 1 distinct random columns within +-span of the row:
+    every row has k entries (7: ELL copies of width 8; 4: width 4)."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        lo, hi = max(0, i - span), min(n, i + span + 1)
+        c = set()
+        while len(c) < k - 1:
+            j = int(rng.integers(lo, hi))
+            if j != i:
+                c.add(j)
+        rows += [i] * k
+        cols += [i] + sorted(c)
+    import scipy.sparse as sp
+
+    vals = rng.standard_normal(len(rows))
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    A.setdiag(np.abs(A).sum(axis=1).A1 * 1.5)
+    return W.from_scipy(A)
+
+
+@pytest.mark.parametrize("kind,col_bytes,width", [("stencil", 1, 8), ("int16", 2, 8), ("int32", 4, 8),
+                                                  ("int16_w4", 2, 4), ("bytes_w4", 1, 4)])
+def test_apply_narrow_column_codes(B, kind, col_bytes, width):
+    """The ELL copies store columns as byte codes into the bucket's offsets
+    (a stencil has few distinct col - row), as int16 offsets, or as int32
+    columns: each form against the oracle, both orientations."""
+    import torch
+
+    if kind == "stencil":
+        A = W.config("4a", small=True)["A"]
+        precs, eps = [O.FP32, O.FP16, O.BF16], 1e-2
+    elif kind == "bytes_w4":  # 4 entries per row, offsets from a set of 100
+        A = _k_per_row(20000, 50, 22, k=4)
+        precs, eps = [O.FP32], 1e-3
+    else:
+        n, span = {"int16": (40000, 30000), "int32": (90000, 45000), "int16_w4": (30000, 20000)}[kind]
+        A = _k_per_row(n, span, 21, k=4 if kind.endswith("w4") else 7)
+        precs, eps = [O.FP32], 1e-3
+    P = A.pattern()
+    _say("apply column codes", kind, A.n)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, eps, precs)
+    h = B.import_m(B.CSRMatrix.from_host(M), eps, precs)
+    st = h.stats()
+    stored = [k for k in range(st["q"]) if st["count"][k] > 0]
+    assert any(st["ell_width"][k] == width and st["col_bytes"][k] == col_bytes for k in stored), st
+    x = np.random.default_rng(6).standard_normal(A.n).astype(np.float32).astype(np.float64)
+    for trans in (False, True):
+        y = (B.apply_T if trans else B.apply)(h, _dev(x, torch.float32)).double().cpu().numpy()
+        ref = (O.apply_T if trans else O.apply)(Mb, x, O.FP64)
+        bound = _apply_bound(Mb, x, U32, transpose=trans) + U32 * np.abs(ref)
+        assert np.all(np.abs(y - ref) <= bound + 1e-300), (kind, trans)
+    h.free()
+
+
 @pytest.mark.parametrize("nrhs", [2, 8, 64, 70])
 def test_apply_multi_rhs_matches_columns(B, nrhs):
     import torch
