@@ -63,10 +63,10 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(kernel_src):
+def _traffic(kernel_src, record="solve_kernel_traffic.json"):
     """HBM traffic per launch from the committed rocprofv3 counter runs, only if
     they were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "solve_kernel_traffic.json")
+    p = os.path.join(ROOT, "profiles", record)
     try:
         with open(p) as f:
             t = json.load(f)
@@ -91,7 +91,7 @@ def main():
                     help="skip the 64-RHS and the 32-system measurements")
     ap.add_argument("--only-apply", action="store_true", help="run only the cold bucketed-apply measurement")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="with --only-apply: also run one 1 GiB device copy (counter calibration)")
+                    help="also run one 1 GiB device copy first (calibration of hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -107,16 +107,18 @@ def main():
 
     torch.cuda.set_device(0)
     dev = "cuda"
+    if args.copy_calibration:
+        # a plain device copy of known size (1 GiB read, 1 GiB written), for
+        # scaling hardware byte counters
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b2 = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b2.copy_(a)
+        torch.cuda.synchronize()
+        del a, b2
+        torch.cuda.empty_cache()
     if args.only_apply:
         res = apply_bench(B, W, torch, np)
-        if args.copy_calibration:
-            # a plain device copy of known size, for scaling hardware byte counters
-            a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-            b2 = torch.empty_like(a)
-            torch.cuda.synchronize()
-            b2.copy_(a)
-            torch.cuda.synchronize()
-            res["copy_calibration_bytes"] = {"read": a.numel() * 4, "write": a.numel() * 4}
         print(json.dumps({"m_apply": res}), flush=True)
         return
     _log("generating workload")
@@ -360,7 +362,9 @@ def apply_bench(B, W, torch, np):
             "us_per_launch": ms * 1e3, "us_per_launch_python_issued": ms_eager * 1e3,
             "algorithmic_bytes": bytes_per, "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
             "bytes_per_nnz": bytes_per / max(1, sum(st["count"])), "ell_width": st["ell_width"],
-            "col_bytes": st["col_bytes"], "moved_bytes": moved, "moved_GBs": moved / (ms * 1e-3) / 1e9}
+            "col_bytes": st["col_bytes"], "moved_bytes": moved, "moved_GBs": moved / (ms * 1e-3) / 1e9,
+            "traffic": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "apply.hip"),
+                                "apply_kernel_traffic.json")}
 
 
 def cpu_baseline(c, eps, kw):
