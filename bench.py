@@ -201,8 +201,30 @@ def main():
             comps[name] = {"solves_per_s": reps / el, "its": s2["its"], "relres": s2["relres"][-1],
                            "eta": s2["eta"][-1]}
             _log(f"{name}: {reps / el:.2f} solves/s its {s2['its']}")
-        h64.free()
         out["comparators"] = comps
+        # the workload's sweep over eps_b: occupancy, storage and iterations
+        # per eps against the unbucketed fp64 SPAI (plain SPAI-GMRES-IR with
+        # the same fp32 Krylov)
+        sweep = []
+        for eps in (1e-6, 1e-4, 1e-2):
+            he = B.build(Ad, Pd, eps=eps, precs=precs)
+            se = he.stats()
+            B.solve(Ad, b, he, **kw)
+            torch.cuda.synchronize()
+            reps = 3
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                xe, ste = B.solve(Ad, b, he, **kw)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t1) / reps
+            sweep.append({"eps": eps, "bucket_counts": se["count"], "storage_pct": se["storage_pct"],
+                          "its": ste["its"], "its_total": ste["its_total"], "eta": ste["eta"][-1],
+                          "relres": ste["relres"][-1], "solves_per_s": 1.0 / el})
+            he.free()
+            _log(f"eps {eps:g}: counts {se['count']} storage {se['storage_pct']:.1f}% its {ste['its']} "
+                 f"{1.0 / el:.2f} solves/s")
+        out["eps_sweep"] = {"plain_spai_its": comps["spai_fp64M_fp32krylov"]["its"], "points": sweep}
+        h64.free()
 
     if not args.no_apply_bench:
         out["m_apply"] = apply_bench(B, W, torch, np)

@@ -133,6 +133,8 @@ typedef struct {
                        the size whose rotated Hessenberg matrix stays on chip */
     int x0_mode;    /* 0: x_0 = M b with the FP64 M; 1: with M_b; 2: x_0 = 0; 3: x holds x_0 on entry */
     int trans;      /* 1: solve A^T x = b with (M_b)^T as a right preconditioner (adjoint solve) */
+    double stag_ratio; /* stagnation: stop when ||d_i||/||x_{i+1}|| > stag_ratio times the previous ratio
+                          (from the second correction on); 0 selects 0.5, a negative value never stops */
 } gmres_ir_tol;
 
 typedef struct {
@@ -151,8 +153,8 @@ typedef struct {
  *   stored FP64), stopping tests, left-preconditioned MGS-GMRES on
  *   M_b A d = M_b r_i in u_g with A rounded to u_g (right-preconditioned
  *   A^T M_b^T for trans = 1) to relative tolerance tau, x_{i+1} = x_i + d_i in FP64.
- *   Stops on tol_rr, tol_be, stagnation of ||d_i||/||x_{i+1}|| (more than half
- *   the previous ratio after the first correction) or i_max.
+ *   Stops on tol_rr, tol_be, stagnation of ||d_i||/||x_{i+1}|| (more than
+ *   stag_ratio times the previous ratio after the first correction) or i_max.
  *   A: device CSR; b, x: device FP64 arrays of n x nrhs, row-major (entry
  *   (i, c) at i * nrhs + c), 1 <= nrhs <= 64; st_host: host array of nrhs
  *   stats (or NULL).  nrhs = 1 runs as one persistent kernel; nrhs > 1 runs

@@ -53,7 +53,8 @@ class GmresOpts(C.Structure):
 class IROpts(C.Structure):
     _fields_ = [("ug", C.c_int), ("up", C.c_int), ("ur_dd", C.c_int), ("tau", C.c_double),
                 ("tol_rr", C.c_double), ("tol_be", C.c_double), ("i_max", C.c_int),
-                ("gmres_max", C.c_int), ("x0_mode", C.c_int), ("trans", C.c_int), ("dot64", C.c_int)]
+                ("gmres_max", C.c_int), ("x0_mode", C.c_int), ("trans", C.c_int), ("dot64", C.c_int),
+                ("stag", C.c_double)]
 
 
 class IRStats(C.Structure):
@@ -311,13 +312,13 @@ def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32,
 
 def gmres_ir(A, M, Mb: Bucketed, b, ug: int = FP32, up: int = FP32, ur_dd: bool = True, tau: float = 1e-4,
              tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: Optional[int] = None,
-             x0_mode: int = 0, trans: bool = False, dot64: bool = False) -> Dict:
+             x0_mode: int = 0, trans: bool = False, dot64: bool = False, stag_ratio: Optional[float] = 0.5) -> Dict:
     """BSPAI-GMRES-IR (Algorithm 4).  M: FP64 SPAI as workloads.CSR (for x_0).
-    dot64 as in :func:`gmres`."""
+    dot64 as in :func:`gmres`; stag_ratio None: no stagnation stop."""
     n = A.n
     gm = min(n, gmres_max if gmres_max is not None else n)
     o = IROpts(ug, up, int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), gm, int(x0_mode),
-               int(trans), int(dot64))
+               int(trans), int(dot64), -1.0 if stag_ratio is None else float(stag_ratio))
     st = IRStats()
     x = np.zeros(n)
     if trans:

@@ -714,7 +714,8 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
  *
  * The paper gives no stopping rule for the refinement loop; this one stops
  * when rho <= tol_rr (reason 1), eta <= tol_be (2), when the correction
- * stagnates: ||d_i||/||x_{i+1}|| > 0.5 ||d_{i-1}||/||x_i|| for i >= 1 (3), or
+ * stagnates: ||d_i||/||x_{i+1}|| > s ||d_{i-1}||/||x_i|| for i >= 1 (3; s = stag,
+ * 0 meaning 0.5 and a negative value switching the test off), or
  * after i_max corrections (4, status ORC_ENOCONV).
  *
  * trans = 1 solves A^T x = b (the adjoint): the caller passes A^T as (rp,ci,v),
@@ -726,6 +727,7 @@ typedef struct {
     double tau, tol_rr, tol_be;
     int i_max, gmres_max, x0_mode, trans;
     int dot64;  /* GMRES dot products accumulated in FP64 (orc_gmres) */
+    double stag;  /* stagnation ratio: 0 means 0.5, negative: no stagnation stop */
 } orc_ir_opts;
 
 typedef struct {
@@ -775,7 +777,8 @@ int orc_gmres_ir(int n, const int *rp, const int *ci, const double *v,
         st->its_total += its;
         for (int l = 0; l < n; l++) x[l] += d[l];
         double dx = vec_norm_inf(n, d) / vec_norm_inf(n, x);
-        if (i >= 1 && dx > 0.5 * dx_prev) stagnated = 1;
+        const double sr = o->stag == 0.0 ? 0.5 : o->stag;
+        if (i >= 1 && sr > 0.0 && dx > sr * dx_prev) stagnated = 1;
         dx_prev = dx;
         i++;
     }

@@ -56,7 +56,7 @@ class _Opts(C.Structure):
 class _Tol(C.Structure):
     _fields_ = [("u_g", C.c_int), ("ur_dd", C.c_int), ("tau", C.c_double), ("tol_rr", C.c_double),
                 ("tol_be", C.c_double), ("i_max", C.c_int), ("gmres_max", C.c_int), ("x0_mode", C.c_int),
-                ("trans", C.c_int)]
+                ("trans", C.c_int), ("stag_ratio", C.c_double)]
 
 
 class _Stats(C.Structure):
@@ -272,13 +272,24 @@ def _stats_dict(s: _Stats) -> Dict:
                 relres=list(s.relres[:k + 1]), stop_reason=s.stop_reason, status=s.status)
 
 
+def _stag(r: Optional[float]) -> float:
+    """stag_ratio for the C struct: None switches the stagnation stop off."""
+    if r is None:
+        return -1.0
+    if r <= 0:
+        raise ValueError("stag_ratio must be positive (None: no stagnation stop)")
+    return float(r)
+
+
 def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4,
           tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0,
-          trans: bool = False, x: Optional[torch.Tensor] = None, stream=None, raise_noconv: bool = False):
+          trans: bool = False, x: Optional[torch.Tensor] = None, stream=None, raise_noconv: bool = False,
+          stag_ratio: Optional[float] = 0.5):
     """BSPAI-GMRES-IR.  b: [n] or [n, nrhs] (1 <= nrhs <= 64, row-major)
     float64 on the GPU.  Returns (x, stats): one stats dict for a 1-D b, a
     list of them (one per column) for a 2-D b.  ENOCONV is reported in the
-    stats (status) unless raise_noconv."""
+    stats (status) unless raise_noconv.  stag_ratio: stop when a correction's
+    ||d||/||x|| exceeds stag_ratio times the previous one (None: never)."""
     if b.dtype != torch.float64 or not b.is_cuda or b.dim() not in (1, 2):
         raise ValueError("b must be a 1-D or 2-D float64 CUDA tensor")
     b = b.contiguous()
@@ -290,7 +301,7 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
     elif x.shape != b.shape or x.dtype != torch.float64 or not x.is_contiguous():
         raise ValueError("x must be a contiguous float64 tensor shaped like b")
     tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), int(gmres_max),
-               int(x0_mode), int(trans))
+               int(x0_mode), int(trans), _stag(stag_ratio))
     st = (_Stats * nrhs)()
     a = A._c()
     allow = () if raise_noconv else (ENOCONV,)
@@ -311,7 +322,7 @@ class MultiPlan:
 
     def __init__(self, systems, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4, tol_rr: float = 1e-10,
                  tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0, trans: bool = False,
-                 group_blocks: int = 0, max_groups: int = 0, stream=None):
+                 group_blocks: int = 0, max_groups: int = 0, stream=None, stag_ratio: Optional[float] = 0.5):
         self._ptr = None
         self.A, self.b, self.x, self.M = [], [], [], []
         arr = (_System * len(systems))()
@@ -329,7 +340,7 @@ class MultiPlan:
             arr[k].x = x.data_ptr()
             arr[k].M = M.ptr
         self.tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max),
-                        int(gmres_max), int(x0_mode), int(trans))
+                        int(gmres_max), int(x0_mode), int(trans), _stag(stag_ratio))
         out = _vp()
         _check(_lib.bspai_multi_plan(arr, len(systems), C.byref(self.tol), int(group_blocks), int(max_groups),
                                      C.byref(out), _stream(stream)))

@@ -56,6 +56,7 @@ struct SolveParams {
   const double *f_val;  // FP64 M (M^T for trans), x0_mode 0
   int x0_mode, trans, ur_dd, i_max;
   double tau, tol_rr, tol_be;
+  double stag;  // stagnation ratio (<= 0: no stagnation stop)
   const double *b;
   double *x;
   VT *rv, *w, *zg, *V;
@@ -486,7 +487,7 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
     if (!grid_reduce<2, true>(G, rtag, dn, sh, bid)) return false;
     if (!grid_sync(G, epoch, bid)) return false;  // publish x for the next residual
     const double dx = dn[1] > 0 ? dn[0] / dn[1] : 0.0;
-    if (it >= 1 && dx > 0.5 * dx_prev) stag = 1;
+    if (it >= 1 && p.stag > 0.0 && dx > p.stag * dx_prev) stag = 1;
     dx_prev = dx;
     if (rec && it < 64) p.stats->its[it] = kdone;
     its_total += kdone;
@@ -641,6 +642,7 @@ static int sys_setup(const bspai_csr *A, const double *b, const bspai_handle *M,
   p.tau = tol->tau;
   p.tol_rr = tol->tol_rr;
   p.tol_be = tol->tol_be;
+  p.stag = tol->stag_ratio == 0.0 ? 0.5 : tol->stag_ratio;
   p.b = b;
   p.x = x;
   p.rv = reinterpret_cast<VT *>(base + L.rv);

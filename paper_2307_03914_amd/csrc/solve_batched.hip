@@ -321,6 +321,7 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   const int n = A->n;
   const int64_t nnz = A->nnz, nr = (int64_t)n * R;
   const bool tr = tol->trans != 0;
+  const double stag_ratio = tol->stag_ratio == 0.0 ? 0.5 : tol->stag_ratio;
   Cols cc{R, 1};
   while (cc.Rp < R) cc.Rp <<= 1;
   const int nblk = (int)std::min<int64_t>(kBGrid, (n + (kBT / cc.Rp) - 1) / (kBT / cc.Rp));
@@ -529,7 +530,7 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
       if (it < 64) st[c].its[it] = kc[c];
       st[c].its_total += kc[c];
       double dx = hxn[c] > 0 ? hdn[c] / hxn[c] : 0.0;
-      if (it >= 1 && dx > 0.5 * dx_prev[c]) stag[c] = 1;
+      if (it >= 1 && stag_ratio > 0.0 && dx > stag_ratio * dx_prev[c]) stag[c] = 1;
       dx_prev[c] = dx;
     }
     it++;

@@ -294,6 +294,22 @@ def test_ir_reaches_fp64_backward_error(orc):
     assert res["its_total"] == sum(res["its"])
 
 
+def test_ir_stagnation_ratio(orc):
+    # with no tolerance to meet, the default rule stops on stagnation; a looser
+    # ratio cannot stop earlier, and with the test off the loop runs to i_max
+    A, M, rng = _random_spai(53, n=200, power=1)
+    Mb = O.Bucketed(M, 1e-4, [O.FP64, O.FP32, O.FP16, O.BF16])
+    b = W.matvec_extended(A, rng.standard_normal(200))
+    runs = {r: orc.gmres_ir(A, M, Mb, b, tol_rr=0.0, tol_be=0.0, i_max=12, stag_ratio=r)
+            for r in (0.5, 0.999, None)}
+    assert runs[0.5]["stop_reason"] == 3 and runs[0.5]["steps"] < 12
+    assert runs[0.999]["steps"] >= runs[0.5]["steps"]
+    assert runs[None]["stop_reason"] == 4 and runs[None]["steps"] == 12 and runs[None]["status"] == O.ENOCONV
+    # the corrections before the stop are the same in every run
+    k = runs[0.5]["steps"]
+    assert runs[None]["eta"][: k + 1] == runs[0.5]["eta"][: k + 1]
+
+
 def test_ir_config1_converges_to_relative_residual(orc):
     c = W.config("1", small=True)
     A, P = c["A"], c["P"]
