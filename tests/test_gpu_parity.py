@@ -550,14 +550,14 @@ def _host_relres(A, b, x):
 
 def test_multi_system_full_size(B):
     """The 32 full-size systems (n from 4,489 to 191,844) in the autotuned
-    launch that the benchmark times.  Every system ends on a stopping test
-    of the method (relative residual, or stagnation of the corrections) with
+    launch that the benchmark times (no stagnation stop, as there).  Every
+    system meets the relative residual or the backward error tolerance, with
     the residual it reports equal to the one recomputed on the host; the
     three smallest systems are also solved by the oracle."""
     c = W.config("4b")
     eps = c["eps"][0]
     _say("multi-system full size")
-    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    kw = dict(tau=1e-4, tol_rr=1e-10, tol_be=2e-15, gmres_max=150, i_max=64, stag_ratio=None)
     systems = _multi_systems(B, c, eps)
     plan = B.MultiPlan(systems, group_blocks=-1, **kw)
     plan.launch()
@@ -573,7 +573,7 @@ def test_multi_system_full_size(B):
              st["relres"][-1], "host", rr, "eta", st["eta"][-1])
     for k, sy in enumerate(c["systems"]):
         st = sts[k]
-        assert st["status"] == 0 and st["stop_reason"] in (1, 3), k
+        assert st["status"] == 0 and st["stop_reason"] in (1, 2), k
         rr = _host_relres(sy["A"], sy["b"], xs[k])
         # the solver's residual is double-double, the host's FP64
         assert abs(rr - st["relres"][-1]) <= 1e-11 + 1e-2 * rr, (k, rr, st["relres"][-1])
