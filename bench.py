@@ -167,6 +167,18 @@ def main():
                 "frac": nbytes / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic(kernel_src),
                 "algorithmic_bytes": nbytes, "kernel_ms": kern_ms}
 
+    # the latency bound of the persistent solver: its dependent grid-wide
+    # exchanges (each MGS pass and norm is an all-reduction, each published
+    # vector a barrier) times the measured cost of one exchange
+    G = B.solve_blocks(n)
+    ex_us = B.exchange_latency_us(G)
+    n_ex = 3 + sum(6 + sum(j + 4 for j in range(k)) for k in stats["its"])
+    latency = {"blocks": G, "exchange_us": ex_us, "exchanges_per_solve": n_ex,
+               "floor_ms": n_ex * ex_us * 1e-3, "frac": n_ex * ex_us * 1e-3 / kern_ms}
+    _log(f"latency floor: {n_ex} exchanges x {ex_us:.2f} us = {n_ex * ex_us * 1e-3:.1f} ms "
+         f"({100 * latency['frac']:.0f}% of the kernel time)")
+    roofline["latency_floor"] = latency
+
     out = {"metric": "GMRES-IR solves/s & M-apply HBM GB/s, BSPAI vs fp64 SPAI at equal backward error",
            "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

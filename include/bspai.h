@@ -259,6 +259,16 @@ int bspai_grad_vals(const bspai_pattern *A, const double *lam, const double *x, 
 void bspai_set_profiling(int on);
 double bspai_last_solve_kernel_ms(void);
 
+/*
+ * bspai_exchange_latency -- the latency floor of the persistent solver: runs
+ * `iters` dependent grid-wide FP64 all-reductions by G co-resident blocks of
+ * the solver's size with the solver's own exchange, and writes the average
+ * time of one to *us_out (microseconds, host pointer).  Synchronises `stream`.
+ * bspai_solve_blocks -- the number of blocks gmres_ir_solve uses for n rows.
+ */
+int bspai_exchange_latency(int G, int iters, double *us_out, void *stream);
+int bspai_solve_blocks(int n);
+
 /* bspai_free -- release a handle (NULL is ignored).  Waits for the device. */
 void bspai_free(bspai_handle *M);
 

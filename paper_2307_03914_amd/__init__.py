@@ -93,6 +93,10 @@ _lib.bspai_last_error.restype = C.c_char_p
 _lib.bspai_set_profiling.argtypes = [C.c_int]
 _lib.bspai_set_profiling.restype = None
 _lib.bspai_last_solve_kernel_ms.restype = C.c_double
+_lib.bspai_exchange_latency.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), _vp]
+_lib.bspai_exchange_latency.restype = C.c_int
+_lib.bspai_solve_blocks.argtypes = [C.c_int]
+_lib.bspai_solve_blocks.restype = C.c_int
 _lib.bspai_multi_plan.argtypes = [C.POINTER(_System), C.c_int, C.POINTER(_Tol), C.c_int, C.c_int, C.POINTER(_vp),
                                   _vp]
 _lib.bspai_multi_launch.argtypes = [_vp, _vp]
@@ -109,12 +113,26 @@ for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
 SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
            "bspai_export", "bspai_free", "bspai_last_error", "bspai_grad_vals", "bspai_set_profiling",
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
-           "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks")
+           "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
+           "bspai_solve_blocks")
 
 
 def set_profiling(on: bool) -> None:
     """Time the solver kernel of each gmres_ir_solve with HIP events."""
     _lib.bspai_set_profiling(int(on))
+
+
+def exchange_latency_us(G: int, iters: int = 20000, stream=None) -> float:
+    """Average time of one grid-wide all-reduction of the persistent solver
+    with G blocks (bspai_exchange_latency)."""
+    out = C.c_double(0.0)
+    _check(_lib.bspai_exchange_latency(int(G), int(iters), C.byref(out), _stream(stream)))
+    return out.value
+
+
+def solve_blocks(n: int) -> int:
+    """Blocks of the persistent solver for n rows (bspai_solve_blocks)."""
+    return _check_int(_lib.bspai_solve_blocks(int(n)))
 
 
 def last_solve_kernel_ms() -> float:
@@ -131,6 +149,13 @@ def _check(code: int, allow=()):
     if code != OK and code not in allow:
         raise BSPAIError(code, _lib.bspai_last_error().decode(errors="replace"))
     return code
+
+
+def _check_int(value: int) -> int:
+    """Calls that return a count on success and a negative status on failure."""
+    if value < 0:
+        raise BSPAIError(value, _lib.bspai_last_error().decode(errors="replace"))
+    return value
 
 
 def _stream(stream=None) -> int:

@@ -1040,6 +1040,71 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
 
 using namespace bspai;
 
+// Instrumentation: `iters` back-to-back all-reductions of one FP64 value by G
+// blocks of the solver's size, with the solver's own grid_reduce.
+__global__ void __launch_bounds__(kSolveThreads) k_exchange_probe(Grid g, int iters, double *out) {
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
+  unsigned rtag = 0;
+  double acc = 0.0;
+  for (int it = 0; it < iters; it++) {
+    double v[1] = {(double)((threadIdx.x + it) & 7)};
+    if (!grid_reduce<1, false>(g, rtag, v, sh, blockIdx.x)) return;
+    acc += v[0];
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+extern "C" int bspai_exchange_latency(int G, int iters, double *us_out, void *stream) {
+  if (G < 1 || G > kMaxBlocks || iters < 1 || !us_out)
+    return fail(BSPAI_EINVAL, "bspai_exchange_latency: need 1 <= G <= %d, iters >= 1", kMaxBlocks);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void *mem = nullptr;
+  const size_t bytes = kSlotBytes + 256 + 8 * (size_t)kMaxBlocks;
+  int rc = dalloc(&mem, bytes);
+  if (rc) return rc;
+  Grid g;
+  g.slots = static_cast<double *>(mem);
+  g.abortf = reinterpret_cast<unsigned *>(static_cast<char *>(mem) + kSlotBytes);
+  g.flags = nullptr;
+  g.G = G;
+  double *out = reinterpret_cast<double *>(static_cast<char *>(mem) + kSlotBytes + 256);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto body = [&]() -> int {
+    BSPAI_HIP(hipMemsetAsync(mem, 0, bytes, s));
+    BSPAI_HIP(hipEventCreate(&e0));
+    BSPAI_HIP(hipEventCreate(&e1));
+    void *args[] = {&g, &iters, &out};
+    BSPAI_HIP(hipEventRecord(e0, s));
+    BSPAI_HIP(hipLaunchCooperativeKernel((void *)k_exchange_probe, dim3(G), dim3(kSolveThreads), args, 0, s));
+    BSPAI_HIP(hipEventRecord(e1, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    BSPAI_HIP(hipEventElapsedTime(&ms, e0, e1));
+    unsigned ab = 0;
+    BSPAI_HIP(hipMemcpy(&ab, g.abortf, 4, hipMemcpyDeviceToHost));
+    if (ab) return fail(BSPAI_EHIP, "bspai_exchange_latency: an exchange timed out");
+    *us_out = ms * 1e3 / iters;
+    return BSPAI_OK;
+  };
+  rc = body();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  dfree(mem);
+  return rc;
+}
+
+extern "C" int bspai_solve_blocks(int n) {
+  if (n < 1) return fail(BSPAI_EINVAL, "bspai_solve_blocks: n < 1");
+  int G = std::min(kMaxBlocks, std::max(1, (n + 2 * kSolveThreads - 1) / (2 * kSolveThreads)));
+  if (const char *e = getenv("BSPAI_SOLVE_BLOCKS")) G = std::min(kMaxBlocks, std::max(1, atoi(e)));
+  int rpb = rows_for(n, G);
+  while ((rpb + kSolveThreads - 1) / kSolveThreads > 16 && G < kMaxBlocks) {
+    G = std::min(kMaxBlocks, G * 2);
+    rpb = rows_for(n, G);
+  }
+  return (n + rpb - 1) / rpb;
+}
+
 extern "C" void bspai_set_profiling(int on) { g_profile = on ? 1 : 0; }
 extern "C" double bspai_last_solve_kernel_ms(void) { return g_last_ms; }
 

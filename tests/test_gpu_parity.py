@@ -836,6 +836,18 @@ def test_theta_gradient_full_size(B):
     _theta_case(B, c, kw, 4, False)
 
 
+def test_exchange_latency_instrumentation(B):
+    """The solver's block count for n rows and the cost of one of its
+    grid-wide exchanges (a few microseconds on one GPU)."""
+    assert B.solve_blocks(65536) == 64
+    assert B.solve_blocks(1) == 1
+    us = B.exchange_latency_us(64, 2000)
+    assert 0.1 < us < 100.0
+    assert 0.05 < B.exchange_latency_us(1, 2000) < 100.0
+    with pytest.raises(B.BSPAIError):
+        B.exchange_latency_us(0, 10)
+
+
 # ---------------------------------------------------------------- block path
 
 def test_build_powerlaw_small_all_rows(B):
