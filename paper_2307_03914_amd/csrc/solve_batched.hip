@@ -206,6 +206,104 @@ __global__ void __launch_bounds__(kBT) k_b_mgs(Cols cc, int n, VT *z, const VT *
   block_cols<false>(cc, s, sh, part);
 }
 
+// 4 consecutive columns per thread (R a multiple of 4): 16-byte loads and
+// stores of z and the basis (two per 4 doubles).  Threads t < rpp * tpr work:
+// tpr = R / 4 threads per row, rpp rows per block and pass.
+template <typename VT>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  __device__ static void load(const float *p, double (&v)[4]) {
+    float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+  }
+  __device__ static void store(float *p, const float (&v)[4]) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <>
+struct Vec4<double> {
+  __device__ static void load(const double *p, double (&v)[4]) {
+    double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+  }
+  __device__ static void store(double *p, const double (&v)[4]) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+  }
+};
+
+// the per-column partials of a block of 4-column threads, fixed order
+__device__ __forceinline__ void block_cols4(int R, int tpr, int rpp, const double (&acc)[4], double *sh, double *part) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; u++) sh[4 * t + u] = acc[u];
+  __syncthreads();
+  if (t < R) {
+    const int cg = t / 4, u = t % 4;
+    double a = sh[4 * cg + u];
+    for (int g = 1; g < rpp; g++) a += sh[4 * (g * tpr + cg) + u];
+    part[(int64_t)blockIdx.x * R + t] = a;
+  }
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(kBT) k_b_mgs4(int R, int n, VT *z, const VT *vprev, const double *hprev,
+                                                const VT *vcur, double *part) {
+  __shared__ double sh[4 * kBT];
+  const int tpr = R / 4, rpp = kBT / tpr;
+  const int g = threadIdx.x / tpr, c0 = 4 * (threadIdx.x % tpr);
+  double hp[4] = {0.0, 0.0, 0.0, 0.0}, acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (vprev && g < rpp)
+#pragma unroll
+    for (int u = 0; u < 4; u++) hp[u] = hprev[c0 + u];
+  if (g < rpp) {
+    for (int64_t i = (int64_t)blockIdx.x * rpp + g; i < n; i += (int64_t)gridDim.x * rpp) {
+      const int64_t e = i * R + c0;
+      double zz[4];
+      Vec4<VT>::load(z + e, zz);
+      if (vprev) {
+        double vp[4];
+        Vec4<VT>::load(vprev + e, vp);
+        VT zo[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          zo[u] = (VT)fma(-hp[u], vp[u], zz[u]);
+          zz[u] = (double)zo[u];
+        }
+        Vec4<VT>::store(z + e, zo);
+      }
+      if (vcur) {
+        double vc[4];
+        Vec4<VT>::load(vcur + e, vc);
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc[u] = fma(vc[u], zz[u], acc[u]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc[u] = fma(zz[u], zz[u], acc[u]);
+      }
+    }
+  }
+  block_cols4(R, tpr, rpp, acc, sh, part);
+}
+
+// v = z / h per column, 4 columns per thread
+template <typename VT>
+__global__ void k_b_scale4(int R, int64_t nr, const VT *z, const double *h, VT *v) {
+  int64_t e = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (e >= nr) return;
+  const int c0 = (int)(e % R);
+  double zz[4];
+  Vec4<VT>::load(z + e, zz);
+  VT o[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) {
+    const double hh = h[c0 + u];
+    o[u] = hh > 0.0 ? (VT)(zz[u] / hh) : (VT)0;
+  }
+  Vec4<VT>::store(v + e, o);
+}
+
 // Givens step j for every column (one thread per column).  H column j holds
 // h_{0..j+1, j} on entry; rotated in place.  Writes res[c] = |g_{j+1}|.
 __global__ void k_b_givens(int R, int m, int j, double *H, double *cs, double *sn, double *g, const int *gm_active,
@@ -326,6 +424,12 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   while (cc.Rp < R) cc.Rp <<= 1;
   const int nblk = (int)std::min<int64_t>(kBGrid, (n + (kBT / cc.Rp) - 1) / (kBT / cc.Rp));
   const unsigned eg = (unsigned)((nr + 255) / 256);
+  // 4-column kernels for the per-iteration passes when R is a multiple of 4
+  // (rows of R values then start 16-byte aligned); they use the same
+  // fixed-order per-column reduction
+  const bool vec4 = R % 4 == 0;
+  const int rpp4 = vec4 ? kBT / (R / 4) : 1;
+  const int nblk4 = (int)std::min<int64_t>(kBGrid, (n + rpp4 - 1) / rpp4);
 
   // operators: A (or A^T) in FP64 and in u_g, M_b (or M_b^T), FP64 M for x_0
   DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb;
@@ -371,11 +475,12 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   const int fp64 = sizeof(VT) == 8;
 
   auto finish = [&](bool mx, const double *part, double *out, int sq, double *out2 = nullptr,
-                    int64_t stride2 = 0) -> int {
+                    int64_t stride2 = 0, int nparts = 0) -> int {
+    const int np = nparts > 0 ? nparts : nblk;  // blocks that wrote partials
     if (mx)
-      hipLaunchKernelGGL(k_finish<true>, dim3(R), dim3(kBT), 0, s, R, nblk, part, out, sq, out2, stride2);
+      hipLaunchKernelGGL(k_finish<true>, dim3(R), dim3(kBT), 0, s, R, np, part, out, sq, out2, stride2);
     else
-      hipLaunchKernelGGL(k_finish<false>, dim3(R), dim3(kBT), 0, s, R, nblk, part, out, sq, out2, stride2);
+      hipLaunchKernelGGL(k_finish<false>, dim3(R), dim3(kBT), 0, s, R, np, part, out, sq, out2, stride2);
     BSPAI_CHECK_LAUNCH();
     return BSPAI_OK;
   };
@@ -484,13 +589,22 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
         const VT *vprev = i > 0 ? V + (int64_t)(i - 1) * nr : nullptr;
         const VT *vcur = i <= j ? V + (int64_t)i * nr : nullptr;
         const double *hprev = S + 5 * R;
-        hipLaunchKernelGGL(k_b_mgs<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, Z, vprev, hprev, vcur, P1);
+        if (vec4)
+          hipLaunchKernelGGL(k_b_mgs4<VT>, dim3(nblk4), dim3(kBT), 0, s, R, n, Z, vprev, hprev, vcur, P1);
+        else
+          hipLaunchKernelGGL(k_b_mgs<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, Z, vprev, hprev, vcur, P1);
         BSPAI_CHECK_LAUNCH();
         // the finished scalar goes to S row 5 (next pass) and into H column j
-        if ((rc = finish(false, P1, S + 5 * R, i > j, H + (int64_t)j * (m + 1) + i, (int64_t)m * (m + 1)))) return rc;
+        if ((rc = finish(false, P1, S + 5 * R, i > j, H + (int64_t)j * (m + 1) + i, (int64_t)m * (m + 1),
+                         vec4 ? nblk4 : nblk)))
+          return rc;
       }
       // v_{j+1} = z / h_{j+1,j}
-      hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, Z, S + 5 * R, V + (int64_t)(j + 1) * nr);
+      if (vec4)
+        hipLaunchKernelGGL(k_b_scale4<VT>, dim3((unsigned)((nr / 4 + 255) / 256)), dim3(256), 0, s, R, nr, Z,
+                           S + 5 * R, V + (int64_t)(j + 1) * nr);
+      else
+        hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, Z, S + 5 * R, V + (int64_t)(j + 1) * nr);
       BSPAI_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_b_givens, dim3(1), dim3(64), 0, s, R, m, j, H, CS, SN, G, GMA, S + 6 * R);
       BSPAI_CHECK_LAUNCH();

@@ -387,15 +387,18 @@ def test_solve_batched_matches_oracle(B):
     h.free()
 
 
-def test_solve_batched_columns_independent(B):
-    """Three columns (not a power of two): a repeated column gives the same
-    bits, a zero column stops at once, and each column agrees with the
-    single-RHS path."""
+@pytest.mark.parametrize("ncols", [3, 4])
+def test_solve_batched_columns_independent(B, ncols):
+    """Three columns (the one-column-per-thread kernels) or four (the
+    four-columns-per-thread ones): a repeated column gives the same bits, a
+    zero column stops at once, and each column agrees with the single-RHS
+    path."""
     c = W.config("2", small=True)
     A, P, b = c["A"], c["P"], c["b"]
-    _say("solve batched independence")
+    _say("solve batched independence", ncols)
     kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
-    Bm = np.stack([b, np.zeros_like(b), b], axis=1)
+    cols = [b, np.zeros_like(b), b] + ([0.5 * b + 1.0] if ncols == 4 else [])
+    Bm = np.stack(cols, axis=1)
     xg, sts, h = _solve_case(B, A, P, Bm, c["precs"], c["eps"][1], **kw)
     assert np.array_equal(xg[:, 0], xg[:, 2])
     assert sts[0] == sts[2]
