@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-RHS and the 32-system measurements")
     ap.add_argument("--only-apply", action="store_true", help="run only the cold bucketed-apply measurement")
+    ap.add_argument("--only-batched", action="store_true", help="run only the 64-RHS measurement")
+    ap.add_argument("--only-multi", action="store_true", help="run only the 32-system measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy first (calibration of hardware byte counters)")
     args = ap.parse_args()
@@ -120,6 +122,13 @@ def main():
     if args.only_apply:
         res = apply_bench(B, W, torch, np)
         print(json.dumps({"m_apply": res}), flush=True)
+        return
+    kw0 = dict(tau=1e-4, tol_rr=1e-10, gmres_max=args.gmres_max, i_max=20)
+    if args.only_batched:
+        print(json.dumps({"batched_rhs": batched_bench(B, W, torch, np, kw0)}), flush=True)
+        return
+    if args.only_multi:
+        print(json.dumps({"multi_system": multi_bench(B, W, torch, np, kw0)}), flush=True)
         return
     _log("generating workload")
     c = W.config("2")
@@ -319,8 +328,18 @@ def batched_bench(B, W, torch, np, kw):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     nr = Bm.shape[1]
+    # the MGS passes of the call: a correction runs as many Arnoldi steps as
+    # its slowest column; step j makes j + 2 passes over n x R values of u_g:
+    # z and v_0 read; z, v_{i-1}, v_i read and z written; z and v_j read and
+    # z written
+    steps = max(q["steps"] for q in sts)
+    per_step = [max(q["its"][i] for q in sts if q["steps"] > i) for i in range(steps)]
+    vec = A.n * nr * 4
+    mgs_passes = sum(j + 2 for k in per_step for j in range(k))
+    mgs_bytes = sum((4 * j + 5) * vec for k in per_step for j in range(k))
     res = {"workload": f"aniso3d 128^3 (1:10:100, n={A.n}), {nr} RHS N(0,1), buckets fp32/bf16/fp16 eps=1e-2",
            "rhs_per_s": nr / el, "s_per_call": el, "single_rhs_per_s": 1.0 / single,
+           "arnoldi_steps_per_correction": per_step, "mgs_passes": mgs_passes, "mgs_algorithmic_bytes": mgs_bytes,
            "its_col0": sts[0]["its"], "max_steps": max(q["steps"] for q in sts),
            "max_relres": max(q["relres"][-1] for q in sts), "all_converged": all(q["status"] == 0 for q in sts)}
     del x, Bm

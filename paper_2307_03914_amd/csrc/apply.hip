@@ -312,6 +312,77 @@ __global__ void __launch_bounds__(kApplyThreads) k_bspmm(BMat M, const XT *__res
   }
 }
 
+// Many right-hand sides with R a multiple of 4 (row-major, ld a multiple of
+// 4): R / 4 lanes per row, each owning 4 consecutive columns, so a wavefront
+// works on several rows; per bucket a row's columns and values are loaded 8
+// at a time ahead of their 16-byte gathers of x.  Same order of operations as
+// bspmm_row (entries in CSR order, per-bucket FP32 or FP64 accumulation,
+// buckets added in FP64 from the least precise).
+template <typename XT>
+__device__ __forceinline__ void ld4(const XT *p, double (&v)[4]) {
+  if (sizeof(XT) == 4) {
+    float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+  } else {
+    double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+  }
+}
+
+template <typename XT>
+__global__ void __launch_bounds__(kApplyThreads) k_bspmm4(BMat M, const XT *__restrict__ x, XT *__restrict__ y,
+                                                          int64_t ld, int nrhs) {
+  const int tpr = nrhs / 4, rpb = kApplyThreads / tpr;
+  const int g = threadIdx.x / tpr, c0 = 4 * (threadIdx.x % tpr);
+  const int i = xcd_block(blockIdx.x, gridDim.x) * rpb + g;
+  if (g >= rpb || i >= M.n) return;
+  double total[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < M.nb; k++) {
+    const int s = M.rp[k][i], e = M.rp[k][i + 1];
+    const int32_t *col = M.col[k];
+    const bool wide = M.prec[k] == BSPAI_FP64 || sizeof(XT) == 8;
+    double accd[4] = {0.0, 0.0, 0.0, 0.0};
+    float accf[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int p0 = s; p0 < e; p0 += 8) {
+      int cc[8];
+      double vv[8];
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        const int p = p0 + t < e ? p0 + t : s;
+        cc[t] = col[p];
+        vv[t] = M.prec[k] == BSPAI_FP64 ? static_cast<const double *>(M.val[k])[p] : (double)load_value_f32(M, k, p);
+      }
+      double xv[8][4];
+#pragma unroll
+      for (int t = 0; t < 8; t++) ld4<XT>(x + (int64_t)cc[t] * ld + c0, xv[t]);
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        if (p0 + t < e) {
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            if (wide)
+              accd[u] = fma(vv[t], xv[t][u], accd[u]);
+            else
+              accf[u] = fmaf((float)vv[t], (float)xv[t][u], accf[u]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) total[u] += (wide ? accd[u] : (double)accf[u]) * M.scale[k];
+  }
+  XT o[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) o[u] = (XT)total[u];
+  XT *yp = y + (int64_t)i * ld + c0;
+  if (sizeof(XT) == 4) {
+    *reinterpret_cast<float4 *>(yp) = make_float4((float)o[0], (float)o[1], (float)o[2], (float)o[3]);
+  } else {
+    reinterpret_cast<double2 *>(yp)[0] = make_double2((double)o[0], (double)o[1]);
+    reinterpret_cast<double2 *>(yp)[1] = make_double2((double)o[2], (double)o[3]);
+  }
+}
+
 int bmat_aligned(const BMat &M) {
   for (int k = 0; k < M.nb; k++)
     if ((reinterpret_cast<uintptr_t>(M.col[k]) & 15) || (reinterpret_cast<uintptr_t>(M.val[k]) & 15)) return 0;
@@ -394,6 +465,19 @@ int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, in
     int lanes = M.lanes > 0 ? M.lanes : pick_lanes(M, M.nnz);
     return fp64 ? launch_vec<double>(M, static_cast<const double *>(x), static_cast<double *>(y), lanes, s)
                 : launch_vec<float>(M, static_cast<const float *>(x), static_cast<float *>(y), lanes, s);
+  }
+  if (nrhs % 4 == 0 && nrhs <= 64 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0 &&
+      (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
+    const int rpb = kApplyThreads / (nrhs / 4);
+    const int64_t nblk = (M.n + rpb - 1) / rpb;
+    if (fp64)
+      hipLaunchKernelGGL(k_bspmm4<double>, dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M,
+                         static_cast<const double *>(x), static_cast<double *>(y), ld, nrhs);
+    else
+      hipLaunchKernelGGL(k_bspmm4<float>, dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M,
+                         static_cast<const float *>(x), static_cast<float *>(y), ld, nrhs);
+    BSPAI_CHECK_LAUNCH();
+    return BSPAI_OK;
   }
   int group = 1;
   while (group < nrhs && group < 64) group <<= 1;
