@@ -178,12 +178,19 @@ int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, c
  *   A_k^T for trans) into device memory it owns, so A_k's values are read
  *   now; b_k and x_k are read and written at every launch and must stay
  *   allocated until bspai_multi_free.  The grid is cut into groups of
- *   group_blocks blocks (0: the smallest group that holds the largest system
- *   at 16 rows per thread; -1: autotune, i.e. plan that size and its
- *   doublings up to 256, run each once, timed with HIP events, and keep the
- *   fastest, which writes every x_k); each group takes the next system off a
- *   device queue, largest first, until the queue is empty.  max_groups (0: as
- *   many as the device keeps resident, at most nsys) caps the number of groups.
+ *   blocks; each group takes the next system of its class off that class's
+ *   device queue, largest first, until the queue is empty.
+ *   group_blocks > 0: one class, every group of that many blocks (at least
+ *   what keeps the largest system within 16 rows per thread).
+ *   group_blocks = 0: size classes, each system solved by a group of the
+ *   smallest power of two of blocks that keeps it within 8 rows per thread;
+ *   the resident blocks are shared among the classes by estimated load
+ *   (sqrt(n) times the exchange cost of the group size), a class that does
+ *   not fit joining the next larger one.
+ *   group_blocks = -1: autotune, i.e. plan size classes and one group size
+ *   (the smallest above and its doublings up to 256), run each once, timed
+ *   with HIP events, and keep the fastest (this writes every x_k).
+ *   max_groups (0: no limit) caps the number of groups.
  *   The launch is captured once into a HIP graph.  Synchronises `stream`.
  *   Results do not depend on which group takes a system, so replays with the
  *   same b_k give identical bits.  EINVAL when a group does not fit on the
@@ -211,7 +218,8 @@ int bspai_multi_launch(bspai_multi *plan, void *stream);
 int bspai_multi_poll(const bspai_multi *plan);
 int bspai_multi_wait(bspai_multi *plan, gmres_ir_stats *st_host, void *stream);
 void bspai_multi_free(bspai_multi *plan);
-/* bspai_multi_group_blocks -- the group size a plan uses (after autotuning). */
+/* bspai_multi_group_blocks -- the group size of a one-class plan (after
+ * autotuning), 0 for a plan with size classes. */
 int bspai_multi_group_blocks(const bspai_multi *plan);
 
 typedef struct {

@@ -780,23 +780,29 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
 
 // ------------------------------------------------------------------ many systems
 
-// Several independent systems in one persistent launch.  The grid is cut into
-// groups of group_blocks blocks; each group takes the next system off a device
-// queue (largest systems first), solves it with the single-system body on its
-// own barrier and exchange words, and goes back to the queue until it is
-// empty.  Results do not depend on which group solves a system: every group
-// has the same size, so the row split and the reduction order of a system are
-// fixed by the plan.
+// Several independent systems in one persistent launch.  The systems fall
+// into classes by the group size that solves them; the grid is cut into
+// groups of those sizes, each group belonging to one class.  A group takes
+// the next system of its class off that class's device queue (largest
+// first), solves it with the single-system body on its own barrier and
+// exchange words, and goes back to the queue until it is empty.  Results do
+// not depend on which group solves a system: all groups of a class have the
+// same size, so the row split and the reduction order of a system are fixed
+// by the plan.
 template <typename VT>
 struct MultiParams {
   const SolveParams<VT> *sys;  // [nsys]
-  const int *order;            // queue position -> system
+  const int *order;            // systems by class, each class largest first
+  const int *class_off;        // [nclass + 1]: class c owns order[class_off[c] .. class_off[c + 1])
   const Grid *grids;           // [ngroups]
-  unsigned *queue;             // next queue position (cleared per launch)
-  unsigned *groups_done;       // groups that have left the queue (cleared per launch)
+  const int *group_class;      // [ngroups]
+  const int *block_group;      // [grid size]: group of each block
+  const int *block_local;      // [grid size]: index of the block within its group
+  unsigned *queues;            // [nclass]: next queue position per class (cleared per launch)
+  unsigned *groups_done;       // groups that have left their queue (cleared per launch)
   const unsigned *seq;         // launches so far (advanced by the clear kernel)
   unsigned *done_host;         // host word: seq of the last launch that has finished
-  int nsys, group_blocks, ngroups;
+  int ngroups;
 };
 
 template <typename VT, typename PT, int ZR>
@@ -804,18 +810,20 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_multi(const MultiParams
   extern __shared__ double sm[];
   __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
   __shared__ int s_flag;
-  const int group = blockIdx.x / mp->group_blocks, bid = blockIdx.x % mp->group_blocks;
+  const int group = mp->block_group[blockIdx.x], bid = mp->block_local[blockIdx.x];
+  const int cls = mp->group_class[group];
+  const int first = mp->class_off[cls], count = mp->class_off[cls + 1] - first;
   const Grid G = mp->grids[group];
   unsigned epoch = 0, rtag = 0;
   for (;;) {
     // the group's first block takes a queue position; the all-reduction (max
     // of it and zeros) hands it to every block of the group
     double q[1] = {0.0};
-    if (bid == 0 && threadIdx.x == 0) q[0] = (double)atomicAdd(mp->queue, 1u);
+    if (bid == 0 && threadIdx.x == 0) q[0] = (double)atomicAdd(&mp->queues[cls], 1u);
     if (!grid_reduce<1, true>(G, rtag, q, sh, bid)) break;
     const int k = (int)q[0];
-    if (k >= mp->nsys) break;
-    if (!gmres_ir_body<VT, PT, ZR>(mp->sys[mp->order[k]], G, bid, epoch, rtag, sm, sh, s_flag)) break;
+    if (k >= count) break;
+    if (!gmres_ir_body<VT, PT, ZR>(mp->sys[mp->order[first + k]], G, bid, epoch, rtag, sm, sh, s_flag)) break;
   }
   if (bid == 0 && threadIdx.x == 0) {
     unsigned d = atomicAdd(mp->groups_done, 1u);
@@ -879,6 +887,18 @@ static void multi_release(bspai_multi *P) {
   delete P;
 }
 
+// smallest power-of-two group that keeps n rows within 8 rows per thread
+static int class_blocks(int n) {
+  const int need = (n + 8 * kSolveThreads - 1) / (8 * kSolveThreads);
+  int g = 1;
+  while (g < need) g <<= 1;
+  return std::min(g, kMaxBlocks);
+}
+
+// rough cost of one exchange by a group of g blocks (microseconds, measured
+// on MI355X: 1.3 for one block ... 2.5 for 48); only ratios matter
+static double exchange_cost(int g) { return 1.3 + 0.25 * std::log2((double)std::max(g, 1)); }
+
 template <typename VT>
 static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_tol *tol, int group_blocks,
                             int max_groups, bspai_multi **out, hipStream_t s) {
@@ -887,75 +907,151 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
   for (int k = 0; k < nsys; k++) nmax = std::max(nmax, sys[k].A.n);
   // smallest group that keeps every system within 16 rows per thread
   const int gmin = (nmax + kSolveThreads * 16 - 1) / (kSolveThreads * 16);
-  int gb = group_blocks > 0 ? group_blocks : gmin;
-  if (gb < gmin || gb > kMaxBlocks)
+  if (group_blocks > 0 && (group_blocks < gmin || group_blocks > kMaxBlocks))
     return fail(BSPAI_EINVAL, "bspai_multi_plan: group_blocks must be in %d..%d for n up to %d", gmin, kMaxBlocks,
                 nmax);
-  int ZR = 1, mmax = 1;
-  std::vector<int> ms(nsys), rpbs(nsys);
-  bool wide = sizeof(VT) == 8;
-  for (int k = 0; k < nsys; k++) {
-    const int n = sys[k].A.n;
-    ms[k] = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
-    mmax = std::max(mmax, ms[k]);
-    rpbs[k] = rows_for(n, gb);
-    while (ZR * kSolveThreads < rpbs[k]) ZR <<= 1;
-    const BMat &Mb = tr ? sys[k].M->matT : sys[k].M->mat;
-    for (int q = 0; q < Mb.nb; q++) wide = wide || Mb.prec[q] == BSPAI_FP64;
-  }
-  const size_t lds = solve_lds(mmax);
-  void *fn = pick_multi<VT>(wide, ZR);
-  BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (nmax > kMaxBlocks * kSolveThreads * 16)
+    return fail(BSPAI_EINVAL, "bspai_multi_plan: n = %d exceeds %d rows", nmax, kMaxBlocks * kSolveThreads * 16);
+  // group size of each system: one size for all (group_blocks > 0) or its class
+  std::vector<int> gs(nsys);
+  for (int k = 0; k < nsys; k++)
+    gs[k] = group_blocks > 0 ? group_blocks : class_blocks(sys[k].A.n);
   int dev = 0, per_cu = 0;
   hipDeviceProp_t prop;
   BSPAI_HIP(hipGetDevice(&dev));
   BSPAI_HIP(hipGetDeviceProperties(&prop, dev));
-  BSPAI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSolveThreads, lds));
-  // every block of the grid must be resident at once (the groups wait on each other's blocks)
-  const int resident = per_cu * prop.multiProcessorCount;
-  int ng = std::min(nsys, resident / gb);
-  if (max_groups > 0) ng = std::min(ng, max_groups);
-  if (ng < 1) return fail(BSPAI_EINVAL, "bspai_multi_plan: a group of %d blocks does not fit on the device", gb);
+  // kernel variant and residency (needs the row split: settle the classes first)
+  auto classes_of = [&](std::vector<int> &sizes) {
+    std::vector<int> c(sizes);
+    std::sort(c.begin(), c.end(), std::greater<int>());
+    c.erase(std::unique(c.begin(), c.end()), c.end());
+    return c;
+  };
+  std::vector<int> csize = classes_of(gs);
+  int ZR = 1, mmax = 1;
+  bool wide = sizeof(VT) == 8;
+  void *fn = nullptr;
+  size_t lds = 0;
+  int resident = 0;
+  auto settle_kernel = [&]() -> int {
+    ZR = 1, mmax = 1;
+    for (int k = 0; k < nsys; k++) {
+      const int n = sys[k].A.n;
+      mmax = std::max(mmax, std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres)));
+      while (ZR * kSolveThreads < rows_for(n, gs[k])) ZR <<= 1;
+      const BMat &Mb = tr ? sys[k].M->matT : sys[k].M->mat;
+      for (int q = 0; q < Mb.nb; q++) wide = wide || Mb.prec[q] == BSPAI_FP64;
+    }
+    lds = solve_lds(mmax);
+    fn = pick_multi<VT>(wide, ZR);
+    BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    BSPAI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSolveThreads, lds));
+    // every block of the grid must be resident at once (a group waits on its blocks)
+    resident = per_cu * prop.multiProcessorCount;
+    return BSPAI_OK;
+  };
+  int rc = settle_kernel();
+  if (rc) return rc;
+  // one group per class must fit (and no more classes than max_groups):
+  // otherwise the smallest class joins the next larger one
+  auto fits = [&]() {
+    int need = 0;
+    for (int g : csize) need += g;
+    return need <= resident && (max_groups <= 0 || (int)csize.size() <= max_groups);
+  };
+  while (!fits() && csize.size() > 1) {
+    const int small = csize.back(), next = csize[csize.size() - 2];
+    for (int &g : gs)
+      if (g == small) g = next;
+    csize.pop_back();
+  }
+  if (!fits())
+    return fail(BSPAI_EINVAL, "bspai_multi_plan: a group of %d blocks does not fit on the device (%d resident)",
+                csize[0], resident);
+  if ((rc = settle_kernel())) return rc;  // the row split may have changed
+  const int nclass = (int)csize.size();
+  std::vector<int> cls(nsys), ccount(nclass, 0);
+  std::vector<double> cload(nclass, 0.0);
+  for (int k = 0; k < nsys; k++) {
+    cls[k] = (int)(std::find(csize.begin(), csize.end(), gs[k]) - csize.begin());
+    ccount[cls[k]]++;
+    // a system's cost: iterations grow about like the grid side, each costs
+    // a few exchanges of its group
+    cload[cls[k]] += std::sqrt((double)sys[k].A.n) * exchange_cost(gs[k]);
+  }
+  // groups per class: start with one each, then give groups to the class
+  // with the largest load per group while blocks remain
+  std::vector<int> kc(nclass, 1);
+  int blocks = 0, ngroups = nclass;
+  for (int c = 0; c < nclass; c++) blocks += csize[c];
+  for (;;) {
+    int best = -1;
+    double bl = 0.0;
+    for (int c = 0; c < nclass; c++) {
+      if (kc[c] >= ccount[c] || blocks + csize[c] > resident) continue;
+      if (max_groups > 0 && ngroups >= max_groups) continue;
+      const double l = cload[c] / kc[c];
+      if (best < 0 || l > bl) best = c, bl = l;
+    }
+    if (best < 0) break;
+    kc[best]++, ngroups++, blocks += csize[best];
+  }
+  // systems by class, largest first within a class
+  std::vector<int> order(nsys), coff(nclass + 1, 0);
+  for (int k = 0; k < nsys; k++) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (cls[a] != cls[b]) return cls[a] < cls[b];
+    return sys[a].A.n > sys[b].A.n;
+  });
+  for (int c = 0; c < nclass; c++) coff[c + 1] = coff[c] + ccount[c];
+  std::vector<int> gclass(ngroups), bgroup(blocks), blocal(blocks), gfirst(ngroups);
+  for (int c = 0, gi = 0, fb = 0; c < nclass; c++) {
+    for (int i = 0; i < kc[c]; i++, gi++) {
+      gclass[gi] = c;
+      gfirst[gi] = fb;
+      for (int t = 0; t < csize[c]; t++, fb++) bgroup[fb] = gi, blocal[fb] = t;
+    }
+  }
 
-  // memory: per-system workspaces, parameters, then the per-launch state
+  // memory: per-system workspaces, parameters, maps, then the per-launch state
   std::vector<SysLayout> L(nsys);
   std::vector<size_t> base(nsys);
   size_t off = 0;
   for (int k = 0; k < nsys; k++) {
-    L[k] = sys_layout<VT>(sys[k].A.n, sys[k].A.nnz, ms[k], tr);
+    L[k] = sys_layout<VT>(sys[k].A.n, sys[k].A.nnz, std::min(std::max(tol->gmres_max, 1), std::min(sys[k].A.n, kMaxGmres)), tr);
     base[k] = off;
     off += L[k].total;
   }
-  const size_t o_params = off;
-  off += align256(sizeof(SolveParams<VT>) * nsys);
-  const size_t o_order = off;
-  off += align256(4 * (size_t)nsys);
-  const size_t o_grids = off;
-  off += align256(sizeof(Grid) * ng);
-  const size_t o_mp = off;
-  off += align256(sizeof(MultiParams<VT>));
-  const size_t o_seq = off;
-  off += 256;
-  // per-launch state, cleared by k_multi_clear: queue, groups_done, aborts, stats, flags, slots
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t o_params = take(sizeof(SolveParams<VT>) * nsys);
+  const size_t o_order = take(4 * (size_t)nsys);
+  const size_t o_coff = take(4 * (size_t)(nclass + 1));
+  const size_t o_grids = take(sizeof(Grid) * ngroups);
+  const size_t o_gclass = take(4 * (size_t)ngroups);
+  const size_t o_bgroup = take(4 * (size_t)blocks);
+  const size_t o_blocal = take(4 * (size_t)blocks);
+  const size_t o_mp = take(sizeof(MultiParams<VT>));
+  const size_t o_seq = take(4);
+  // per-launch state, cleared by k_multi_clear: queues and the group counter,
+  // aborts, stats, flags, exchange words
   const size_t o_state = off;
-  const size_t o_queue = off;
-  off += 256;
-  const size_t o_aborts = off;
-  off += align256(4 * (size_t)ng);
-  const size_t o_stats = off;
-  off += align256(sizeof(gmres_ir_stats) * nsys);
-  const size_t o_flags = off;
-  off += align256(4 * (size_t)kMaxBlocks * ng);
-  const size_t o_slots = off;
-  off += kSlotBytes * ng;
+  const size_t o_queues = take(4 * (size_t)(nclass + 1));
+  const size_t o_aborts = take(4 * (size_t)ngroups);
+  const size_t o_stats = take(sizeof(gmres_ir_stats) * nsys);
+  const size_t o_flags = take(4 * (size_t)kMaxBlocks * ngroups);
+  const size_t o_slots = take(kSlotBytes * ngroups);
   const size_t state_bytes = off - o_state;
 
   bspai_multi *P = new bspai_multi;
   P->nsys = nsys;
-  P->ngroups = ng;
-  P->group_blocks = gb;
+  P->ngroups = ngroups;
+  P->group_blocks = nclass == 1 ? csize[0] : 0;
   P->device = dev;
-  int rc = dalloc(&P->mem, off);
+  rc = dalloc(&P->mem, off);
   if (rc) {
     multi_release(P);
     return rc;
@@ -976,43 +1072,48 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
   gmres_ir_stats *stats = reinterpret_cast<gmres_ir_stats *>(mem + o_stats);
   for (int k = 0; k < nsys; k++) {
     bool w = false;
-    rc = sys_setup<VT>(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, ms[k], gb, rpbs[k], mem + base[k], L[k], ps[k],
-                       w, s);
+    const int m = std::min(std::max(tol->gmres_max, 1), std::min(sys[k].A.n, kMaxGmres));
+    rc = sys_setup<VT>(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, m, gs[k], rows_for(sys[k].A.n, gs[k]),
+                       mem + base[k], L[k], ps[k], w, s);
     if (rc) return bail(rc);
     ps[k].stats = stats + k;
   }
-  std::vector<int> order(nsys);
-  for (int k = 0; k < nsys; k++) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sys[a].A.n > sys[b].A.n; });
-  std::vector<Grid> grids(ng);
+  std::vector<Grid> grids(ngroups);
   unsigned *aborts = reinterpret_cast<unsigned *>(mem + o_aborts);
-  for (int g = 0; g < ng; g++) {
+  for (int g = 0; g < ngroups; g++) {
     grids[g].flags = reinterpret_cast<unsigned *>(mem + o_flags) + (size_t)kMaxBlocks * g;
     grids[g].abortf = aborts + g;
     grids[g].slots = reinterpret_cast<double *>(mem + o_slots + kSlotBytes * g);
-    grids[g].G = gb;
+    grids[g].G = csize[gclass[g]];
   }
   MultiParams<VT> mp;
   memset(&mp, 0, sizeof(mp));
   mp.sys = reinterpret_cast<const SolveParams<VT> *>(mem + o_params);
   mp.order = reinterpret_cast<const int *>(mem + o_order);
+  mp.class_off = reinterpret_cast<const int *>(mem + o_coff);
   mp.grids = reinterpret_cast<const Grid *>(mem + o_grids);
-  mp.queue = reinterpret_cast<unsigned *>(mem + o_queue);
-  mp.groups_done = mp.queue + 1;
+  mp.group_class = reinterpret_cast<const int *>(mem + o_gclass);
+  mp.block_group = reinterpret_cast<const int *>(mem + o_bgroup);
+  mp.block_local = reinterpret_cast<const int *>(mem + o_blocal);
+  mp.queues = reinterpret_cast<unsigned *>(mem + o_queues);
+  mp.groups_done = mp.queues + nclass;
   mp.seq = reinterpret_cast<const unsigned *>(mem + o_seq);
   mp.done_host = done_dev;
-  mp.nsys = nsys;
-  mp.group_blocks = gb;
-  mp.ngroups = ng;
+  mp.ngroups = ngroups;
   // pageable host copies: synchronise before the vectors go out of scope
   if (hipMemcpyAsync(mem + o_params, ps.data(), sizeof(SolveParams<VT>) * nsys, hipMemcpyHostToDevice, s) ||
       hipMemcpyAsync(mem + o_order, order.data(), 4 * (size_t)nsys, hipMemcpyHostToDevice, s) ||
-      hipMemcpyAsync(mem + o_grids, grids.data(), sizeof(Grid) * ng, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_coff, coff.data(), 4 * (size_t)(nclass + 1), hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_grids, grids.data(), sizeof(Grid) * ngroups, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_gclass, gclass.data(), 4 * (size_t)ngroups, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_bgroup, bgroup.data(), 4 * (size_t)blocks, hipMemcpyHostToDevice, s) ||
+      hipMemcpyAsync(mem + o_blocal, blocal.data(), 4 * (size_t)blocks, hipMemcpyHostToDevice, s) ||
       hipMemcpyAsync(mem + o_mp, &mp, sizeof(mp), hipMemcpyHostToDevice, s) ||
       hipMemsetAsync(mem + o_seq, 0, 4, s) || hipStreamSynchronize(s))
     return bail(fail(BSPAI_EHIP, "bspai_multi_plan: setting up the parameters failed"));
   P->stats = stats;
   P->aborts = aborts;
+  const int gb = blocks;  // grid size of the launch
 
   // capture clear + solve into a graph on a private stream
   hipStream_t cs = nullptr;
@@ -1025,7 +1126,7 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
                        nwords, reinterpret_cast<unsigned *>(mem + o_seq));
     const MultiParams<VT> *mpd = reinterpret_cast<const MultiParams<VT> *>(mem + o_mp);
     void *args[] = {&mpd};
-    hipError_t el = hipLaunchKernel(fn, dim3(gb * ng), dim3(kSolveThreads), args, lds, cs);
+    hipError_t el = hipLaunchKernel(fn, dim3(gb), dim3(kSolveThreads), args, lds, cs);
     hipError_t ee = hipStreamEndCapture(cs, &P->graph);
     e = el != hipSuccess ? el : ee;
   }
@@ -1142,8 +1243,9 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
                                   : multi_plan_typed<float>(sys, nsys, tol, gb, max_groups, out, s);
   };
   if (group_blocks >= 0) return plan(group_blocks, plan_out);
-  // autotune: the smallest group that holds the largest system, then doubled
-  // sizes; one timed launch of each, keep the fastest plan
+  // autotune: size classes, then one group size for all systems (the
+  // smallest that holds the largest system, then doubled); one timed launch
+  // of each, keep the fastest plan
   int nmax = 0;
   for (int k = 0; k < nsys; k++) nmax = std::max(nmax, sys[k].A.n);
   const int gmin = std::max(1, (nmax + kSolveThreads * 16 - 1) / (kSolveThreads * 16));
@@ -1153,7 +1255,9 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
   BSPAI_HIP(hipEventCreate(&e0));
   BSPAI_HIP(hipEventCreate(&e1));
   int rc = BSPAI_OK;
-  for (int gb = gmin; gb <= kMaxBlocks; gb *= 2) {
+  std::vector<int> cands = {0};
+  for (int gb = gmin; gb <= kMaxBlocks; gb *= 2) cands.push_back(gb);
+  for (int gb : cands) {
     bspai_multi *cand = nullptr;
     rc = plan(gb, &cand);
     if (rc) {
