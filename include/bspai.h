@@ -222,6 +222,29 @@ void bspai_multi_free(bspai_multi *plan);
  * autotuning), 0 for a plan with size classes. */
 int bspai_multi_group_blocks(const bspai_multi *plan);
 
+/*
+ * Kernel of bspai_apply / bspai_apply_T for one right-hand side.  All of them
+ * compute Algorithm 3's sum with the same per-bucket accumulation precision;
+ * they differ in how entries are grouped over threads, so results can
+ * differ in the last bits of the accumulation (each stays within the bound
+ * of that accumulation).
+ *   0 automatic: ELL/SELL copies when every bucket has one, else LDS tiles;
+ *   1 the padded copies (ELL with byte or int16 column codes, else SELL-64);
+ *   2 LDS tiles of contiguous rows (balanced for rows of any length);
+ *   3 two rows per thread;  4 a group of lanes per row.
+ * bspai_set_apply_kind -- use kernel `kind` for M_b (trans = 0) or M_b^T
+ *   (trans = 1); EINVAL when the handle lacks what the kernel needs (kind 1:
+ *   a copy for every bucket; padded copies are not built where padding would
+ *   exceed half the entries).
+ * bspai_tune_apply -- time every available kernel (20 products of an fp32
+ *   vector each, HIP events on `stream`) for M_b and, with build_T, for
+ *   M_b^T, and keep the fastest.  Synchronises `stream`.  Not called by
+ *   bspai_build: a tuned handle's products may differ in the last bits from
+ *   an untuned one's.
+ */
+int bspai_set_apply_kind(bspai_handle *M, int trans, int kind);
+int bspai_tune_apply(bspai_handle *M, void *stream);
+
 typedef struct {
     int32_t n;
     int32_t q;
@@ -238,6 +261,8 @@ typedef struct {
     int32_t ell_width[6];    /* width W of the bucket's row-major padded copy used by bspai_apply (0: none) */
     int32_t col_bytes[6];    /* bytes per column index that bspai_apply reads for the bucket: 1 (index
                                 into 256 offsets col - row), 2 (int16 offset) or 4 */
+    int32_t apply_kind[2];   /* kernel bspai_apply / bspai_apply_T use (1..4, see bspai_set_apply_kind;
+                                0 for apply_T without build_T) */
 } bspai_bucket_stats;
 
 /* bspai_stats -- bucket occupancy and storage of a handle (host struct). */

@@ -69,7 +69,7 @@ class _BStats(C.Structure):
                 ("count", C.c_int64 * 6), ("threshold", C.c_double * 6), ("scale", C.c_double * 6),
                 ("norm_inf", C.c_double), ("eps_b", C.c_double), ("bytes_values", C.c_int64),
                 ("bytes_indices", C.c_int64), ("storage_pct", C.c_double), ("ell_width", C.c_int32 * 6),
-                ("col_bytes", C.c_int32 * 6)]
+                ("col_bytes", C.c_int32 * 6), ("apply_kind", C.c_int32 * 2)]
 
 
 class _System(C.Structure):
@@ -93,6 +93,10 @@ _lib.bspai_last_error.restype = C.c_char_p
 _lib.bspai_set_profiling.argtypes = [C.c_int]
 _lib.bspai_set_profiling.restype = None
 _lib.bspai_last_solve_kernel_ms.restype = C.c_double
+_lib.bspai_set_apply_kind.argtypes = [_vp, C.c_int, C.c_int]
+_lib.bspai_set_apply_kind.restype = C.c_int
+_lib.bspai_tune_apply.argtypes = [_vp, _vp]
+_lib.bspai_tune_apply.restype = C.c_int
 _lib.bspai_exchange_latency.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_double), _vp]
 _lib.bspai_exchange_latency.restype = C.c_int
 _lib.bspai_solve_blocks.argtypes = [C.c_int]
@@ -114,7 +118,7 @@ SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
            "bspai_export", "bspai_free", "bspai_last_error", "bspai_grad_vals", "bspai_set_profiling",
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
            "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
-           "bspai_solve_blocks")
+           "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply")
 
 
 def set_profiling(on: bool) -> None:
@@ -230,7 +234,17 @@ class Handle:
         return dict(n=s.n, q=q, nnz=s.nnz, precs=list(s.precs[:q]), count=list(s.count[:q]),
                     threshold=list(s.threshold[:q]), scale=list(s.scale[:q]), norm_inf=s.norm_inf, eps_b=s.eps_b,
                     bytes_values=s.bytes_values, bytes_indices=s.bytes_indices, storage_pct=s.storage_pct,
-                    ell_width=list(s.ell_width[:q]), col_bytes=list(s.col_bytes[:q]))
+                    ell_width=list(s.ell_width[:q]), col_bytes=list(s.col_bytes[:q]),
+                    apply_kind=list(s.apply_kind))
+
+    def set_apply_kind(self, kind: int, trans: bool = False) -> None:
+        """Kernel of apply (trans False) or apply_T: 0 automatic, 1 padded
+        copies, 2 LDS tiles, 3 two rows per thread, 4 lanes per row."""
+        _check(_lib.bspai_set_apply_kind(self.ptr, int(trans), int(kind)))
+
+    def tune_apply(self, stream=None) -> None:
+        """Time every available apply kernel and keep the fastest."""
+        _check(_lib.bspai_tune_apply(self.ptr, _stream(stream)))
 
     def export(self, fp64: bool = True) -> Dict:
         import numpy as np

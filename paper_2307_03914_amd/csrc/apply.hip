@@ -93,19 +93,6 @@ __global__ void __launch_bounds__(kApplyThreads) k_bspmv_ell(BMat M, const XT *_
 // format switch is resolved at compile time so the kernel stays small enough
 // for full occupancy.  NT: stream the codes and values with non-temporal
 // loads (they are read once; x stays in L2).
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-template <bool NT, typename V>
-__device__ __forceinline__ V ld_stream(const void *p) {
-  const V *q = static_cast<const V *>(p);
-  if (NT) return __builtin_nontemporal_load(q);
-  return *q;
-}
 
 template <typename XT, typename PT, int FMT, bool NT>
 __global__ void __launch_bounds__(kApplyThreads) k_bspmv_ell1(BMat M, const XT *__restrict__ x, XT *__restrict__ y) {
@@ -281,20 +268,12 @@ __global__ void __launch_bounds__(kApplyThreads) k_bspmv_rows(BMat M, const XT *
     if (rows[r] >= 0) y[rows[r]] = (XT)out[r];
 }
 
+// two rows per thread (one row per thread and four measured slower: four
+// costs occupancy)
 template <typename XT, typename PT>
 static int launch_rowthread(const BMat &M, const XT *x, XT *y, hipStream_t s) {
-  int rt = 2;
-  if (const char *e = getenv("BSPAI_APPLY_RT")) rt = atoi(e);
-  if (rt <= 1) {
-    int64_t nblk = (M.n + kApplyThreads - 1) / kApplyThreads;
-    hipLaunchKernelGGL((k_bspmv_row<XT, PT>), dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M, x, y);
-  } else if (rt == 2) {
-    int64_t nblk = (M.n + 2 * kApplyThreads - 1) / (2 * kApplyThreads);
-    hipLaunchKernelGGL((k_bspmv_rows<2, XT, PT>), dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M, x, y);
-  } else {
-    int64_t nblk = (M.n + 4 * kApplyThreads - 1) / (4 * kApplyThreads);
-    hipLaunchKernelGGL((k_bspmv_rows<4, XT, PT>), dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M, x, y);
-  }
+  int64_t nblk = (M.n + 2 * kApplyThreads - 1) / (2 * kApplyThreads);
+  hipLaunchKernelGGL((k_bspmv_rows<2, XT, PT>), dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M, x, y);
   BSPAI_CHECK_LAUNCH();
   return BSPAI_OK;
 }
@@ -403,7 +382,6 @@ static int launch_tile(const BMat &M, const XT *x, XT *y, hipStream_t s) {
   double avg = M.n ? (double)M.nnz / M.n : 1.0;
   int rows = (int)(cap / (1.3 * std::max(avg, 1.0)));
   rows = std::max(32, std::min(1024, rows & ~31));
-  if (const char *e = getenv("BSPAI_TILE_ROWS")) rows = std::max(32, std::min(1024, atoi(e) & ~31));
   int64_t nblk = (M.n + rows - 1) / rows;
   size_t lds = (size_t)cap * sizeof(PT) + (size_t)rows * sizeof(double) + 4 * ((size_t)rows + 1) + 16;
   hipLaunchKernelGGL((k_bspmv_tile<XT, PT>), dim3((unsigned)nblk), dim3(kApplyThreads), lds, s, M, x, y, rows, cap);
@@ -439,32 +417,51 @@ static int launch_vec(const BMat &M, const XT *x, XT *y, int lanes, hipStream_t 
   return BSPAI_OK;
 }
 
+// every stored bucket has an ELL or a SELL copy
+static bool sell_ok(const BMat &M) {
+  for (int k = 0; k < M.nb; k++)
+    if (!M.ell_w[k] && !M.sell_ptr[k]) return false;
+  return M.nb > 0;
+}
+
+bool apply_kind_ok(const BMat &M, int kind) {
+  switch (kind) {
+    case kApplyAuto: return true;
+    case kApplySell: return sell_ok(M);
+    case kApplyTile: return M.aligned != 0;
+    case kApplyRows:
+    case kApplyLanes: return true;
+  }
+  return false;
+}
+
+// the padded copies when every bucket has one, else LDS tiles (balanced for
+// rows of any length), else one group of lanes per row
+int apply_kind_resolved(const BMat &M) {
+  if (M.apply_kind > 0 && apply_kind_ok(M, M.apply_kind)) return M.apply_kind;
+  if (sell_ok(M)) return kApplySell;
+  if (M.aligned) return kApplyTile;
+  return kApplyLanes;
+}
+
+template <typename XT, typename PT>
+static int launch_one(const BMat &M, const XT *x, XT *y, int kind, hipStream_t s) {
+  switch (kind) {
+    case kApplySell: return launch_sell<XT, PT>(M, x, y, s);
+    case kApplyTile: return launch_tile<XT, PT>(M, x, y, s);
+    case kApplyRows: return launch_rowthread<XT, PT>(M, x, y, s);
+    default: return launch_vec<XT>(M, x, y, M.lanes > 0 ? M.lanes : pick_lanes(M, M.nnz), s);
+  }
+}
+
 int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s) {
   if (M.n == 0) return BSPAI_OK;
   if (nrhs == 1) {
-    double avg = M.n ? (double)M.nnz / M.n : 0.0;
-    const char *kind = getenv("BSPAI_APPLY_KERNEL");
-    if (M.sell_ptr[0] && !(kind && (kind[0] == 't' || kind[0] == 'r'))) {
-      if (fp64) return launch_sell<double, double>(M, static_cast<const double *>(x), static_cast<double *>(y), s);
-      if (has_fp64_bucket(M))
-        return launch_sell<float, double>(M, static_cast<const float *>(x), static_cast<float *>(y), s);
-      return launch_sell<float, float>(M, static_cast<const float *>(x), static_cast<float *>(y), s);
-    }
-    if (avg <= 24 && !(kind && kind[0] == 't')) {
-      if (fp64) return launch_rowthread<double, double>(M, static_cast<const double *>(x), static_cast<double *>(y), s);
-      if (has_fp64_bucket(M))
-        return launch_rowthread<float, double>(M, static_cast<const float *>(x), static_cast<float *>(y), s);
-      return launch_rowthread<float, float>(M, static_cast<const float *>(x), static_cast<float *>(y), s);
-    }
-    if (M.aligned && avg <= 48) {
-      if (fp64) return launch_tile<double, double>(M, static_cast<const double *>(x), static_cast<double *>(y), s);
-      if (has_fp64_bucket(M))
-        return launch_tile<float, double>(M, static_cast<const float *>(x), static_cast<float *>(y), s);
-      return launch_tile<float, float>(M, static_cast<const float *>(x), static_cast<float *>(y), s);
-    }
-    int lanes = M.lanes > 0 ? M.lanes : pick_lanes(M, M.nnz);
-    return fp64 ? launch_vec<double>(M, static_cast<const double *>(x), static_cast<double *>(y), lanes, s)
-                : launch_vec<float>(M, static_cast<const float *>(x), static_cast<float *>(y), lanes, s);
+    const int kind = apply_kind_resolved(M);
+    if (fp64) return launch_one<double, double>(M, static_cast<const double *>(x), static_cast<double *>(y), kind, s);
+    if (has_fp64_bucket(M))
+      return launch_one<float, double>(M, static_cast<const float *>(x), static_cast<float *>(y), kind, s);
+    return launch_one<float, float>(M, static_cast<const float *>(x), static_cast<float *>(y), kind, s);
   }
   if (nrhs % 4 == 0 && nrhs <= 64 && ld % 4 == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0 &&
       (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
@@ -520,6 +517,96 @@ extern "C" int bspai_apply(const bspai_handle *M, const void *x, void *y, int nr
 extern "C" int bspai_apply_T(const bspai_handle *M, const void *x, void *y, int nrhs, int64_t ld,
                              bspai_prec xy_prec, void *stream) {
   return bspai::apply_common(M, x, y, nrhs, ld, xy_prec, stream, true);
+}
+
+// ------------------------------------------------------------------ kernel choice
+
+namespace bspai {
+
+__global__ void k_fill_pattern(int n, float *x) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 1.0f + 0.125f * (float)(i % 13);
+}
+
+// average time of `reps` products with kernel `kind` (fp32 vectors)
+static int time_kind(const BMat &M, int kind, const float *x, float *y, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                     float *ms) {
+  BMat T = M;
+  T.apply_kind = kind;
+  constexpr int kWarm = 2, kReps = 20;
+  for (int r = 0; r < kWarm; r++) {
+    int rc = launch_bspmv(T, x, y, 1, 1, 0, s);
+    if (rc) return rc;
+  }
+  BSPAI_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < kReps; r++) {
+    int rc = launch_bspmv(T, x, y, 1, 1, 0, s);
+    if (rc) return rc;
+  }
+  BSPAI_HIP(hipEventRecord(e1, s));
+  BSPAI_HIP(hipEventSynchronize(e1));
+  BSPAI_HIP(hipEventElapsedTime(ms, e0, e1));
+  *ms /= kReps;
+  return BSPAI_OK;
+}
+
+static int tune_one(BMat &M, const float *x, float *y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  int best = kApplyAuto;
+  float best_ms = 0.f;
+  for (int kind : {kApplySell, kApplyTile, kApplyRows, kApplyLanes}) {
+    if (!apply_kind_ok(M, kind)) continue;
+    float ms = 0.f;
+    int rc = time_kind(M, kind, x, y, s, e0, e1, &ms);
+    if (rc) return rc;
+    if (best == kApplyAuto || ms < best_ms) best = kind, best_ms = ms;
+  }
+  M.apply_kind = best;
+  return BSPAI_OK;
+}
+
+}  // namespace bspai
+
+extern "C" int bspai_set_apply_kind(bspai_handle *M, int trans, int kind) {
+  using namespace bspai;
+  if (!M) return fail(BSPAI_EINVAL, "bspai_set_apply_kind: null handle");
+  if (trans && !M->has_T) return fail(BSPAI_EINVAL, "bspai_set_apply_kind: handle built without build_T");
+  BMat &B = trans ? M->matT : M->mat;
+  if (kind < kApplyAuto || kind > kApplyLanes || !apply_kind_ok(B, kind))
+    return fail(BSPAI_EINVAL, "bspai_set_apply_kind: kernel %d is not available for this matrix", kind);
+  B.apply_kind = kind;
+  return BSPAI_OK;
+}
+
+extern "C" int bspai_tune_apply(bspai_handle *M, void *stream) {
+  using namespace bspai;
+  if (!M) return fail(BSPAI_EINVAL, "bspai_tune_apply: null handle");
+  if (M->n == 0 || M->mat.nb == 0) return BSPAI_OK;
+  int dev = 0;
+  BSPAI_HIP(hipGetDevice(&dev));
+  if (dev != M->device) return fail(BSPAI_EINVAL, "bspai_tune_apply: handle lives on device %d", M->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float *x = nullptr, *y = nullptr;
+  int rc;
+  if ((rc = dalloc_t(&x, (size_t)M->n)) || (rc = dalloc_t(&y, (size_t)M->n))) {
+    dfree(x);
+    return rc;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto body = [&]() -> int {
+    BSPAI_HIP(hipEventCreate(&e0));
+    BSPAI_HIP(hipEventCreate(&e1));
+    hipLaunchKernelGGL(k_fill_pattern, dim3((M->n + 255) / 256), dim3(256), 0, s, M->n, x);
+    BSPAI_CHECK_LAUNCH();
+    int r = tune_one(M->mat, x, y, s, e0, e1);
+    if (!r && M->has_T) r = tune_one(M->matT, x, y, s, e0, e1);
+    return r;
+  };
+  rc = body();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  dfree(x), dfree(y);
+  return rc;
 }
 
 // ------------------------------------------------------------------ adjoint

@@ -1024,6 +1024,8 @@ extern "C" int bspai_stats(const bspai_handle *M, bspai_bucket_stats *o) {
     o->ell_width[k] = M->mat.ell_w[j++];
   }
   o->storage_pct = M->nnz ? 100.0 * num / ((double)M->nnz * value_bytes(M->precs[0])) : 100.0;
+  o->apply_kind[0] = M->mat.nb ? apply_kind_resolved(M->mat) : 0;
+  o->apply_kind[1] = M->has_T && M->matT.nb ? apply_kind_resolved(M->matT) : 0;
   return BSPAI_OK;
 }
 

@@ -71,7 +71,13 @@ struct BMat {
   const void *ell_code[kMaxBuckets];
   const int32_t *ell_dict[kMaxBuckets];
   int32_t ell_cw[kMaxBuckets];
+  // kernel of the single-vector product: 0 chosen from the layout, else one
+  // of the ApplyKind values (set by bspai_set_apply_kind / bspai_tune_apply)
+  int32_t apply_kind;
 };
+
+// kernels of the single-vector bucketed product
+enum ApplyKind { kApplyAuto = 0, kApplySell = 1, kApplyTile = 2, kApplyRows = 3, kApplyLanes = 4 };
 
 constexpr int kSlice = 64;
 
@@ -147,7 +153,8 @@ int csr_transpose(int n, int64_t nnz, const int32_t *rp, const int32_t *col, con
                   int32_t *trp, int32_t *tcol, void *tval, hipStream_t s);
 
 // SELL-64 copy of one CSR (values of vbytes bytes); allocates *sptr (n/64+1),
-// *scol and *sval (padded length).
+// *scol and *sval (padded length).  No copy (null pointers, BSPAI_OK) when
+// the padding would exceed half the entries.
 // *width gets the common slice width when all slices are padded to the
 // widest one (chosen when that pads at most 15% more than per-slice widths),
 // else 0.
@@ -170,6 +177,9 @@ int ell_codes(int n, int w, const int32_t *ecol, void **code, int32_t **dict, in
 int pick_lanes(const BMat &M, int64_t nnz);
 int bmat_aligned(const BMat &M);
 int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s);
+// whether M has what kernel `kind` needs, and the kernel used when none is set
+bool apply_kind_ok(const BMat &M, int kind);
+int apply_kind_resolved(const BMat &M);
 
 // gmres_ir_solve for 2 <= R <= 64 right-hand sides (solve_batched.hip);
 // arguments already validated, m the GMRES cap.

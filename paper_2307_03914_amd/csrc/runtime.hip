@@ -283,6 +283,13 @@ int csr_to_sell(int n, const int32_t *rp, const int32_t *col, const void *val, i
         tot += v;
         wmax = std::max(wmax, v / kSlice);
       }
+      // slices of rows with very different lengths (power-law matrices) pad
+      // each row to the longest of its slice: no SELL copy when that more
+      // than 1.5x the entries
+      int32_t nnz = 0;
+      BSPAI_HIP(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      BSPAI_HIP(hipStreamSynchronize(s));
+      if ((double)tot > 1.5 * (double)std::max(nnz, 1) || tot >= INT32_MAX) return 1;  // no copy
       if ((double)ns * kSlice * wmax <= 1.15 * (double)tot && (int64_t)ns * kSlice * wmax < INT32_MAX) {
         *width = wmax;  // one width for all slices
         hipLaunchKernelGGL(k_fill_value, dim3((ns + 255) / 256), dim3(256), 0, s, len, (int64_t)ns, wmax * kSlice);
@@ -308,8 +315,9 @@ int csr_to_sell(int n, const int32_t *rp, const int32_t *col, const void *val, i
   if (rc) {
     dfree(*sptr), dfree(*scol), dfree(*sval);
     *sptr = nullptr, *scol = nullptr, *sval = nullptr;
+    *width = 0;
   }
-  return rc;
+  return rc == 1 ? BSPAI_OK : rc;
 }
 
 // ------------------------------------------------------------------ ELL

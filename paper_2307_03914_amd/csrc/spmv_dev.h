@@ -134,23 +134,40 @@ __device__ __forceinline__ void bspmm_row(const BMat &M, const XT *__restrict__ 
 
 constexpr int kTileVec = 8;  // entries per thread and pass
 
-template <typename PT>
+// vector loads, optionally non-temporal (data read once: leave the caches to
+// the gathered vector)
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT, typename V>
+__device__ __forceinline__ V ld_stream(const void *p) {
+  const V *q = static_cast<const V *>(p);
+  if (NT) return __builtin_nontemporal_load(q);
+  return *q;
+}
+
+template <typename PT, bool NT = false>
 __device__ __forceinline__ void load_vals8(const BMat &M, int k, int64_t base, PT (&v)[kTileVec]) {
   // base is a multiple of 8 entries: every load below is naturally aligned
   switch (M.prec[k]) {
     case BSPAI_FP64: {
-      const double4 *p = reinterpret_cast<const double4 *>(static_cast<const double *>(M.val[k]) + base);
-      double4 a = p[0], b = p[1];
+      const double *p = static_cast<const double *>(M.val[k]) + base;
+      f64x4 a = ld_stream<NT, f64x4>(p), b = ld_stream<NT, f64x4>(p + 4);
       v[0] = (PT)a.x; v[1] = (PT)a.y; v[2] = (PT)a.z; v[3] = (PT)a.w;
       v[4] = (PT)b.x; v[5] = (PT)b.y; v[6] = (PT)b.z; v[7] = (PT)b.w;
     } break;
     case BSPAI_FP32: {
-      const float4 *p = reinterpret_cast<const float4 *>(static_cast<const float *>(M.val[k]) + base);
-      float4 a = p[0], b = p[1];
+      const float *p = static_cast<const float *>(M.val[k]) + base;
+      f32x4 a = ld_stream<NT, f32x4>(p), b = ld_stream<NT, f32x4>(p + 4);
       v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
     } break;
     case BSPAI_FP16: {
-      uint4 a = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(M.val[k]) + base);
+      u32x4 a = ld_stream<NT, u32x4>(static_cast<const uint16_t *>(M.val[k]) + base);
       uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
       for (int t = 0; t < 4; t++) {
@@ -159,7 +176,7 @@ __device__ __forceinline__ void load_vals8(const BMat &M, int k, int64_t base, P
       }
     } break;
     case BSPAI_BF16: {
-      uint4 a = *reinterpret_cast<const uint4 *>(static_cast<const uint16_t *>(M.val[k]) + base);
+      u32x4 a = ld_stream<NT, u32x4>(static_cast<const uint16_t *>(M.val[k]) + base);
       uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
       for (int t = 0; t < 4; t++) {
@@ -168,7 +185,7 @@ __device__ __forceinline__ void load_vals8(const BMat &M, int k, int64_t base, P
       }
     } break;
     case BSPAI_FP8_E4M3: {
-      uint2 a = *reinterpret_cast<const uint2 *>(static_cast<const uint8_t *>(M.val[k]) + base);
+      u32x2 a = ld_stream<NT, u32x2>(static_cast<const uint8_t *>(M.val[k]) + base);
       uint32_t w[2] = {a.x, a.y};
 #pragma unroll
       for (int t = 0; t < 8; t++) v[t] = decode_e4m3((uint8_t)((w[t >> 2] >> (8 * (t & 3))) & 0xFFu));
@@ -204,12 +221,13 @@ __device__ void bspmv_tile_rows(const BMat &M, const XT *__restrict__ x, YT *__r
         const int eb = e0 & ~(kTileVec - 1);
         for (int base = eb + tid * kTileVec; base < e1; base += nt * kTileVec) {
           if (base >= e0 && base + kTileVec <= e1) {
-            // 8 entries inside the range: aligned vector loads, 8 gathers in flight
-            int4 ca = *reinterpret_cast<const int4 *>(col + base);
-            int4 cb = *reinterpret_cast<const int4 *>(col + base + 4);
+            // 8 entries inside the range: aligned non-temporal vector loads
+            // (read once, so x keeps the caches), 8 gathers in flight
+            i32x4 ca = ld_stream<true, i32x4>(col + base);
+            i32x4 cb = ld_stream<true, i32x4>(col + base + 4);
             int cc[kTileVec] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
             PT vv[kTileVec];
-            load_vals8<PT>(M, k, base, vv);
+            load_vals8<PT, true>(M, k, base, vv);
             PT xv[kTileVec];
 #pragma unroll
             for (int t = 0; t < kTileVec; t++) xv[t] = (PT)x[cc[t]];

@@ -271,6 +271,47 @@ def test_apply_narrow_column_codes(B, kind, col_bytes, width):
     h.free()
 
 
+@pytest.mark.parametrize("key", ["2s", "3s", "4as", "5s"])
+def test_apply_every_kernel_and_tuning(B, key):
+    """Every single-vector apply kernel the handle supports (padded copies,
+    LDS tiles, two rows per thread, lanes per row), both orientations,
+    against the oracle; then the tuner's choice."""
+    import torch
+
+    c = W.config(key[:-1], small=True)
+    A, P = c["A"], c["P"]
+    eps = c["eps"][0]
+    _say("apply kernels", key)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, eps, c["precs"])
+    h = B.import_m(B.CSRMatrix.from_host(M), eps, c["precs"])
+    x = np.random.default_rng(8).standard_normal(A.n).astype(np.float32).astype(np.float64)
+    xd = _dev(x, torch.float32)
+    refs = {t: (O.apply_T if t else O.apply)(Mb, x, O.FP64) for t in (False, True)}
+    bounds = {t: _apply_bound(Mb, x, U32, transpose=t) + U32 * np.abs(refs[t]) for t in (False, True)}
+    ran = 0
+    for kind in (1, 2, 3, 4, 0):
+        for t in (False, True):
+            try:
+                h.set_apply_kind(kind, trans=t)
+            except B.BSPAIError:
+                assert kind == 1  # only the padded copies can be missing
+                continue
+            y = (B.apply_T if t else B.apply)(h, xd).double().cpu().numpy()
+            assert np.all(np.abs(y - refs[t]) <= bounds[t] + 1e-300), (key, kind, t)
+            ran += 1
+    assert ran >= 8
+    h.tune_apply()
+    st = h.stats()
+    assert all(1 <= k <= 4 for k in st["apply_kind"]), st["apply_kind"]
+    for t in (False, True):
+        y = (B.apply_T if t else B.apply)(h, xd).double().cpu().numpy()
+        assert np.all(np.abs(y - refs[t]) <= bounds[t] + 1e-300)
+    with pytest.raises(B.BSPAIError):
+        h.set_apply_kind(7)
+    h.free()
+
+
 @pytest.mark.parametrize("nrhs", [2, 8, 64, 70])
 def test_apply_multi_rhs_matches_columns(B, nrhs):
     import torch
@@ -317,6 +358,7 @@ def test_apply_full_size_sampled_rows(B):
         assert abs(y[i] - ref) <= tol + U32 * abs(ref)
     st = h.stats()
     assert st["count"][-1] == A.nnz  # every entry lands in the bf16 bucket at eps = 1e-2
+    assert st["apply_kind"] == [1, 1]  # ELL copies both ways
     h.free()
 
 
@@ -887,4 +929,7 @@ def test_build_powerlaw_full_size_sampled_rows(B):
         assert np.abs(m[s] - Ms.val[s]).max() <= 1e-9 * np.abs(Ms.val[s]).max(), (i, lens[i])
     st = h.stats()
     assert sum(st["count"]) == P.nnz
+    # power-law rows would pad 64-row slices many times over: no padded
+    # copies, the products default to LDS tiles
+    assert st["apply_kind"] == [2, 2], st["apply_kind"]
     h.free()
