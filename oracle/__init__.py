@@ -84,6 +84,8 @@ def lib():
     L.orc_householder_ls.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p]
     L.orc_spai.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, C.c_void_p, C.c_int, C.c_int,
                            C.POINTER(C.c_int)]
+    L.orc_spai_adaptive.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, C.c_void_p, C.c_void_p, C.c_int,
+                                    C.c_int, C.c_double, C.c_int, _i32p, _i32p, _f64p, _i32p, C.POINTER(C.c_int)]
     L.orc_norm_inf.argtypes = [C.c_int, _i32p, _f64p]
     L.orc_norm_inf.restype = C.c_double
     L.orc_bucketize.argtypes = [C.c_int, _i32p, _f64p, C.c_double, _i32p, C.c_int, _i8p, _f64p, _f64p, _f64p, _i64p]
@@ -171,6 +173,39 @@ def spai(A, P, rows: Optional[np.ndarray] = None, scale: bool = False):
     st = lib().orc_spai(A.n, _i32(A.row_ptr), _i32(A.col), _f64(A.val), _i32(P.row_ptr), _i32(P.col), Mv,
                         rptr, nr, int(scale), C.byref(bad))
     return st, Mv, bad.value
+
+
+def spai_adaptive(A, alpha: int = 5, beta: int = 8, eps: float = 0.4, J0=None) -> Dict:
+    """Adaptive SPAI (Algorithm 1 with augmentation, on A^T).  J0: initial
+    pattern (workloads.CSR; None: the identity).  Returns dict(status, M
+    (workloads.CSR with each row's columns ascending), steps (solves per
+    row), bad_row)."""
+    import workloads as W
+    n = A.n
+    AT = transpose_csr(A)
+    j0max = 1 if J0 is None else int(np.diff(J0.row_ptr).max(initial=0))
+    jmax = max(1, j0max + alpha * beta)
+    cnt = np.zeros(n, dtype=np.int32)
+    cols = np.zeros(n * jmax, dtype=np.int32)
+    vals = np.zeros(n * jmax)
+    steps = np.zeros(n, dtype=np.int32)
+    bad = C.c_int(-1)
+    keep = []
+    if J0 is not None:
+        jr, jc = _i32(J0.row_ptr), _i32(J0.col)
+        keep = [jr, jc]
+        jrp, jcp = jr.ctypes.data_as(C.c_void_p), jc.ctypes.data_as(C.c_void_p)
+    else:
+        jrp = jcp = None
+    st = lib().orc_spai_adaptive(n, _i32(A.row_ptr), _i32(A.col), _f64(A.val), _i32(AT.row_ptr), _i32(AT.col), jrp,
+                                 jcp, int(alpha), int(beta), float(eps), int(jmax), cnt, cols, vals, steps,
+                                 C.byref(bad))
+    del keep
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(cnt)
+    sel = (np.arange(jmax)[None, :] < cnt[:, None]).reshape(-1)
+    M = W.CSR(n, rp, cols[sel].astype(np.int32), vals[sel])
+    return dict(status=st, M=M, steps=steps, bad_row=bad.value)
 
 
 def norm_inf(M) -> float:

@@ -346,6 +346,165 @@ int orc_spai(int n, const int *Arp, const int *Aci, const double *Av,
 }
 
 /* ------------------------------------------------------------------------
+ * Adaptive SPAI: Algorithm 1 with its augmentation loop, run on A^T (row k
+ * of M is column k of SPAI(A^T), as in orc_spai).  Row k starts from
+ * J_k = J0(k,:) (the identity when J0rp is NULL) and for step = 0..alpha:
+ *   - I_k is the shadow of J_k (the nonzero columns of the rows j in J_k of
+ *     A); the least squares problem (redprob) with Abar = A(J_k, I_k)^T is
+ *     solved by Householder QR from scratch (the QR update of the paper gives
+ *     the same solution up to rounding);
+ *   - s = Abar m - e_k(I_k) is the residual; the row is done when
+ *     ||s||_2 <= eps or after the last solve (step = alpha);
+ *   - L_k holds the rows l of I_k with s(l) != 0; the candidates are the j
+ *     with a_jl != 0 for some l in L_k (column l of A), minus J_k;
+ *   - for a candidate j, rho_j^2 = ||s||^2 - (s . a_j)^2 / ||a_j||^2, with
+ *     a_j the whole row j of A (as a vector over l): the residual norm
+ *     after adding j alone with its best coefficient;
+ *   - rho_j is compared after rounding to fp32, the mean is the FP64 sum of
+ *     the rounded values in ascending j divided by the number of candidates;
+ *     the candidates with rho_j <= mean, ordered by (rho_j, j), join J_k up
+ *     to beta of them (J_k is kept sorted).  No candidate left: the row is
+ *     done.
+ * Out: cnt[k] = |J_k|, its columns (ascending) and values at k*jmax ..,
+ * steps[k] = least squares solves made.  |J_k| never exceeds jmax (further
+ * candidates are not added).  Errors as orc_spai (EZEROROW, ERANK).
+ * ---------------------------------------------------------------------- */
+typedef struct { float rho; int j; } orc_cand;
+
+static int cmp_cand(const void *a, const void *b) {
+    const orc_cand *x = (const orc_cand *)a, *y = (const orc_cand *)b;
+    if (x->rho != y->rho) return (x->rho > y->rho) - (x->rho < y->rho);
+    return (x->j > y->j) - (x->j < y->j);
+}
+
+int orc_spai_adaptive(int n, const int *Arp, const int *Aci, const double *Av,
+                      const int *ATrp, const int *ATci, const int *J0rp, const int *J0ci,
+                      int alpha, int beta, double eps, int jmax,
+                      int *cnt, int *cols, double *vals, int *steps, int *bad_row) {
+    int status = ORC_OK;
+    int first_bad = n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < n; k++) {
+        int *J = (int *)malloc(sizeof(int) * (size_t)jmax);
+        int nJ = 0;
+        if (J0rp) {
+            for (int e = J0rp[k]; e < J0rp[k + 1] && nJ < jmax; e++) J[nJ++] = J0ci[e];
+            qsort(J, (size_t)nJ, sizeof(int), cmp_int);
+        } else {
+            J[nJ++] = k;
+        }
+        int st = ORC_OK, nsolve = 0;
+        double *m = NULL;
+        for (int step = 0; step <= alpha; step++) {
+            /* shadow */
+            int cap = 0;
+            for (int c = 0; c < nJ; c++) cap += Arp[J[c] + 1] - Arp[J[c]];
+            int *I = (int *)malloc(sizeof(int) * (size_t)(cap > 0 ? cap : 1));
+            int nI = 0;
+            for (int c = 0; c < nJ; c++)
+                for (int e = Arp[J[c]]; e < Arp[J[c] + 1]; e++)
+                    if (Av[e] != 0.0) I[nI++] = Aci[e];
+            qsort(I, (size_t)nI, sizeof(int), cmp_int);
+            int u = 0;
+            for (int l = 0; l < nI; l++)
+                if (u == 0 || I[l] != I[u - 1]) I[u++] = I[l];
+            nI = u;
+            const int kpos = find_sorted(I, nI, k);
+            if (kpos < 0) { st = ORC_EZEROROW; free(I); break; }
+            if (nI < nJ) { st = ORC_ERANK; free(I); break; }
+            double *Ab = (double *)calloc((size_t)nI * nJ, sizeof(double));
+            double *A0 = (double *)calloc((size_t)nI * nJ, sizeof(double));
+            double *eb = (double *)calloc((size_t)nI, sizeof(double));
+            free(m);
+            m = (double *)calloc((size_t)nJ, sizeof(double));
+            for (int c = 0; c < nJ; c++)
+                for (int e = Arp[J[c]]; e < Arp[J[c] + 1]; e++) {
+                    if (Av[e] == 0.0) continue;
+                    Ab[find_sorted(I, nI, Aci[e]) + (size_t)c * nI] = Av[e];
+                }
+            memcpy(A0, Ab, sizeof(double) * (size_t)nI * nJ);
+            eb[kpos] = 1.0;
+            st = orc_householder_ls(nI, nJ, Ab, eb, m);
+            nsolve++;
+            if (st != ORC_OK) { free(Ab); free(A0); free(eb); free(I); break; }
+            /* residual on the shadow */
+            double *sv = (double *)malloc(sizeof(double) * (size_t)nI);
+            double ns2 = 0.0;
+            for (int l = 0; l < nI; l++) {
+                double t = 0.0;
+                for (int c = 0; c < nJ; c++) t += A0[l + (size_t)c * nI] * m[c];
+                sv[l] = t - (l == kpos ? 1.0 : 0.0);
+                ns2 += sv[l] * sv[l];
+            }
+            free(Ab); free(A0); free(eb);
+            int done = sqrt(ns2) <= eps || step == alpha;
+            if (!done) {
+                /* candidates: columns l of A over the residual's support */
+                int ccap = 0;
+                for (int l = 0; l < nI; l++)
+                    if (sv[l] != 0.0) ccap += ATrp[I[l] + 1] - ATrp[I[l]];
+                int *C = (int *)malloc(sizeof(int) * (size_t)(ccap > 0 ? ccap : 1));
+                int nC = 0;
+                for (int l = 0; l < nI; l++)
+                    if (sv[l] != 0.0)
+                        for (int e = ATrp[I[l]]; e < ATrp[I[l] + 1]; e++) C[nC++] = ATci[e];
+                qsort(C, (size_t)nC, sizeof(int), cmp_int);
+                u = 0;
+                for (int t = 0; t < nC; t++)
+                    if ((u == 0 || C[t] != C[u - 1]) && find_sorted(J, nJ, C[t]) < 0) C[u++] = C[t];
+                nC = u;
+                orc_cand *cd = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(nC > 0 ? nC : 1));
+                double sum = 0.0;
+                for (int t = 0; t < nC; t++) {
+                    const int j = C[t];
+                    double dot = 0.0, nrm = 0.0;
+                    for (int e = Arp[j]; e < Arp[j + 1]; e++) {
+                        const int l = find_sorted(I, nI, Aci[e]);
+                        if (l >= 0) dot += sv[l] * Av[e];
+                        nrm += Av[e] * Av[e];
+                    }
+                    double r2 = nrm > 0.0 ? ns2 - dot * dot / nrm : ns2;
+                    cd[t].rho = (float)sqrt(r2 > 0.0 ? r2 : 0.0);
+                    cd[t].j = j;
+                    sum += (double)cd[t].rho;
+                }
+                int nacc = 0;
+                if (nC > 0) {
+                    const double mean = sum / nC;
+                    for (int t = 0; t < nC; t++)
+                        if ((double)cd[t].rho <= mean) cd[nacc++] = cd[t];
+                    qsort(cd, (size_t)nacc, sizeof(orc_cand), cmp_cand);
+                }
+                int add = nacc < beta ? nacc : beta;
+                if (add > jmax - nJ) add = jmax - nJ;
+                for (int t = 0; t < add; t++) J[nJ++] = cd[t].j;
+                qsort(J, (size_t)nJ, sizeof(int), cmp_int);
+                free(cd); free(C);
+                if (add == 0) done = 1;
+                else { free(m); m = NULL; }  /* J changed: solve again */
+            }
+            free(sv); free(I);
+            if (done) break;
+        }
+        cnt[k] = nJ;
+        steps[k] = nsolve;
+        for (int c = 0; c < nJ; c++) {
+            cols[(size_t)k * jmax + c] = J[c];
+            vals[(size_t)k * jmax + c] = (st == ORC_OK && m) ? m[c] : 0.0;
+        }
+        free(m); free(J);
+        if (st != ORC_OK) {
+#pragma omp critical
+            {
+                if (status == ORC_OK || k < first_bad) { status = st; first_bad = k; }
+            }
+        }
+    }
+    if (bad_row) *bad_row = (status == ORC_OK) ? -1 : first_bad;
+    return status;
+}
+
+/* ------------------------------------------------------------------------
  * ||M||_inf = max_i sum_j |m_ij| (the default norm of Section 2.1), each row
  * summed left to right in CSR order.
  * ---------------------------------------------------------------------- */
