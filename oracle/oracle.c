@@ -355,8 +355,10 @@ int orc_spai(int n, const int *Arp, const int *Aci, const double *Av,
  *     the same solution up to rounding);
  *   - s = Abar m - e_k(I_k) is the residual; the row is done when
  *     ||s||_2 <= eps or after the last solve (step = alpha);
- *   - L_k holds the rows l of I_k with s(l) != 0; the candidates are the j
- *     with a_jl != 0 for some l in L_k (column l of A), minus J_k;
+ *   - L_k holds the rows l of I_k with s(l) != 0, "nonzero" meaning
+ *     |s(l)| > 2^-40 (||e_k|| = 1: where the fit is exact, s(l) is rounding
+ *     noise whose exact zeros depend on the summation order); the candidates
+ *     are the j with a_jl != 0 for some l in L_k (column l of A), minus J_k;
  *   - for a candidate j, rho_j^2 = ||s||^2 - (s . a_j)^2 / ||a_j||^2, with
  *     a_j the whole row j of A (as a vector over l): the residual norm
  *     after adding j alone with its best coefficient;
@@ -442,11 +444,11 @@ int orc_spai_adaptive(int n, const int *Arp, const int *Aci, const double *Av,
                 /* candidates: columns l of A over the residual's support */
                 int ccap = 0;
                 for (int l = 0; l < nI; l++)
-                    if (sv[l] != 0.0) ccap += ATrp[I[l] + 1] - ATrp[I[l]];
+                    if (fabs(sv[l]) > 0x1p-40) ccap += ATrp[I[l] + 1] - ATrp[I[l]];
                 int *C = (int *)malloc(sizeof(int) * (size_t)(ccap > 0 ? ccap : 1));
                 int nC = 0;
                 for (int l = 0; l < nI; l++)
-                    if (sv[l] != 0.0)
+                    if (fabs(sv[l]) > 0x1p-40)
                         for (int e = ATrp[I[l]]; e < ATrp[I[l] + 1]; e++) C[nC++] = ATci[e];
                 qsort(C, (size_t)nC, sizeof(int), cmp_int);
                 u = 0;

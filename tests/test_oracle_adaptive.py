@@ -39,7 +39,7 @@ def _brute_force_first_addition(A, k, m0):
     D = A.dense()
     s = m0 * D[k, :]  # row k of M A with M(k, :) = m0 e_k^T
     s[k] -= 1.0
-    support = np.flatnonzero(s != 0.0)
+    support = np.flatnonzero(np.abs(s) > 2.0 ** -40)
     cands = sorted(set(np.flatnonzero(D[:, support].any(axis=1))) - {k})
     if not cands:
         return None, []
