@@ -223,6 +223,38 @@ void bspai_multi_free(bspai_multi *plan);
 int bspai_multi_group_blocks(const bspai_multi *plan);
 
 /*
+ * bspai_build_adaptive -- SPAI with Algorithm 1's augmentation loop, then
+ * bucketing as bspai_build.  Run on A^T (row k of M is column k of
+ * SPAI(A^T)).  Row k starts from J0(k,:) (NULL: the identity, the paper's
+ * setting) and for step = 0..alpha: solves the least squares problem
+ * (redprob) on the shadow of J_k by Householder QR (recomputed each round),
+ * stops when the residual's 2-norm is <= eps or after the last solve, and
+ * otherwise adds up to beta candidates: the rows j of A with a_jl != 0 for
+ * some l in the residual's support (|s(l)| > 2^-40), not yet in J_k, scored by the residual
+ * norm after adding j alone, rho_j^2 = ||s||^2 - (s . a_j)^2 / ||a_j||^2
+ * (a_j the whole row j of A); rho_j is compared after rounding to fp32; the
+ * candidates with rho_j at or below their mean (summed in ascending j),
+ * ordered by (rho_j, j), join first.  No acceptable candidate ends the row.
+ * Limits: initial entries + alpha * beta <= 64 per row; at most 4096 shadow
+ * rows and 4096 distinct candidates per round (EINVAL names the row).
+ * steps_host: NULL or a host array of n ints (least squares solves per row).
+ * Errors: EZEROROW, ERANK, EINVAL, ENOMEM, EHIP.  Synchronises `stream`.
+ */
+typedef struct {
+    int alpha;      /* augmentation rounds: at most alpha + 1 solves per row */
+    int beta;       /* at most beta entries added per round */
+    double eps;     /* a row is done when its least squares residual is <= eps */
+} bspai_adaptive_opts;
+
+int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0, const bspai_adaptive_opts *ad, double eps_b,
+                         const bspai_prec *precs, int q, const bspai_opts *opts, bspai_handle **M_out,
+                         int32_t *steps_host, void *stream);
+
+/* bspai_export_pattern -- copy M's CSR pattern to host arrays (n + 1 and nnz
+ * ints; either may be NULL).  Synchronous. */
+int bspai_export_pattern(const bspai_handle *M, int32_t *row_ptr_host, int32_t *col_host);
+
+/*
  * Kernel of bspai_apply / bspai_apply_T for one right-hand side.  All of them
  * compute Algorithm 3's sum with the same per-bucket accumulation precision;
  * they differ in how entries are grouped over threads, so results can

@@ -118,7 +118,8 @@ SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
            "bspai_export", "bspai_free", "bspai_last_error", "bspai_grad_vals", "bspai_set_profiling",
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
            "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
-           "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply")
+           "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply", "bspai_build_adaptive",
+           "bspai_export_pattern")
 
 
 def set_profiling(on: bool) -> None:
@@ -237,6 +238,15 @@ class Handle:
                     ell_width=list(s.ell_width[:q]), col_bytes=list(s.col_bytes[:q]),
                     apply_kind=list(s.apply_kind))
 
+    def export_pattern(self):
+        """M's CSR pattern (row_ptr, col) as numpy int32 arrays."""
+        import numpy as np
+
+        rp = np.zeros(self.n + 1, dtype=np.int32)
+        col = np.zeros(max(self.nnz, 1), dtype=np.int32)
+        _check(_lib.bspai_export_pattern(self.ptr, rp.ctypes.data_as(C.c_void_p), col.ctypes.data_as(C.c_void_p)))
+        return rp, col[: self.nnz]
+
     def set_apply_kind(self, kind: int, trans: bool = False) -> None:
         """Kernel of apply (trans False) or apply_T: 0 automatic, 1 padded
         copies, 2 LDS tiles, 3 two rows per thread, 4 lanes per row."""
@@ -270,6 +280,39 @@ def build(A: CSRMatrix, P: Optional[CSRMatrix] = None, eps: float = 1e-4, precs:
     _check(_lib.bspai_build(C.byref(a), C.byref(p) if p is not None else None, float(eps), pids, q,
                             C.byref(_opts(build_T, keep_fp64_M, scale)), C.byref(out), _stream(stream)))
     return Handle(out.value, A.n, P.nnz if P is not None else A.nnz)
+
+
+class _AdOpts(C.Structure):
+    _fields_ = [("alpha", C.c_int), ("beta", C.c_int), ("eps", C.c_double)]
+
+
+_lib.bspai_build_adaptive.argtypes = [C.POINTER(_CSR), C.POINTER(_Pattern), C.POINTER(_AdOpts), C.c_double,
+                                      C.POINTER(C.c_int), C.c_int, C.POINTER(_Opts), C.POINTER(_vp), _vp, _vp]
+_lib.bspai_build_adaptive.restype = C.c_int
+_lib.bspai_export_pattern.argtypes = [_vp, _vp, _vp]
+_lib.bspai_export_pattern.restype = C.c_int
+
+
+def build_adaptive(A: CSRMatrix, J0: Optional[CSRMatrix] = None, alpha: int = 5, beta: int = 8,
+                   eps_spai: float = 0.4, eps: float = 1e-4, precs: Sequence = ("fp64",), build_T: bool = True,
+                   keep_fp64_M: bool = True, stream=None):
+    """SPAI with Algorithm 1's augmentation loop (bspai_build_adaptive), then
+    bucketing.  J0 None: identity start.  Returns (Handle, steps per row)."""
+    import numpy as np
+
+    ids, q = _prec_ids(precs)
+    o = _opts(build_T, keep_fp64_M, False)
+    ad = _AdOpts(int(alpha), int(beta), float(eps_spai))
+    out = _vp()
+    steps = np.zeros(A.n, dtype=np.int32)
+    a = A._c()
+    p = J0._p() if J0 is not None else None
+    _check(_lib.bspai_build_adaptive(C.byref(a), C.byref(p) if p is not None else None, C.byref(ad), float(eps),
+                                     ids, q, C.byref(o), C.byref(out), steps.ctypes.data_as(C.c_void_p),
+                                     _stream(stream)))
+    st = _BStats()
+    _check(_lib.bspai_stats(out.value, C.byref(st)))
+    return Handle(out.value, A.n, st.nnz), steps
 
 
 def import_m(M: CSRMatrix, eps: float, precs: Sequence, build_T: bool = True, keep_fp64_M: bool = True,
@@ -413,5 +456,5 @@ class MultiPlan:
 
 from .autograd import BSPAISolve  # noqa: E402  (needs the names above)
 
-__all__ = ["CSRMatrix", "Handle", "build", "import_m", "apply", "apply_T", "solve", "MultiPlan", "BSPAISolve",
+__all__ = ["CSRMatrix", "Handle", "build", "build_adaptive", "import_m", "apply", "apply_T", "solve", "MultiPlan", "BSPAISolve",
            "BSPAIError", "SYMBOLS", "PREC"]

@@ -428,6 +428,316 @@ __global__ void __launch_bounds__(kBigThreads) k_spai_big(SpaiBigArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ adaptive SPAI
+//
+// Algorithm 1 with its augmentation loop, run on A^T: one block per row k of
+// M.  Each round rebuilds the shadow of J_k, solves the least squares
+// problem by Householder QR in global scratch, forms the residual, and (if
+// it is above eps and rounds remain) scores the candidates from the columns
+// of A over the residual's support by the univariate minimisation
+// rho_j^2 = ||s||^2 - (s . a_j)^2 / ||a_j||^2 (a_j the whole row j of A),
+// rounded to fp32; the candidates at or below the mean (summed in ascending
+// j), ordered by (rho_j, j), join J_k up to beta of them.
+
+constexpr int kAdThreads = 256;
+constexpr int kAdCand = 8192;    // candidate entries per round (LDS)
+constexpr int kAdShadow = 4096;  // shadow rows (LDS)
+constexpr int kAdJ = 64;         // pattern entries per row of M
+
+struct AdaptiveArgs {
+  int n, alpha, beta, jmax;
+  double eps;
+  const int32_t *arp, *acol;
+  const double *aval;
+  const int32_t *atrp, *atcol;  // pattern of A^T (columns of A)
+  const int32_t *j0rp, *j0col;  // initial pattern (null: identity)
+  const double *rownorm2;       // sum of a_jl^2 over row j of A, in CSR order
+  const int32_t *rows;          // rows of this batch
+  double *tiles, *rhs;          // per block: kAdShadow * jmax and kAdShadow doubles
+  int32_t *cnt, *cols, *steps;
+  double *vals;
+  int32_t *err;                 // [0] zero row, [1] rank, [2] limits: smallest row
+};
+
+__global__ void k_rownorm2(int n, const int32_t *rp, const double *v, double *out) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int e = rp[j]; e < rp[j + 1]; e++) s += v[e] * v[e];
+  out[j] = s;
+}
+
+// ascending sort of len (a power of two) keys in LDS by the whole block
+template <typename K>
+__device__ void block_bitonic(K *S, int len) {
+  for (int size = 2; size <= len; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < len / 2; t += kAdThreads) {
+        int lo = 2 * stride * (t / stride) + (t % stride);
+        int hi = lo + stride;
+        bool up = ((lo & size) == 0);
+        K x = S[lo], y = S[hi];
+        if ((x > y) == up) {
+          S[lo] = y;
+          S[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kAdThreads) k_spai_adaptive(AdaptiveArgs a) {
+  extern __shared__ double lds_a[];
+  unsigned long long *key = reinterpret_cast<unsigned long long *>(lds_a);  // kAdCand
+  int32_t *S = reinterpret_cast<int32_t *>(lds_a);                          // aliases key
+  int32_t *I = reinterpret_cast<int32_t *>(lds_a + kAdCand);                // kAdShadow
+  double *sv = lds_a + kAdCand + kAdShadow / 2;                             // kAdShadow
+  __shared__ int32_t J[kAdJ], off[kAdJ + 1];
+  __shared__ double yv[kAdJ], diagR[kAdJ];
+  __shared__ double sh[kAdThreads / 64];
+  __shared__ int s_n, s_nI, s_kpos, s_nJ, s_done, s_nsolve;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = a.rows[blockIdx.x];
+  double *tile = a.tiles + (int64_t)blockIdx.x * kAdShadow * a.jmax;
+  double *rhs = a.rhs + (int64_t)blockIdx.x * kAdShadow;
+  auto fail_row = [&](int slot) {
+    if (tid == 0) atomicMin(&a.err[slot], k);
+  };
+  if (tid == 0) {
+    int nJ = 0;
+    if (a.j0rp) {
+      for (int e = a.j0rp[k]; e < a.j0rp[k + 1] && nJ < a.jmax; e++) {
+        int v = a.j0col[e], p = nJ++;  // insertion sort
+        while (p > 0 && J[p - 1] > v) J[p] = J[p - 1], p--;
+        J[p] = v;
+      }
+    } else {
+      J[nJ++] = k;
+    }
+    s_nJ = nJ;
+    s_nsolve = 0;
+  }
+  __syncthreads();
+  for (int step = 0; step <= a.alpha; step++) {
+    const int nJ = s_nJ;
+    // ---- shadow: the nonzero columns of the rows J of A, sorted, unique
+    if (tid == 0) {
+      int o = 0;
+      for (int c = 0; c < nJ; c++) {
+        off[c] = o;
+        o += a.arp[J[c] + 1] - a.arp[J[c]];
+      }
+      off[nJ] = o;
+      s_n = o;
+    }
+    __syncthreads();
+    const int nc = s_n;
+    if (nc > kAdCand) return fail_row(2);
+    for (int c = tid; c < nJ; c += kAdThreads) {
+      int o = off[c];
+      for (int p = a.arp[J[c]]; p < a.arp[J[c] + 1]; p++) S[o++] = a.aval[p] != 0.0 ? a.acol[p] : INT_MAX;
+    }
+    int P2 = 1;
+    while (P2 < nc) P2 <<= 1;
+    __syncthreads();
+    for (int p = nc + tid; p < P2; p += kAdThreads) S[p] = INT_MAX;
+    __syncthreads();
+    block_bitonic<int32_t>(S, P2);
+    if (w == 0) {  // compaction of the distinct indices by one wavefront
+      int cntI = 0;
+      for (int b0 = 0; b0 < nc; b0 += 64) {
+        int p = b0 + lane;
+        int v = p < nc ? S[p] : INT_MAX;
+        bool keep = v != INT_MAX && (p == 0 || S[p - 1] != v);
+        unsigned long long m = __ballot(keep);
+        int pos = cntI + __popcll(m & ((1ull << lane) - 1ull));
+        if (keep && pos < kAdShadow) I[pos] = v;
+        cntI += __popcll(m);
+      }
+      if (lane == 0) s_nI = cntI;
+    }
+    __syncthreads();
+    const int nI = s_nI;
+    if (nI > kAdShadow) return fail_row(2);
+    if (tid == 0) {
+      int p = lower_bound_i(I, nI, k);
+      s_kpos = (p < nI && I[p] == k) ? p : -1;
+    }
+    __syncthreads();
+    const int kpos = s_kpos;
+    if (kpos < 0) return fail_row(0);
+    if (nI < nJ) return fail_row(1);
+    // ---- tile A(J, I)^T in scratch, column c = row J[c] of A
+    auto scatter = [&]() {
+      for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) tile[p] = 0.0;
+      __syncthreads();
+      for (int c = tid; c < nJ; c += kAdThreads)
+        for (int p = a.arp[J[c]]; p < a.arp[J[c] + 1]; p++)
+          if (a.aval[p] != 0.0) tile[lower_bound_i(I, nI, a.acol[p]) + (int64_t)c * nI] = a.aval[p];
+      __syncthreads();
+    };
+    scatter();
+    for (int l = tid; l < nI; l += kAdThreads) rhs[l] = (l == kpos) ? 1.0 : 0.0;
+    double fl = 0.0;
+    for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) fl += tile[p] * tile[p];
+    const double fro = sqrt(block_sum_big(fl, sh));
+    for (int c = 0; c < nJ; c++) {
+      double *col = tile + (int64_t)c * nI;
+      double s2 = 0.0;
+      for (int l = c + tid; l < nI; l += kAdThreads) s2 += col[l] * col[l];
+      double nrm = sqrt(block_sum_big(s2, sh));
+      double al = col[c];
+      double be = -copysign(nrm, al);
+      if (nrm == 0.0 || fabs(be) <= (double)nJ * 0x1p-53 * fro) return fail_row(1);
+      __syncthreads();
+      if (tid == 0) {
+        col[c] = al - be;
+        diagR[c] = be;
+      }
+      __syncthreads();
+      double vt = 0.0;
+      for (int l = c + tid; l < nI; l += kAdThreads) vt += col[l] * col[l];
+      const double vtv = block_sum_big(vt, sh);
+      for (int jj = c + 1 + w; jj <= nJ; jj += kAdThreads / 64) {
+        double *cj = (jj < nJ) ? tile + (int64_t)jj * nI : rhs;
+        double d = 0.0;
+        for (int l = c + lane; l < nI; l += 64) d += col[l] * cj[l];
+        double f = 2.0 * wave_sum_d(d) / vtv;
+        for (int l = c + lane; l < nI; l += 64) cj[l] -= f * col[l];
+      }
+      __syncthreads();
+    }
+    for (int c = tid; c < nJ; c += kAdThreads) yv[c] = rhs[c];
+    __syncthreads();
+    for (int c = nJ - 1; c >= 0; c--) {
+      double yc = yv[c] / diagR[c];
+      __syncthreads();
+      if (tid == 0) yv[c] = yc;
+      const double *Rc = tile + (int64_t)c * nI;
+      for (int i = tid; i < c; i += kAdThreads) yv[i] -= Rc[i] * yc;
+      __syncthreads();
+    }
+    if (tid == 0) s_nsolve++;
+    // ---- residual s = Abar m - e_k on the shadow (tile rebuilt)
+    scatter();
+    double q2 = 0.0;
+    for (int l = tid; l < nI; l += kAdThreads) {
+      double t = 0.0;
+      for (int c = 0; c < nJ; c++) t += tile[l + (int64_t)c * nI] * yv[c];
+      t -= (l == kpos) ? 1.0 : 0.0;
+      sv[l] = t;
+      q2 += t * t;
+    }
+    const double ns2 = block_sum_big(q2, sh);
+    if (tid == 0) s_done = (sqrt(ns2) <= a.eps || step == a.alpha) ? 1 : 0;
+    __syncthreads();
+    if (s_done) break;
+    // ---- candidates: columns l of A over the residual's support, minus J
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    for (int l = tid; l < nI; l += kAdThreads) {
+      if (!(fabs(sv[l]) > 0x1p-40)) continue;  // rounding noise of an exact fit counts as zero
+      const int i = I[l];
+      const int len = a.atrp[i + 1] - a.atrp[i];
+      int o = atomicAdd(&s_n, len);
+      for (int e = 0; e < len && o + e < kAdCand; e++) S[o + e] = a.atcol[a.atrp[i] + e];
+    }
+    __syncthreads();
+    const int ncand = s_n;
+    if (ncand > kAdCand) return fail_row(2);
+    P2 = 1;
+    while (P2 < ncand) P2 <<= 1;
+    for (int p = ncand + tid; p < P2; p += kAdThreads) S[p] = INT_MAX;
+    __syncthreads();
+    block_bitonic<int32_t>(S, P2);
+    // distinct candidates not in J, ascending, moved to the upper half of the
+    // key area as int32 (keys are written below them)
+    int32_t *C = S + kAdCand;  // second half of the 64-bit key array, as ints
+    if (w == 0) {
+      int nC = 0;
+      for (int b0 = 0; b0 < ncand; b0 += 64) {
+        int p = b0 + lane;
+        int v = p < ncand ? S[p] : INT_MAX;
+        bool keep = v != INT_MAX && (p == 0 || S[p - 1] != v);
+        if (keep) {
+          for (int c = 0; c < nJ; c++) keep = keep && (J[c] != v);
+        }
+        unsigned long long m = __ballot(keep);
+        int pos = nC + __popcll(m & ((1ull << lane) - 1ull));
+        if (keep && pos < kAdCand / 2) C[pos] = v;  // C and rho share the upper half
+        nC += __popcll(m);
+      }
+      if (lane == 0) s_n = nC;
+    }
+    __syncthreads();
+    const int nC = s_n;
+    if (nC > kAdCand / 2) return fail_row(2);
+    // rho_j rounded to fp32, kept as its bit pattern beside j
+    float *rho = reinterpret_cast<float *>(C + nC);
+    for (int t = tid; t < nC; t += kAdThreads) {
+      const int j = C[t];
+      double dot = 0.0;
+      for (int e = a.arp[j]; e < a.arp[j + 1]; e++) {
+        int p = lower_bound_i(I, nI, a.acol[e]);
+        if (p < nI && I[p] == a.acol[e]) dot += sv[p] * a.aval[e];
+      }
+      const double nrm = a.rownorm2[j];
+      const double r2 = nrm > 0.0 ? ns2 - dot * dot / nrm : ns2;
+      rho[t] = (float)sqrt(r2 > 0.0 ? r2 : 0.0);
+    }
+    __syncthreads();
+    if (tid == 0) {  // mean over the candidates, ascending j, in FP64
+      double sum = 0.0;
+      for (int t = 0; t < nC; t++) sum += (double)rho[t];
+      sh[0] = nC > 0 ? sum / nC : 0.0;
+      s_n = 0;
+    }
+    __syncthreads();
+    const double mean = sh[0];
+    __syncthreads();
+    // acceptable candidates as 64-bit keys (rho bits, j) in the lower half
+    for (int t = tid; t < nC; t += kAdThreads) {
+      if ((double)rho[t] <= mean) {
+        int o = atomicAdd(&s_n, 1);
+        key[o] = ((unsigned long long)__float_as_uint(rho[t]) << 32) | (unsigned)C[t];
+      }
+    }
+    __syncthreads();
+    const int nacc = s_n;
+    int P = 1;
+    while (P < nacc) P <<= 1;
+    for (int p = nacc + tid; p < P; p += kAdThreads) key[p] = ~0ull;
+    __syncthreads();
+    block_bitonic<unsigned long long>(key, P);
+    if (tid == 0) {
+      int add = nacc < a.beta ? nacc : a.beta;
+      if (add > a.jmax - nJ) add = a.jmax - nJ;
+      int cntJ = nJ;
+      for (int t = 0; t < add; t++) {
+        int v = (int)(key[t] & 0xFFFFFFFFull), p = cntJ++;
+        while (p > 0 && J[p - 1] > v) J[p] = J[p - 1], p--;
+        J[p] = v;
+      }
+      s_nJ = cntJ;
+      s_done = add == 0;
+    }
+    __syncthreads();
+    if (s_done) break;
+  }
+  // the last solve belongs to the final J (a round that added entries always
+  // solves again before it can end)
+  const int nJ = s_nJ;
+  for (int c = tid; c < nJ; c += kAdThreads) {
+    a.cols[(int64_t)k * a.jmax + c] = J[c];
+    a.vals[(int64_t)k * a.jmax + c] = yv[c];
+  }
+  if (tid == 0) {
+    a.cnt[k] = nJ;
+    a.steps[k] = s_nsolve;
+  }
+}
+
 // ------------------------------------------------------------------ buckets
 
 // ||M||_inf: each row summed left to right in CSR order; the maximum of the
@@ -996,6 +1306,148 @@ extern "C" int bspai_import(const bspai_csr *M, double eps_b, const bspai_prec *
     return rc;
   }
   return finish_build(h, precs, q, eps_b, o, s, out);
+}
+
+namespace bspai {
+__global__ void k_iota(int n, int32_t *o) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = i;
+}
+
+// rows of width jmax (cnt[k] used) into CSR at rp
+__global__ void k_compact_rows(int n, int jmax, const int32_t *cnt, const int32_t *cols, const double *vals,
+                               const int32_t *rp, int32_t *col, double *val) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  for (int c = 0; c < cnt[k]; c++) {
+    col[rp[k] + c] = cols[(int64_t)k * jmax + c];
+    val[rp[k] + c] = vals[(int64_t)k * jmax + c];
+  }
+}
+}  // namespace bspai
+
+extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0, const bspai_adaptive_opts *ad,
+                                    double eps_b, const bspai_prec *precs, int q, const bspai_opts *opts,
+                                    bspai_handle **out, int32_t *steps_host, void *stream) {
+  using namespace bspai;
+  if (!out) return fail(BSPAI_EINVAL, "bspai_build_adaptive: null output");
+  *out = nullptr;
+  if (!A || !ad) return fail(BSPAI_EINVAL, "bspai_build_adaptive: null argument");
+  int rc;
+  if ((rc = check_csr("A", A->n, A->nnz, A->row_ptr, A->col))) return rc;
+  if (A->n < 1 || (A->nnz > 0 && !A->val)) return fail(BSPAI_EINVAL, "bspai_build_adaptive: empty A or null values");
+  if (J0 && (rc = check_csr("J0", J0->n, J0->nnz, J0->row_ptr, J0->col))) return rc;
+  if (J0 && J0->n != A->n) return fail(BSPAI_EINVAL, "bspai_build_adaptive: J0 is %d x %d, A %d x %d", J0->n, J0->n,
+                                       A->n, A->n);
+  if (ad->alpha < 0 || ad->beta < 0 || !(ad->eps >= 0) || !std::isfinite(ad->eps))
+    return fail(BSPAI_EINVAL, "bspai_build_adaptive: need alpha >= 0, beta >= 0 and a finite eps >= 0");
+  if ((rc = check_precs(precs, q))) return rc;
+  if (!(eps_b >= 0) || !std::isfinite(eps_b)) return fail(BSPAI_EINVAL, "eps_b must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = A->n;
+  const int64_t nnz = A->nnz;
+  int j0max = 1;
+  if (J0) {
+    std::vector<int32_t> h(n + 1);
+    BSPAI_HIP(hipMemcpy(h.data(), J0->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    j0max = 0;
+    for (int i = 0; i < n; i++) j0max = std::max(j0max, h[i + 1] - h[i]);
+  }
+  const int64_t jmax64 = (int64_t)j0max + (int64_t)ad->alpha * ad->beta;
+  if (jmax64 > kAdJ)
+    return fail(BSPAI_EINVAL, "bspai_build_adaptive: initial entries + alpha * beta = %lld exceeds %d per row",
+                (long long)jmax64, kAdJ);
+  const int jmax = (int)std::max<int64_t>(jmax64, 1);
+  const int batch = std::min(n, 512);
+  int32_t *trp = nullptr, *tcol = nullptr, *iota = nullptr, *cnt = nullptr, *cols = nullptr, *stp = nullptr,
+          *err = nullptr, *mrp = nullptr, *mcol = nullptr;
+  double *rn2 = nullptr, *vals = nullptr, *tiles = nullptr, *rhs = nullptr, *mval = nullptr;
+  void *tmp = nullptr;
+  auto body = [&]() -> int {
+    int r;
+    if ((r = dalloc_t(&trp, (size_t)n + 1)) || (r = dalloc_t(&tcol, (size_t)nnz + 1)) ||
+        (r = dalloc_t(&iota, (size_t)n)) || (r = dalloc_t(&cnt, (size_t)n)) ||
+        (r = dalloc_t(&cols, (size_t)n * jmax)) || (r = dalloc_t(&stp, (size_t)n)) || (r = dalloc_t(&err, 3)) ||
+        (r = dalloc_t(&rn2, (size_t)n)) || (r = dalloc_t(&vals, (size_t)n * jmax)) ||
+        (r = dalloc_t(&tiles, (size_t)batch * kAdShadow * jmax)) || (r = dalloc_t(&rhs, (size_t)batch * kAdShadow)))
+      return r;
+    if ((r = csr_transpose(n, nnz, A->row_ptr, A->col, nullptr, 0, trp, tcol, nullptr, s))) return r;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_rownorm2, dim3(g), dim3(256), 0, s, n, A->row_ptr, A->val, rn2);
+    hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, s, n, iota);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n, s));
+    const int32_t init[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+    BSPAI_HIP(hipMemcpyAsync(err, init, sizeof(init), hipMemcpyHostToDevice, s));
+    const size_t lds = sizeof(double) * ((size_t)kAdCand + kAdShadow / 2 + kAdShadow);
+    BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai_adaptive, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    AdaptiveArgs a;
+    a.n = n;
+    a.alpha = ad->alpha;
+    a.beta = ad->beta;
+    a.jmax = jmax;
+    a.eps = ad->eps;
+    a.arp = A->row_ptr;
+    a.acol = A->col;
+    a.aval = A->val;
+    a.atrp = trp;
+    a.atcol = tcol;
+    a.j0rp = J0 ? J0->row_ptr : nullptr;
+    a.j0col = J0 ? J0->col : nullptr;
+    a.rownorm2 = rn2;
+    a.tiles = tiles;
+    a.rhs = rhs;
+    a.cnt = cnt;
+    a.cols = cols;
+    a.steps = stp;
+    a.vals = vals;
+    a.err = err;
+    for (int r0 = 0; r0 < n; r0 += batch) {
+      a.rows = iota + r0;
+      const int nb = std::min(batch, n - r0);
+      hipLaunchKernelGGL(k_spai_adaptive, dim3(nb), dim3(kAdThreads), lds, s, a);
+      BSPAI_CHECK_LAUNCH();
+    }
+    int32_t he[3];
+    BSPAI_HIP(hipMemcpyAsync(he, err, sizeof(he), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    if (he[0] != INT32_MAX) return fail(BSPAI_EZEROROW, "bspai_build_adaptive: row %d of M is zero (a_kk = 0?)", he[0]);
+    if (he[1] != INT32_MAX) return fail(BSPAI_ERANK, "bspai_build_adaptive: rank-deficient least squares in row %d", he[1]);
+    if (he[2] != INT32_MAX)
+      return fail(BSPAI_EINVAL, "bspai_build_adaptive: row %d exceeds %d shadow rows or %d candidates", he[2],
+                  kAdShadow, kAdCand / 2);
+    if (steps_host) BSPAI_HIP(hipMemcpy(steps_host, stp, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    // CSR of M
+    if ((r = dalloc_t(&mrp, (size_t)n + 1)) || (r = dalloc(&tmp, scan_tmp_bytes(n)))) return r;
+    if ((r = exclusive_scan(cnt, mrp, n, tmp, s))) return r;
+    int32_t mnnz = 0;
+    BSPAI_HIP(hipMemcpyAsync(&mnnz, mrp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    if ((r = dalloc_t(&mcol, (size_t)mnnz + 1)) || (r = dalloc_t(&mval, (size_t)mnnz + 1))) return r;
+    hipLaunchKernelGGL(k_compact_rows, dim3(g), dim3(256), 0, s, n, jmax, cnt, cols, vals, mrp, mcol, mval);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipStreamSynchronize(s));
+    bspai_csr Mc;
+    Mc.n = n;
+    Mc.nnz = mnnz;
+    Mc.row_ptr = mrp;
+    Mc.col = mcol;
+    Mc.val = mval;
+    return bspai_import(&Mc, eps_b, precs, q, opts, out, stream);
+  };
+  rc = body();
+  (void)hipStreamSynchronize(s);
+  dfree(trp), dfree(tcol), dfree(iota), dfree(cnt), dfree(cols), dfree(stp), dfree(err), dfree(rn2), dfree(vals);
+  dfree(tiles), dfree(rhs), dfree(mrp), dfree(mcol), dfree(mval), dfree(tmp);
+  return rc;
+}
+
+extern "C" int bspai_export_pattern(const bspai_handle *M, int32_t *row_ptr_host, int32_t *col_host) {
+  using namespace bspai;
+  if (!M) return fail(BSPAI_EINVAL, "bspai_export_pattern: null handle");
+  if (row_ptr_host) BSPAI_HIP(hipMemcpy(row_ptr_host, M->m_rp, sizeof(int32_t) * ((size_t)M->n + 1), hipMemcpyDeviceToHost));
+  if (col_host && M->nnz) BSPAI_HIP(hipMemcpy(col_host, M->m_col, sizeof(int32_t) * (size_t)M->nnz, hipMemcpyDeviceToHost));
+  return BSPAI_OK;
 }
 
 extern "C" int bspai_stats(const bspai_handle *M, bspai_bucket_stats *o) {

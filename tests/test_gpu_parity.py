@@ -893,6 +893,70 @@ def test_exchange_latency_instrumentation(B):
         B.exchange_latency_us(0, 10)
 
 
+# ---------------------------------------------------------------- adaptive SPAI
+
+def _adaptive_cases():
+    rng = np.random.default_rng(71)
+    rnd = W.random_sparse(400, 0.015, rng, dominance=0.7)
+    return [("cfg1", W.config("1")["A"]), ("cfg2s", W.config("2", small=True)["A"]),
+            ("cfg5s", W.config("5", small=True)["A"]), ("rand400", rnd)]
+
+
+@pytest.mark.parametrize("case", _adaptive_cases(), ids=lambda c: c[0])
+@pytest.mark.parametrize("alpha,beta,eps", [(5, 8, 0.4), (3, 4, 0.1), (2, 8, 0.0)])
+def test_build_adaptive_matches_oracle(B, case, alpha, beta, eps):
+    """Pattern, per-row solve counts (integers: exact) and values of the
+    adaptive SPAI against the oracle."""
+    name, A = case
+    _say("adaptive", name, alpha, beta, eps)
+    ref = O.spai_adaptive(A, alpha=alpha, beta=beta, eps=eps)
+    assert ref["status"] == O.OK
+    h, steps = B.build_adaptive(B.CSRMatrix.from_host(A), alpha=alpha, beta=beta, eps_spai=eps,
+                                precs=["fp64"], eps=2.0 ** -53)
+    rp, col = h.export_pattern()
+    assert np.array_equal(steps, ref["steps"])
+    assert np.array_equal(rp, ref["M"].row_ptr)
+    assert np.array_equal(col, ref["M"].col)
+    m = h.export()["m64"]
+    for k in range(A.n):
+        s_, e_ = rp[k], rp[k + 1]
+        assert np.abs(m[s_:e_] - ref["M"].val[s_:e_]).max() <= 1e-10 * np.abs(ref["M"].val[s_:e_]).max(), k
+    h.free()
+
+
+def test_solve_with_adaptive_spai(B):
+    """BSPAI-GMRES-IR with the adaptive SPAI from an identity start (the
+    paper's setting, beta = 8) against the oracle's solve with its own
+    adaptive M."""
+    import torch
+
+    c = W.config("2", small=True)
+    A, b = c["A"], c["b"]
+    eps_b, precs = 1e-4, c["precs"]
+    _say("solve adaptive")
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    ref_m = O.spai_adaptive(A, alpha=5, beta=8, eps=0.3)["M"]
+    ref = O.gmres_ir(A, ref_m, O.Bucketed(ref_m, eps_b, precs), b, dot64=True, **kw)
+    Ad = B.CSRMatrix.from_host(A)
+    h, _ = B.build_adaptive(Ad, alpha=5, beta=8, eps_spai=0.3, precs=precs, eps=eps_b)
+    x, st = B.solve(Ad, _dev(b), h, **kw)
+    torch.cuda.synchronize()
+    _check_column(st, ref, O.backward_error(A, b, x.cpu().numpy()))
+    h.free()
+
+
+def test_build_adaptive_limits_and_errors(B):
+    A = W.config("1", small=True)["A"]
+    Ad = B.CSRMatrix.from_host(A)
+    with pytest.raises(B.BSPAIError):  # 1 + alpha * beta > 64
+        B.build_adaptive(Ad, alpha=8, beta=8)
+    D = np.diag(np.arange(1.0, 7.0))
+    D[2, 2] = 0.0
+    D[2, 3] = 1.0
+    with pytest.raises(B.BSPAIError):  # a_22 = 0 with the identity start: zero row
+        B.build_adaptive(B.CSRMatrix.from_host(W.from_dense(D)), alpha=1, beta=1)
+
+
 # ---------------------------------------------------------------- block path
 
 def test_build_powerlaw_small_all_rows(B):
