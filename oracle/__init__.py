@@ -19,7 +19,9 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
   the error bound of Theorem 3.1 as quoted in Section 2.3.
 * ``residual``  pinned: exact rational residual (double-double error bound).
 * ``gmres`` / ``gmres_ir``  pinned: termination in <= n steps, Arnoldi relation,
-  closed-form spectra, dense solves, backward error reaching O(u).
+  closed-form spectra, dense solves, backward error reaching O(u).  Their
+  bucketed-A option (``Ab``): a one-bucket A_b reproduces the u_p path bit for
+  bit, the first Arnoldi step by hand, the per-row product bound.
 * ``gradient``  pinned: dense ``numpy.linalg.solve`` adjoint and finite differences.
 """
 from __future__ import annotations
@@ -47,14 +49,16 @@ _i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
 
 class GmresOpts(C.Structure):
     _fields_ = [("ug", C.c_int), ("up", C.c_int), ("tau", C.c_double), ("max_it", C.c_int), ("trans", C.c_int),
-                ("dot64", C.c_int)]
+                ("dot64", C.c_int), ("arp_b", C.c_void_p), ("aci_b", C.c_void_p), ("at_b", C.c_void_p),
+                ("ab_b", C.c_void_p), ("qa", C.c_int)]
 
 
 class IROpts(C.Structure):
     _fields_ = [("ug", C.c_int), ("up", C.c_int), ("ur_dd", C.c_int), ("tau", C.c_double),
                 ("tol_rr", C.c_double), ("tol_be", C.c_double), ("i_max", C.c_int),
                 ("gmres_max", C.c_int), ("x0_mode", C.c_int), ("trans", C.c_int), ("dot64", C.c_int),
-                ("stag", C.c_double)]
+                ("stag", C.c_double), ("arp_b", C.c_void_p), ("aci_b", C.c_void_p), ("at_b", C.c_void_p),
+                ("ab_b", C.c_void_p), ("qa", C.c_int)]
 
 
 class IRStats(C.Structure):
@@ -313,14 +317,27 @@ def backward_error(A, b, x, dd: bool = True) -> float:
 
 # ---------------------------------------------------------------- Krylov
 
+def _set_ab(o, Ab, trans):
+    """Point the option struct at the bucketed A (A^T when trans); returns the
+    object that owns the arrays, to be kept alive over the call."""
+    if Ab is None:
+        return None
+    Aop_b = Ab.transpose() if trans else Ab
+    o.arp_b, o.aci_b = Aop_b.row_ptr.ctypes.data, Aop_b.col.ctypes.data
+    o.at_b, o.ab_b, o.qa = Aop_b.mt.ctypes.data, Aop_b.bucket.ctypes.data, Aop_b.q
+    return Aop_b
+
+
 def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32, max_it: Optional[int] = None,
-          trans: bool = False, want_basis: bool = False, dot64: bool = False) -> Dict:
+          trans: bool = False, want_basis: bool = False, dot64: bool = False,
+          Ab: Optional[Bucketed] = None) -> Dict:
     """One preconditioned MGS-GMRES solve (left: M A d = M r; trans: A^T M^T).
     dot64: dots and norms accumulated in FP64 over u_g data (the default sums
-    sequentially in u_g)."""
+    sequentially in u_g).  Ab: A applied bucketed (eqs. (nbe2), (fe2))."""
     n = A.n
     m = min(n, max_it if max_it is not None else n)
     o = GmresOpts(ug, up, float(tau), m, int(trans), int(dot64))
+    Aop_b = _set_ab(o, Ab, trans)
     d = np.zeros(n)
     its = C.c_int(0)
     rel = C.c_double(0)
@@ -347,13 +364,17 @@ def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32,
 
 def gmres_ir(A, M, Mb: Bucketed, b, ug: int = FP32, up: int = FP32, ur_dd: bool = True, tau: float = 1e-4,
              tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: Optional[int] = None,
-             x0_mode: int = 0, trans: bool = False, dot64: bool = False, stag_ratio: Optional[float] = 0.5) -> Dict:
+             x0_mode: int = 0, trans: bool = False, dot64: bool = False, stag_ratio: Optional[float] = 0.5,
+             Ab: Optional["Bucketed"] = None) -> Dict:
     """BSPAI-GMRES-IR (Algorithm 4).  M: FP64 SPAI as workloads.CSR (for x_0).
-    dot64 as in :func:`gmres`; stag_ratio None: no stagnation stop."""
+    dot64 as in :func:`gmres`; stag_ratio None: no stagnation stop; Ab: A
+    bucketed (Bucketed of A) to apply A inside GMRES as well (eqs. (nbe2),
+    (fe2)); None: A rounded to u_p."""
     n = A.n
     gm = min(n, gmres_max if gmres_max is not None else n)
     o = IROpts(ug, up, int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), gm, int(x0_mode),
                int(trans), int(dot64), -1.0 if stag_ratio is None else float(stag_ratio))
+    Aop_b = _set_ab(o, Ab, trans)
     st = IRStats()
     x = np.zeros(n)
     if trans:

@@ -734,6 +734,13 @@ typedef struct {
     int max_it;       /* iteration cap (<= n) */
     int trans;        /* 0: left-preconditioned M A, 1: right-preconditioned A^T M^T */
     int dot64;        /* 1: dots and norms accumulated in FP64 (see above) */
+    /* A applied bucketed too (eqs. (nbe2), (fe2)): CSR, stored values and
+     * bucket ids of A (of A^T when trans), q buckets; arp_b NULL: A rounded
+     * to u_p as above */
+    const int *arp_b, *aci_b;
+    const double *at_b;
+    const signed char *ab_b;
+    int qa;
 } orc_gmres_opts;
 
 static inline double wp(int prec, double x) {
@@ -789,11 +796,13 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
     for (int j = 0; j < m; j++) {
         double *vj = V + (size_t)j * n;
         if (o->trans == 0) {
-            orc_spmv(n, rp, ci, v, up, vj, w, ug);                /* w = A_p v_j */
+            if (o->arp_b) orc_apply(n, o->arp_b, o->aci_b, o->at_b, o->ab_b, o->qa, vj, w, ug);  /* w = A_b v_j */
+            else orc_spmv(n, rp, ci, v, up, vj, w, ug);           /* w = A_p v_j */
             orc_apply(n, mrp, mci, mt, mb, q, w, z, ug);          /* z = M_b w   */
         } else {
             orc_apply(n, mrp, mci, mt, mb, q, vj, w, ug);         /* w = M_b^T v_j */
-            orc_spmv(n, rp, ci, v, up, w, z, ug);                 /* z = A_p^T w   */
+            if (o->arp_b) orc_apply(n, o->arp_b, o->aci_b, o->at_b, o->ab_b, o->qa, w, z, ug);   /* z = A_b^T w */
+            else orc_spmv(n, rp, ci, v, up, w, z, ug);            /* z = A_p^T w   */
         }
         double *hj = H + (size_t)j * ld;
         for (int i = 0; i <= j; i++) {                             /* modified Gram-Schmidt */
@@ -889,6 +898,10 @@ typedef struct {
     int i_max, gmres_max, x0_mode, trans;
     int dot64;  /* GMRES dot products accumulated in FP64 (orc_gmres) */
     double stag;  /* stagnation ratio: 0 means 0.5, negative: no stagnation stop */
+    const int *arp_b, *aci_b;  /* bucketed A for GMRES, as in orc_gmres_opts */
+    const double *at_b;
+    const signed char *ab_b;
+    int qa;
 } orc_ir_opts;
 
 typedef struct {
@@ -916,7 +929,8 @@ int orc_gmres_ir(int n, const int *rp, const int *ci, const double *v,
     } else {
         for (int i = 0; i < n; i++) x[i] = 0.0;
     }
-    orc_gmres_opts go = {o->ug, o->up, o->tau, o->gmres_max, o->trans, o->dot64};
+    orc_gmres_opts go = {o->ug, o->up, o->tau, o->gmres_max, o->trans, o->dot64,
+                         o->arp_b, o->aci_b, o->at_b, o->ab_b, o->qa};
     int status = ORC_OK, stagnated = 0;
     double dx_prev = 0;
     int i = 0;
