@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--only-powerlaw", action="store_true", help="run only the power-law matrix measurement")
     ap.add_argument("--only-gradient", action="store_true", help="run only the 512^2 gradient measurement")
     ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive-SPAI measurement")
+    ap.add_argument("--only-bucketed-a", action="store_true", help="run only the bucketed-A measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy first (calibration of hardware byte counters)")
     args = ap.parse_args()
@@ -141,6 +142,9 @@ def main():
         return
     if args.only_adaptive:
         print(json.dumps({"adaptive_spai": adaptive_bench(B, W, torch, np, kw0)}), flush=True)
+        return
+    if args.only_bucketed_a:
+        print(json.dumps({"bucketed_a": bucketed_a_bench(B, W, torch, np, kw0)}), flush=True)
         return
     _log("generating workload")
     c = W.config("2")
@@ -268,6 +272,7 @@ def main():
         out["powerlaw"] = powerlaw_bench(B, W, torch, np, kw)
         out["gradient"] = gradient_bench(B, W, torch, np)
         out["adaptive_spai"] = adaptive_bench(B, W, torch, np, kw)
+        out["bucketed_a"] = bucketed_a_bench(B, W, torch, np, kw)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.eps, kw)
@@ -482,6 +487,49 @@ def adaptive_bench(B, W, torch, np, kw, reps=5):
         h.free()
         _log(f"{name}: build {build_s * 1e3:.1f} ms, nnz(M) {res[name]['nnz_M']}, its {ss['its']}, "
              f"{1.0 / el:.2f} solves/s")
+    return res
+
+
+def bucketed_a_bench(B, W, torch, np, kw, reps=5):
+    """A bucketed inside GMRES too (eqs. (nbe2), (fe2)) on the 256^2
+    convection-diffusion system, M as the headline (eps_b = 1e-4): per eps of
+    A, its bucket counts, the bytes of one product with A_b, iterations,
+    backward error and solve rate, against A rounded to fp32."""
+    c = W.config("2")
+    A, P = c["A"], c["P"]
+    Ad = B.CSRMatrix.from_host(A)
+    b = torch.as_tensor(c["b"], device="cuda")
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=1e-4, precs=c["precs"])
+    res = {"workload": "convdiff2d 256x256 (n=65536), M pattern(A^2) eps_b=1e-4; A bucketed fp64/fp32/fp16/bf16 "
+                       "at eps_A", "points": []}
+    vbytes = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1}
+
+    def run(hA):
+        B.solve(Ad, b, h, A_b=hA, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, ss = B.solve(Ad, b, h, A_b=hA, **kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        return ss, el
+
+    ss, el = run(None)
+    res["plain_fp32"] = {"a_value_bytes": 4 * A.nnz, "its": ss["its"], "its_total": ss["its_total"],
+                         "relres": ss["relres"][-1], "eta": ss["eta"][-1], "solves_per_s": 1.0 / el}
+    _log(f"A rounded to fp32: its {ss['its']} {1.0 / el:.2f} solves/s")
+    for eps in (1e-6, 1e-4, 1e-2):
+        hA = B.bucket_a(Ad, eps, c["precs"])
+        st = hA.stats()
+        ss, el = run(hA)
+        vb = int(sum(cnt * vbytes[p] for cnt, p in zip(st["count"], [0, 1, 2, 3])))
+        res["points"].append({"eps_A": eps, "bucket_counts": st["count"], "a_value_bytes": vb, "its": ss["its"],
+                              "its_total": ss["its_total"], "relres": ss["relres"][-1], "eta": ss["eta"][-1],
+                              "stop_reason": ss["stop_reason"], "solves_per_s": 1.0 / el})
+        _log(f"A_b eps {eps:g}: counts {st['count']} its {ss['its']} eta {ss['eta'][-1]:.2e} "
+             f"{1.0 / el:.2f} solves/s")
+        hA.free()
+    h.free()
     return res
 
 

@@ -170,6 +170,20 @@ int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, c
                    double *x, int nrhs, gmres_ir_stats *st_host, void *stream);
 
 /*
+ * gmres_ir_solve_ab -- gmres_ir_solve with A bucketed inside GMRES too
+ * (Section 3, eqs. (nbe2) and (fe2)): every Krylov product with A (A^T for
+ * trans) is the bucketed product of A_b (A_b^T), computed as bspai_apply
+ * computes M_b's, instead of the product of A rounded to u_g.  The refinement
+ * residual and the stopping tests keep the FP64 A.
+ *   A_b: handle from bspai_import of A itself (same n, same device; build_T
+ *   for trans), bucketed with its own eps and precisions; the caller keeps it
+ *   alive during the call.  Other arguments, workspace and errors as
+ *   gmres_ir_solve; EINVAL for a null A_b or one that does not fit A.
+ */
+int gmres_ir_solve_ab(const bspai_csr *A, const bspai_handle *A_b, const double *b, const bspai_handle *M,
+                      const gmres_ir_tol *tol, double *x, int nrhs, gmres_ir_stats *st_host, void *stream);
+
+/*
  * Many independent systems in one persistent launch (Algorithm 4 for each).
  *
  * bspai_multi_plan -- prepare the solve of systems A_k x_k = b_k, k < nsys,

@@ -85,6 +85,8 @@ _lib.bspai_import.argtypes = [C.POINTER(_CSR), C.c_double, C.POINTER(C.c_int), C
 _lib.bspai_apply.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int64, C.c_int, _vp]
 _lib.bspai_apply_T.argtypes = [_vp, _vp, _vp, C.c_int, C.c_int64, C.c_int, _vp]
 _lib.gmres_ir_solve.argtypes = [C.POINTER(_CSR), _vp, _vp, C.POINTER(_Tol), _vp, C.c_int, C.POINTER(_Stats), _vp]
+_lib.gmres_ir_solve_ab.argtypes = [C.POINTER(_CSR), _vp, _vp, _vp, C.POINTER(_Tol), _vp, C.c_int, C.POINTER(_Stats),
+                                   _vp]
 _lib.bspai_stats.argtypes = [_vp, C.POINTER(_BStats)]
 _lib.bspai_export.argtypes = [_vp, _vp, _vp, _vp]
 _lib.bspai_free.argtypes = [_vp]
@@ -109,7 +111,8 @@ _lib.bspai_multi_wait.argtypes = [_vp, C.POINTER(_Stats), _vp]
 _lib.bspai_multi_group_blocks.argtypes = [_vp]
 _lib.bspai_multi_free.argtypes = [_vp]
 _lib.bspai_multi_free.restype = None
-for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "bspai_stats",
+for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "gmres_ir_solve_ab",
+           "bspai_stats",
            "bspai_export", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll", "bspai_multi_wait",
            "bspai_multi_group_blocks"):
     getattr(_lib, _f).restype = C.c_int
@@ -119,7 +122,7 @@ SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
            "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
            "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply", "bspai_build_adaptive",
-           "bspai_export_pattern")
+           "bspai_export_pattern", "gmres_ir_solve_ab")
 
 
 def set_profiling(on: bool) -> None:
@@ -325,6 +328,15 @@ def import_m(M: CSRMatrix, eps: float, precs: Sequence, build_T: bool = True, ke
     return Handle(out.value, M.n, M.nnz)
 
 
+def bucket_a(A: CSRMatrix, eps: float, precs: Sequence, build_T: bool = False, keep_fp64: bool = False,
+             stream=None) -> Handle:
+    """A split into buckets by Algorithm 2's rule (thresholds fl(eps ||A||_inf)
+    / u_k), for the GMRES products of :func:`solve` (``A_b``); build_T for the
+    adjoint (trans) solve; keep_fp64 keeps a copy of A's FP64 values (needed
+    by Handle.export only)."""
+    return import_m(A, eps, precs, build_T=build_T, keep_fp64_M=keep_fp64, stream=stream)
+
+
 def _apply(fn, h: Handle, x: torch.Tensor, out: Optional[torch.Tensor], stream):
     if x.dtype not in (torch.float32, torch.float64) or not x.is_cuda:
         raise ValueError("x must be a float32/float64 CUDA tensor")
@@ -366,12 +378,14 @@ def _stag(r: Optional[float]) -> float:
 def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4,
           tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0,
           trans: bool = False, x: Optional[torch.Tensor] = None, stream=None, raise_noconv: bool = False,
-          stag_ratio: Optional[float] = 0.5):
+          stag_ratio: Optional[float] = 0.5, A_b: Optional[Handle] = None):
     """BSPAI-GMRES-IR.  b: [n] or [n, nrhs] (1 <= nrhs <= 64, row-major)
     float64 on the GPU.  Returns (x, stats): one stats dict for a 1-D b, a
     list of them (one per column) for a 2-D b.  ENOCONV is reported in the
     stats (status) unless raise_noconv.  stag_ratio: stop when a correction's
-    ||d||/||x|| exceeds stag_ratio times the previous one (None: never)."""
+    ||d||/||x|| exceeds stag_ratio times the previous one (None: never).
+    A_b: A bucketed (:func:`bucket_a`) for the products inside GMRES
+    (``gmres_ir_solve_ab``); None: A rounded to u_g."""
     if b.dtype != torch.float64 or not b.is_cuda or b.dim() not in (1, 2):
         raise ValueError("b must be a 1-D or 2-D float64 CUDA tensor")
     b = b.contiguous()
@@ -387,8 +401,13 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
     st = (_Stats * nrhs)()
     a = A._c()
     allow = () if raise_noconv else (ENOCONV,)
-    _check(_lib.gmres_ir_solve(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), nrhs, st,
-                               _stream(stream)), allow=allow)
+    if A_b is None:
+        rc = _lib.gmres_ir_solve(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), nrhs, st,
+                                 _stream(stream))
+    else:
+        rc = _lib.gmres_ir_solve_ab(C.byref(a), A_b.ptr, b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), nrhs, st,
+                                    _stream(stream))
+    _check(rc, allow=allow)
     if b.dim() == 1:
         return x, _stats_dict(st[0])
     return x, [_stats_dict(q) for q in st]

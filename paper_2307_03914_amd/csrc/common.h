@@ -182,9 +182,10 @@ bool apply_kind_ok(const BMat &M, int kind);
 int apply_kind_resolved(const BMat &M);
 
 // gmres_ir_solve for 2 <= R <= 64 right-hand sides (solve_batched.hip);
-// arguments already validated, m the GMRES cap.
+// arguments already validated, m the GMRES cap, Ab the bucketed A used inside
+// GMRES (NULL: A rounded to u_g).
 template <typename VT>
-int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
-                  int R, int m, gmres_ir_stats *st_host, hipStream_t s);
+int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+                  const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s);
 
 }  // namespace bspai

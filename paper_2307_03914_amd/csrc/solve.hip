@@ -578,12 +578,13 @@ static SysLayout sys_layout(int n, int64_t nnz, int m, bool tr) {
 static size_t solve_lds(int m) { return sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2) + kTileBytes; }
 
 // Parameters of one system whose workspace starts at `base` (rows split into
-// blocks of rpb rows): A rounded to u_g, A^T and its copy for trans.  `wide`
-// is set when the products need FP64 partials.  Enqueues work on s.
+// blocks of rpb rows): A rounded to u_g, A^T and its copy for trans; with Ab
+// the GMRES products use the bucketed A_b (A_b^T) instead of A rounded to u_g.
+// `wide` is set when the products need FP64 partials.  Enqueues work on s.
 template <typename VT>
-static int sys_setup(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
-                     int m, int G, int rpb, char *base, const SysLayout &L, SolveParams<VT> &p, bool &wide,
-                     hipStream_t s) {
+static int sys_setup(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+                     const gmres_ir_tol *tol, double *x, int m, int G, int rpb, char *base, const SysLayout &L,
+                     SolveParams<VT> &p, bool &wide, hipStream_t s) {
   const int n = A->n;
   const int64_t nnz = A->nnz;
   const bool tr = tol->trans != 0;
@@ -611,7 +612,7 @@ static int sys_setup(const bspai_csr *A, const double *b, const bspai_handle *M,
   p.a_col = acol;
   p.a_val = aval;
   VT *apv = reinterpret_cast<VT *>(base + L.ap);
-  if (nnz > 0) {
+  if (nnz > 0 && !Ab) {
     hipLaunchKernelGGL(k_to_prec<VT>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, aval, apv);
     BSPAI_CHECK_LAUNCH();
   }
@@ -627,6 +628,7 @@ static int sys_setup(const bspai_csr *A, const double *b, const bspai_handle *M,
   Ap.val[0] = apv;
   Ap.lanes = pick_lanes(Ap, nnz);
   Ap.aligned = 1;
+  if (Ab) Ap = tr ? Ab->matT : Ab->mat;
   p.Ap = Ap;
   p.Mb = tr ? M->matT : M->mat;
   auto clamp_lanes = [](int l) { return l <= 4 ? 4 : (l >= 16 ? 16 : 8); };
@@ -658,13 +660,14 @@ static int sys_setup(const bspai_csr *A, const double *b, const bspai_handle *M,
   p.stats = reinterpret_cast<gmres_ir_stats *>(base + L.stats);
   wide = sizeof(VT) == 8;
   for (int k = 0; k < p.Mb.nb; k++) wide = wide || p.Mb.prec[k] == BSPAI_FP64;
+  for (int k = 0; k < p.Ap.nb; k++) wide = wide || p.Ap.prec[k] == BSPAI_FP64;
   {
     const int cap = kTileBytes / (wide ? 8 : 4);
     auto rows_for_avg = [&](double avg) {
       int r = (int)(cap / (1.25 * std::max(avg, 1.0)));
       return std::max(1, std::min(kSolveThreads, r));
     };
-    p.rows_a = rows_for_avg((double)nnz / n);
+    p.rows_a = rows_for_avg((double)p.Ap.nnz / n);
     p.rows_m = rows_for_avg((double)p.Mb.nnz / n);
   }
   return BSPAI_OK;
@@ -694,8 +697,8 @@ static void *pick_single(bool wide, int ZR) {
 }
 
 template <typename VT>
-static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
-                       gmres_ir_stats *st_host, hipStream_t s) {
+static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+                       const gmres_ir_tol *tol, double *x, gmres_ir_stats *st_host, hipStream_t s) {
   const int n = A->n;
   const int64_t nnz = A->nnz;
   int m = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
@@ -737,7 +740,7 @@ static int solve_typed(const bspai_csr *A, const double *b, const bspai_handle *
   char *base = static_cast<char *>(g_ws.ptr);
   SolveParams<VT> p;
   bool wide = false;
-  int rc = sys_setup<VT>(A, b, M, tol, x, m, G, rpb, base, L, p, wide, s);
+  int rc = sys_setup<VT>(A, Ab, b, M, tol, x, m, G, rpb, base, L, p, wide, s);
   if (rc) return rc;
   BSPAI_HIP(hipMemsetAsync(p.grid.flags, 0, 4 * kMaxBlocks, s));
   BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
@@ -1073,7 +1076,7 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
   for (int k = 0; k < nsys; k++) {
     bool w = false;
     const int m = std::min(std::max(tol->gmres_max, 1), std::min(sys[k].A.n, kMaxGmres));
-    rc = sys_setup<VT>(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, m, gs[k], rows_for(sys[k].A.n, gs[k]),
+    rc = sys_setup<VT>(&sys[k].A, nullptr, sys[k].b, sys[k].M, tol, sys[k].x, m, gs[k], rows_for(sys[k].A.n, gs[k]),
                        mem + base[k], L[k], ps[k], w, s);
     if (rc) return bail(rc);
     ps[k].stats = stats + k;
@@ -1340,17 +1343,34 @@ extern "C" int bspai_multi_wait(bspai_multi *plan, gmres_ir_stats *st_host, void
 
 extern "C" void bspai_multi_free(bspai_multi *plan) { multi_release(plan); }
 
-extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
-                              double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
-  if (nrhs < 1 || nrhs > 64) return fail(BSPAI_EINVAL, "gmres_ir_solve: nrhs must be in 1..64 (got %d)", nrhs);
-  int rc = check_system(A, b, M, tol, x, "gmres_ir_solve");
+static int solve_entry(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+                       const gmres_ir_tol *tol, double *x, int nrhs, gmres_ir_stats *st_host, void *stream,
+                       const char *who) {
+  if (nrhs < 1 || nrhs > 64) return fail(BSPAI_EINVAL, "%s: nrhs must be in 1..64 (got %d)", who, nrhs);
+  int rc = check_system(A, b, M, tol, x, who);
   if (rc) return rc;
+  if (Ab) {
+    if (Ab->n != A->n) return fail(BSPAI_EINVAL, "%s: A is %d x %d but A_b is %d x %d", who, A->n, A->n, Ab->n, Ab->n);
+    if (tol->trans && !Ab->has_T) return fail(BSPAI_EINVAL, "%s: trans needs A_b built with build_T", who);
+    if (Ab->device != M->device) return fail(BSPAI_EINVAL, "%s: A_b lives on device %d", who, Ab->device);
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (nrhs > 1) {
     const int m = std::min(std::max(tol->gmres_max, 1), std::min(A->n, kMaxGmres));
-    if (tol->u_g == BSPAI_FP64) return solve_batched<double>(A, b, M, tol, x, nrhs, m, st_host, s);
-    return solve_batched<float>(A, b, M, tol, x, nrhs, m, st_host, s);
+    if (tol->u_g == BSPAI_FP64) return solve_batched<double>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
+    return solve_batched<float>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
   }
-  if (tol->u_g == BSPAI_FP64) return solve_typed<double>(A, b, M, tol, x, st_host, s);
-  return solve_typed<float>(A, b, M, tol, x, st_host, s);
+  if (tol->u_g == BSPAI_FP64) return solve_typed<double>(A, Ab, b, M, tol, x, st_host, s);
+  return solve_typed<float>(A, Ab, b, M, tol, x, st_host, s);
+}
+
+extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
+                              double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
+  return solve_entry(A, nullptr, b, M, tol, x, nrhs, st_host, stream, "gmres_ir_solve");
+}
+
+extern "C" int gmres_ir_solve_ab(const bspai_csr *A, const bspai_handle *A_b, const double *b, const bspai_handle *M,
+                                 const gmres_ir_tol *tol, double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
+  if (!A_b) return fail(BSPAI_EINVAL, "gmres_ir_solve_ab: null A_b");
+  return solve_entry(A, A_b, b, M, tol, x, nrhs, st_host, stream, "gmres_ir_solve_ab");
 }

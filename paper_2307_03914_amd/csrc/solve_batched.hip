@@ -414,8 +414,8 @@ struct DevBuf {
 };
 
 template <typename VT>
-int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol, double *x,
-                  int R, int m, gmres_ir_stats *st_host, hipStream_t s) {
+int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+                  const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s) {
   const int n = A->n;
   const int64_t nnz = A->nnz, nr = (int64_t)n * R;
   const bool tr = tol->trans != 0;
@@ -431,7 +431,8 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   const int rpp4 = vec4 ? kBT / (R / 4) : 1;
   const int nblk4 = (int)std::min<int64_t>(kBGrid, (n + rpp4 - 1) / rpp4);
 
-  // operators: A (or A^T) in FP64 and in u_g, M_b (or M_b^T), FP64 M for x_0
+  // operators: A (or A^T) in FP64 and, inside GMRES, in u_g or bucketed (A_b
+  // or A_b^T), M_b (or M_b^T), FP64 M for x_0
   DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb;
   int rc;
   const int32_t *arp = A->row_ptr, *acol = A->col;
@@ -443,7 +444,7 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
     if ((rc = csr_transpose(n, nnz, arp, acol, aval, 8, (int32_t *)trp.p, (int32_t *)tcol.p, tval.p, s))) return rc;
     arp = (const int32_t *)trp.p, acol = (const int32_t *)tcol.p, aval = (const double *)tval.p;
   }
-  if ((rc = dalloc(&apv.p, sizeof(VT) * (size_t)(nnz + 1))) || (rc = dalloc(&rbuf.p, 8 * (size_t)nr)) ||
+  if ((!Ab && (rc = dalloc(&apv.p, sizeof(VT) * (size_t)(nnz + 1)))) || (rc = dalloc(&rbuf.p, 8 * (size_t)nr)) ||
       (rc = dalloc(&rv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&wv.p, sizeof(VT) * (size_t)nr)) ||
       (rc = dalloc(&zv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&Vb.p, sizeof(VT) * (size_t)nr * (m + 1))) ||
       (rc = dalloc(&dtmp.p, 8 * (size_t)nr)) || (rc = dalloc(&parts.p, 2 * 8 * (size_t)kBGrid * R)) ||
@@ -457,7 +458,7 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   double *S = (double *)scal.p;  // 8 rows of R scalars
   double *H = (double *)Hb.p, *CS = (double *)csb.p, *SN = (double *)snb.p, *G = (double *)gb.p, *Y = (double *)yb.p;
   int *KC = (int *)kcb.p, *ACT = (int *)actb.p;
-  if (nnz > 0) {
+  if (nnz > 0 && !Ab) {
     hipLaunchKernelGGL(k_to_vt_vals<VT>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, s, nnz, aval, Ap);
     BSPAI_CHECK_LAUNCH();
   }
@@ -471,6 +472,7 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   Apm.rp[0] = arp;
   Apm.col[0] = acol;
   Apm.val[0] = Ap;
+  if (Ab) Apm = tr ? Ab->matT : Ab->mat;
   const BMat &Mb = tr ? M->matT : M->mat;
   const int fp64 = sizeof(VT) == 8;
 
@@ -662,9 +664,9 @@ int solve_batched(const bspai_csr *A, const double *b, const bspai_handle *M, co
   return BSPAI_OK;
 }
 
-template int solve_batched<float>(const bspai_csr *, const double *, const bspai_handle *, const gmres_ir_tol *,
-                                  double *, int, int, gmres_ir_stats *, hipStream_t);
-template int solve_batched<double>(const bspai_csr *, const double *, const bspai_handle *, const gmres_ir_tol *,
-                                   double *, int, int, gmres_ir_stats *, hipStream_t);
+template int solve_batched<float>(const bspai_csr *, const bspai_handle *, const double *, const bspai_handle *,
+                                  const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t);
+template int solve_batched<double>(const bspai_csr *, const bspai_handle *, const double *, const bspai_handle *,
+                                   const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t);
 
 }  // namespace bspai

@@ -52,4 +52,6 @@ def test_argument_errors_without_gpu():
         assert lib.bspai_build(ctypes.byref(a), None, 1e-3, arr, len(precs), None, ctypes.byref(out), None) == B.EINVAL
     assert lib.bspai_apply(None, None, None, 1, 1, B.FP32, None) == B.EINVAL
     assert lib.gmres_ir_solve(None, None, None, None, None, 1, None, None) == B.EINVAL
+    assert lib.gmres_ir_solve_ab(None, None, None, None, None, None, 1, None, None) == B.EINVAL
+    assert b"null A_b" in lib.bspai_last_error()
     assert lib.bspai_stats(None, None) == B.EINVAL

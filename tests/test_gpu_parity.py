@@ -494,6 +494,152 @@ def test_solve_batched_adjoint(B):
     h.free()
 
 
+# ------------------------------------------------- bucketed A inside GMRES
+
+def _ab_cases():
+    out = []
+    c = W.config("2", small=True)
+    for eps in c["eps"]:  # fp32 / fp32+fp16 / bf16 buckets of the stencil
+        out.append((f"2s_eps{eps}", c, eps))
+    c5 = W.config("5", small=True)
+    out.append(("5s", c5, c5["eps"][0]))  # fp16, bf16 and fp8 buckets
+    return out
+
+
+@pytest.mark.parametrize("case", _ab_cases(), ids=lambda c: c[0])
+def test_solve_bucketed_a_matches_oracle(B, case):
+    """A bucketed with the same eps and precisions as M (eqs. (nbe2), (fe2)):
+    the device bucketing of A is bit-exact, and the solve agrees with the
+    oracle's bucketed-A refinement as the plain solve does with its oracle."""
+    import torch
+
+    name, c, eps = case
+    A, P, b = c["A"], c["P"], c["b"]
+    _say("solve bucketed A", name)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=40)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"])
+    hA = B.bucket_a(Ad, eps, c["precs"], keep_fp64=True)
+    Ab = O.Bucketed(A, eps, c["precs"])
+    ex = hA.export()
+    assert np.array_equal(ex["bucket"], Ab.bucket) and np.array_equal(ex["stored"], Ab.mt)
+    assert hA.stats()["count"] == list(Ab.counts)
+    x, st = B.solve(Ad, _dev(b), h, A_b=hA, **kw)
+    torch.cuda.synchronize()
+    xg = x.cpu().numpy()
+    M = _spai_oracle(A, P)
+    ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, dot64=True, Ab=Ab, **kw)
+    _check_column(st, ref, O.backward_error(A, b, xg))
+    hA.free()
+    h.free()
+
+
+def test_solve_bucketed_a_one_fp32_bucket_is_the_plain_solve(B):
+    """One fp32 bucket holds A rounded to fp32, stored as the plain path
+    stores A_p: same products, so the same bits."""
+    import torch
+
+    c = W.config("2", small=True)
+    A, P, b = c["A"], c["P"], c["b"]
+    _say("solve bucketed A one fp32 bucket")
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=c["eps"][1], precs=c["precs"])
+    hA = B.bucket_a(Ad, 1e-4, ["fp32"])
+    x0, st0 = B.solve(Ad, _dev(b), h, **kw)
+    x1, st1 = B.solve(Ad, _dev(b), h, A_b=hA, **kw)
+    torch.cuda.synchronize()
+    assert st0 == st1
+    assert torch.equal(x0, x1)
+    hA.free()
+    h.free()
+
+
+def test_solve_bucketed_a_batched_and_adjoint(B):
+    """Three right-hand sides in one call and the transposed (adjoint) solve,
+    both with A_b: columns against the oracle, the adjoint against a dense
+    solve and the oracle's A_b^T refinement."""
+    import torch
+
+    c = W.config("5", small=True)
+    A, P = c["A"], c["P"]
+    eps = c["eps"][0]
+    _say("solve bucketed A batched + adjoint")
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=40)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"])
+    hA = B.bucket_a(Ad, eps, c["precs"], build_T=True)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, eps, c["precs"])
+    Ab = O.Bucketed(A, eps, c["precs"])
+    rng = np.random.default_rng(21)
+    Bm = rng.standard_normal((A.n, 3))
+    xg, sts = B.solve(Ad, _dev(Bm), h, A_b=hA, **kw)
+    xg = xg.cpu().numpy()
+    for col in range(3):
+        ref = O.gmres_ir(A, M, Mb, Bm[:, col].copy(), dot64=True, Ab=Ab, **kw)
+        _check_column(sts[col], ref, O.backward_error(A, Bm[:, col], xg[:, col]))
+    g = rng.standard_normal(A.n)
+    kwt = dict(kw, tol_rr=1e-13)
+    lam, st = B.solve(Ad, _dev(g), h, A_b=hA, trans=True, **kwt)
+    torch.cuda.synchronize()
+    lam = lam.cpu().numpy()
+    assert st["status"] == 0
+    dense = np.linalg.solve(A.dense().T, g)
+    assert np.abs(lam - dense).max() <= 1e-9 * np.abs(dense).max()
+    ref = O.gmres_ir(A, M, Mb, g, trans=True, dot64=True, Ab=Ab, **kwt)
+    assert abs(st["steps"] - ref["steps"]) <= 1
+    assert abs(st["its_total"] - ref["its_total"]) <= max(3, 0.15 * ref["its_total"]), (st["its"], ref["its"])
+    hA.free()
+    h.free()
+
+
+def test_solve_bucketed_a_argument_errors(B):
+    c = W.config("2", small=True)
+    A, P = c["A"], c["P"]
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=1e-4, precs=c["precs"])
+    hA = B.bucket_a(Ad, 1e-4, c["precs"])  # no transpose
+    with pytest.raises(B.BSPAIError, match="build_T"):
+        B.solve(Ad, _dev(c["b"]), h, A_b=hA, trans=True)
+    small = W.config("5", small=True)["A"]
+    hS = B.bucket_a(B.CSRMatrix.from_host(small), 1e-4, c["precs"])
+    with pytest.raises(B.BSPAIError, match="A_b is"):
+        B.solve(Ad, _dev(c["b"]), h, A_b=hS)
+    hS.free()
+    hA.free()
+    h.free()
+
+
+def test_solve_bucketed_a_full_size(B):
+    """The 256^2 convection-diffusion system with A in fp32 + fp16 buckets:
+    the solve reaches the plain solve's backward error, and A_b's stored
+    values on sampled rows are the oracle's."""
+    import torch
+
+    c = W.config("2")
+    A, P, b = c["A"], c["P"], c["b"]
+    eps = c["eps"][1]
+    _say("solve bucketed A full size", A.n)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"])
+    hA = B.bucket_a(Ad, eps, c["precs"], keep_fp64=True)
+    Ab = O.Bucketed(A, eps, c["precs"])
+    ex = hA.export()
+    assert np.array_equal(ex["bucket"], Ab.bucket) and np.array_equal(ex["stored"], Ab.mt)
+    x0, st0 = B.solve(Ad, _dev(b), h, **kw)
+    x1, st1 = B.solve(Ad, _dev(b), h, A_b=hA, **kw)
+    torch.cuda.synchronize()
+    assert st0["stop_reason"] == st1["stop_reason"] == 1
+    e0 = O.backward_error(A, b, x0.cpu().numpy())
+    e1 = O.backward_error(A, b, x1.cpu().numpy())
+    assert e1 <= 10 * e0 + 1e-17
+    assert st1["steps"] <= st0["steps"] + 2
+    hA.free()
+    h.free()
+
+
 def _multi_systems(B, c, eps):
     out = []
     for sy in c["systems"]:
