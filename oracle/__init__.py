@@ -11,7 +11,10 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
 * ``round_to`` / ``encode`` / ``decode``  pinned: exhaustive code round trips,
   NumPy float16/float32 and torch bfloat16/float8_e4m3fn casts, hand-made ties.
 * ``householder_ls`` / ``spai``  pinned: NumPy ``lstsq``, full pattern gives the
-  dense inverse, diagonal and block-diagonal closed forms, LS optimality.
+  dense inverse, diagonal and block-diagonal closed forms, LS optimality.  In
+  a lower u_f: Householder's backward-stability and forward-error bounds,
+  rounding placement against IEEE float16/float32 scalars, fp16 overflow
+  without Section 4's scaling.
 * ``bucketize``  pinned: hand-computed bucket ids at the interval ends of
   eq. (nint), invariants (counts, monotonicity in eps, limits).
 * ``storage_pct``  pinned: the "str." column of Tables 3 and 4.
@@ -86,6 +89,9 @@ def lib():
     L.orc_storage_pct.argtypes = [_i64p, _i32p, C.c_int, C.c_double, C.c_int]
     L.orc_storage_pct.restype = C.c_double
     L.orc_householder_ls.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p]
+    L.orc_householder_ls_prec.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p, C.c_int]
+    L.orc_spai_prec.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, C.c_void_p, C.c_int, C.c_int,
+                                C.c_int, C.POINTER(C.c_int)]
     L.orc_spai.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p, C.c_void_p, C.c_int, C.c_int,
                            C.POINTER(C.c_int)]
     L.orc_spai_adaptive.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, C.c_void_p, C.c_void_p, C.c_int,
@@ -154,19 +160,24 @@ def storage_pct(counts: Sequence[int], precs: Sequence[int], drop_bytes: float =
 
 # ---------------------------------------------------------------- SPAI
 
-def householder_ls(A: np.ndarray, b: np.ndarray):
-    """(status, x) for min ||b - A x||_2 (dense, m >= n)."""
+def householder_ls(A: np.ndarray, b: np.ndarray, prec: int = FP64):
+    """(status, x) for min ||b - A x||_2 (dense, m >= n); prec: every
+    operation rounded to that precision (A and b must hold its numbers)."""
     A = np.asfortranarray(A, dtype=np.float64)
     m, n = A.shape
     a = _f64(A.reshape(-1, order="F"))
     bb = _f64(b).copy()
     x = np.zeros(n)
-    st = lib().orc_householder_ls(m, n, a, bb, x)
+    if prec == FP64:
+        st = lib().orc_householder_ls(m, n, a, bb, x)
+    else:
+        st = lib().orc_householder_ls_prec(m, n, a, bb, x, int(prec))
     return st, x
 
 
-def spai(A, P, rows: Optional[np.ndarray] = None, scale: bool = False):
-    """(status, M values on P's CSR, bad_row).  A, P: workloads.CSR."""
+def spai(A, P, rows: Optional[np.ndarray] = None, scale: bool = False, uf: int = FP64):
+    """(status, M values on P's CSR, bad_row).  A, P: workloads.CSR.  uf: the
+    construction precision u_f (FP64, FP32 or FP16)."""
     Mv = np.zeros(P.nnz, dtype=np.float64)
     bad = C.c_int(-1)
     if rows is not None:
@@ -174,8 +185,8 @@ def spai(A, P, rows: Optional[np.ndarray] = None, scale: bool = False):
         rptr, nr = rr.ctypes.data_as(C.c_void_p), rr.size
     else:
         rr, rptr, nr = None, None, 0
-    st = lib().orc_spai(A.n, _i32(A.row_ptr), _i32(A.col), _f64(A.val), _i32(P.row_ptr), _i32(P.col), Mv,
-                        rptr, nr, int(scale), C.byref(bad))
+    st = lib().orc_spai_prec(A.n, _i32(A.row_ptr), _i32(A.col), _f64(A.val), _i32(P.row_ptr), _i32(P.col), Mv,
+                             rptr, nr, int(scale), int(uf), C.byref(bad))
     return st, Mv, bad.value
 
 

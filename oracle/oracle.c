@@ -194,55 +194,69 @@ double orc_storage_pct(const int64_t *counts, const int *precs, int q, double dr
  * construction (Section 2.2, eq. (redprob)).
  * Returns ORC_ERANK when some |r_cc| <= n u ||A||_F.
  * ---------------------------------------------------------------------- */
-int orc_householder_ls(int m, int n, double *A, double *b, double *x) {
+/* Householder least squares with every elementary operation (+, -, *, /,
+ * sqrt) rounded to precision `prec` (FP64: plain double arithmetic), sums
+ * taken left to right: the QR factorisation "in u_f" of Section 2.2.  Every
+ * operation on two u_f numbers done in FP64 and then rounded is correctly
+ * rounded in u_f for fp32 and fp16 (53 >= 2p + 2 bits).  A rank-deficiency
+ * test uses n u_f ||A||_F; a non-finite result (overflow in u_f) is ENAN. */
+int orc_householder_ls_prec(int m, int n, double *A, double *b, double *x, int prec) {
+#define R_(v) orc_round(prec, (v))
     if (m < n || n <= 0) return ORC_ERANK;
     double fro = 0;
     for (int j = 0; j < n; j++)
-        for (int i = 0; i < m; i++) fro += A[i + (size_t)j * m] * A[i + (size_t)j * m];
-    fro = sqrt(fro);
+        for (int i = 0; i < m; i++) fro = R_(fro + R_(A[i + (size_t)j * m] * A[i + (size_t)j * m]));
+    fro = R_(sqrt(fro));
+    if (!isfinite(fro)) return ORC_ENAN;  /* an entry or ||A||_F overflows u_f */
     double *v = (double *)malloc(sizeof(double) * (size_t)m);
     if (!v) return ORC_ENOMEM;
     int status = ORC_OK;
     for (int c = 0; c < n; c++) {
         double *col = A + (size_t)c * m;
         double nrm2 = 0;
-        for (int i = c; i < m; i++) nrm2 += col[i] * col[i];
-        double nrm = sqrt(nrm2);
+        for (int i = c; i < m; i++) nrm2 = R_(nrm2 + R_(col[i] * col[i]));
+        double nrm = R_(sqrt(nrm2));
         if (nrm == 0.0) { status = ORC_ERANK; break; }
         double alpha = col[c];
         double beta = -copysign(nrm, alpha);
         int len = m - c;
         for (int i = 0; i < len; i++) v[i] = col[c + i];
-        v[0] = alpha - beta;
+        v[0] = R_(alpha - beta);
         double vtv = 0;
-        for (int i = 0; i < len; i++) vtv += v[i] * v[i];
+        for (int i = 0; i < len; i++) vtv = R_(vtv + R_(v[i] * v[i]));
         /* apply H = I - 2 v v^T / (v^T v) to the trailing columns and to b */
         for (int j = c + 1; j < n; j++) {
             double *cj = A + (size_t)j * m + c;
             double w = 0;
-            for (int i = 0; i < len; i++) w += v[i] * cj[i];
-            double f = 2.0 * w / vtv;
-            for (int i = 0; i < len; i++) cj[i] -= f * v[i];
+            for (int i = 0; i < len; i++) w = R_(w + R_(v[i] * cj[i]));
+            double f = R_(2.0 * w / vtv);
+            for (int i = 0; i < len; i++) cj[i] = R_(cj[i] - R_(f * v[i]));
         }
         {
             double w = 0;
-            for (int i = 0; i < len; i++) w += v[i] * b[c + i];
-            double f = 2.0 * w / vtv;
-            for (int i = 0; i < len; i++) b[c + i] -= f * v[i];
+            for (int i = 0; i < len; i++) w = R_(w + R_(v[i] * b[c + i]));
+            double f = R_(2.0 * w / vtv);
+            for (int i = 0; i < len; i++) b[c + i] = R_(b[c + i] - R_(f * v[i]));
         }
         col[c] = beta;
         for (int i = c + 1; i < m; i++) col[i] = 0.0;
-        if (fabs(beta) <= (double)n * ldexp(1.0, -53) * fro) { status = ORC_ERANK; break; }
+        if (fabs(beta) <= (double)n * orc_unit_roundoff(prec) * fro) { status = ORC_ERANK; break; }
     }
     if (status == ORC_OK) {
         for (int c = n - 1; c >= 0; c--) {
             double s = b[c];
-            for (int j = c + 1; j < n; j++) s -= A[c + (size_t)j * m] * x[j];
-            x[c] = s / A[c + (size_t)c * m];
+            for (int j = c + 1; j < n; j++) s = R_(s - R_(A[c + (size_t)j * m] * x[j]));
+            x[c] = R_(s / A[c + (size_t)c * m]);
+            if (!isfinite(x[c])) { status = ORC_ENAN; break; }
         }
     }
     free(v);
     return status;
+#undef R_
+}
+
+int orc_householder_ls(int m, int n, double *A, double *b, double *x) {
+    return orc_householder_ls_prec(m, n, A, b, x, OP_FP64);
 }
 
 static int cmp_int(const void *a, const void *b) {
@@ -272,13 +286,19 @@ static int find_sorted(const int *a, int len, int key) {
  * d_j = 1 / max_l |a_{jl}| and M(k, j) = mbar_j d_j (the one-sided scaling
  * of Section 4).
  *
+ * uf is the construction precision u_f (Section 4's settings use double,
+ * single and half): each entry of Abar is a_{J_c, I_l} d_j computed in FP64
+ * and rounded once to u_f, the least squares runs with every operation in
+ * u_f (orc_householder_ls_prec), and M(k, j) is mbar_j d_j computed in FP64
+ * and rounded once to u_f.  orc_spai is uf = FP64.
+ *
  * rows/nrows select a subset of rows (NULL: all).  On failure bad_row gets
  * the first failing row and the status is ORC_EZEROROW (k not in I: the
- * zero-row case of Section 4) or ORC_ERANK.
+ * zero-row case of Section 4), ORC_ERANK or ORC_ENAN (overflow in u_f).
  * ---------------------------------------------------------------------- */
-int orc_spai(int n, const int *Arp, const int *Aci, const double *Av,
-             const int *Prp, const int *Pci, double *Mv,
-             const int *rows, int nrows, int scale, int *bad_row) {
+int orc_spai_prec(int n, const int *Arp, const int *Aci, const double *Av,
+                  const int *Prp, const int *Pci, double *Mv,
+                  const int *rows, int nrows, int scale, int uf, int *bad_row) {
     int status = ORC_OK;
     int first_bad = n;
     int count = rows ? nrows : n;
@@ -323,13 +343,13 @@ int orc_spai(int n, const int *Arp, const int *Aci, const double *Av,
                 for (int e = Arp[J[c]]; e < Arp[J[c] + 1]; e++) {
                     if (Av[e] == 0.0) continue;
                     int l = find_sorted(I, nI, Aci[e]);
-                    Ab[l + (size_t)c * nI] = Av[e] * dj;
+                    Ab[l + (size_t)c * nI] = orc_round(uf, Av[e] * dj);
                 }
             }
             eb[find_sorted(I, nI, k)] = 1.0;
-            st = orc_householder_ls(nI, nJ, Ab, eb, m);
+            st = orc_householder_ls_prec(nI, nJ, Ab, eb, m, uf);
             if (st == ORC_OK)
-                for (int c = 0; c < nJ; c++) Mv[Prp[k] + c] = m[c] * (scale ? dscale[J[c]] : 1.0);
+                for (int c = 0; c < nJ; c++) Mv[Prp[k] + c] = orc_round(uf, m[c] * (scale ? dscale[J[c]] : 1.0));
             free(Ab); free(eb); free(m);
         }
         free(I);
@@ -343,6 +363,12 @@ int orc_spai(int n, const int *Arp, const int *Aci, const double *Av,
     free(dscale);
     if (bad_row) *bad_row = (status == ORC_OK) ? -1 : first_bad;
     return status;
+}
+
+int orc_spai(int n, const int *Arp, const int *Aci, const double *Av,
+             const int *Prp, const int *Pci, double *Mv,
+             const int *rows, int nrows, int scale, int *bad_row) {
+    return orc_spai_prec(n, Arp, Aci, Av, Prp, Pci, Mv, rows, nrows, scale, OP_FP64, bad_row);
 }
 
 /* ------------------------------------------------------------------------
