@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--only-gradient", action="store_true", help="run only the 512^2 gradient measurement")
     ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive-SPAI measurement")
     ap.add_argument("--only-bucketed-a", action="store_true", help="run only the bucketed-A measurement")
+    ap.add_argument("--only-low-uf", action="store_true", help="run only the low-u_f SPAI measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy first (calibration of hardware byte counters)")
     args = ap.parse_args()
@@ -145,6 +146,9 @@ def main():
         return
     if args.only_bucketed_a:
         print(json.dumps({"bucketed_a": bucketed_a_bench(B, W, torch, np, kw0)}), flush=True)
+        return
+    if args.only_low_uf:
+        print(json.dumps({"low_uf_spai": low_uf_bench(B, W, torch, np, kw0)}), flush=True)
         return
     _log("generating workload")
     c = W.config("2")
@@ -273,6 +277,7 @@ def main():
         out["gradient"] = gradient_bench(B, W, torch, np)
         out["adaptive_spai"] = adaptive_bench(B, W, torch, np, kw)
         out["bucketed_a"] = bucketed_a_bench(B, W, torch, np, kw)
+        out["low_uf_spai"] = low_uf_bench(B, W, torch, np, kw)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.eps, kw)
@@ -530,6 +535,45 @@ def bucketed_a_bench(B, W, torch, np, kw, reps=5):
              f"{1.0 / el:.2f} solves/s")
         hA.free()
     h.free()
+    return res
+
+
+def low_uf_bench(B, W, torch, np, kw, reps=5):
+    """The SPAI least squares in u_f = fp64, fp32 and fp16 (Section 4's
+    settings, with its column scaling) on the 256^2 convection-diffusion
+    system, pattern(A^2), bucketed at eps_b = 1e-4: build time (median of 5),
+    the bucket counts, iterations and solve rate of the resulting M."""
+    c = W.config("2")
+    A, P = c["A"], c["P"]
+    Ad = B.CSRMatrix.from_host(A)
+    Pd = B.CSRMatrix.from_host(P)
+    b = torch.as_tensor(c["b"], device="cuda")
+    res = {"workload": "convdiff2d 256x256 (n=65536), SPAI pattern(A^2) with column scaling, buckets "
+                       "fp64/fp32/fp16/bf16 eps_b=1e-4"}
+    for uf in ("fp64", "fp32", "fp16"):
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = B.build(Ad, Pd, eps=1e-4, precs=c["precs"], scale=True, u_f=uf)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            st = h.stats()
+            if len(times) < 5:
+                h.free()
+        B.solve(Ad, b, h, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, ss = B.solve(Ad, b, h, **kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        res[uf] = {"build_ms": 1e3 * float(np.median(times)), "bucket_counts": st["count"],
+                   "storage_pct": st["storage_pct"], "its": ss["its"], "relres": ss["relres"][-1],
+                   "eta": ss["eta"][-1], "solves_per_s": 1.0 / el}
+        h.free()
+        _log(f"u_f {uf}: build {res[uf]['build_ms']:.2f} ms, counts {st['count']}, its {ss['its']}, "
+             f"{1.0 / el:.2f} solves/s")
     return res
 
 

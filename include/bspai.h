@@ -74,6 +74,9 @@ typedef struct {
     int build_T;     /* also pack (M_b)^T, needed by bspai_apply_T and the transposed solve */
     int keep_fp64_M; /* keep the unbucketed FP64 M on the device (x_0 = M b, Algorithm 4 step 2) */
     int scale;       /* one-sided column scaling of A^T before the least squares (Section 4) */
+    bspai_prec u_f;  /* precision of the SPAI least squares (Section 4's settings): BSPAI_FP64 (0,
+                      * the default), BSPAI_FP32 or BSPAI_FP16; see bspai_build.  Ignored by
+                      * bspai_import; bspai_build_adaptive takes FP64 only */
 } bspai_opts;
 
 typedef struct bspai_handle bspai_handle;
@@ -89,9 +92,16 @@ typedef struct bspai_handle bspai_handle;
  *   A, P: device CSR (P NULL means the pattern of A).  precs[0..q-1]: host
  *   array, strictly increasing unit roundoff (fp64 < fp32 < fp16 < bf16 <
  *   fp8 < drop), DROP only last, 1 <= q <= 6.  opts may be NULL (defaults:
- *   build_T = 1, keep_fp64_M = 1, scale = 0).  On success *out owns device
- *   memory until bspai_free.  Synchronises `stream`.
- *   Errors: EINVAL, ENOMEM, EHIP, EZEROROW, ERANK (no handle is returned).
+ *   build_T = 1, keep_fp64_M = 1, scale = 0, u_f = FP64).  On success *out
+ *   owns device memory until bspai_free.  Synchronises `stream`.
+ *   u_f = FP32 or FP16 (Section 4's single and half settings): each entry of
+ *   the reduced matrix (scaled if `scale`) is rounded to u_f, the Householder
+ *   QR and back substitution run in u_f arithmetic, and M's entries are
+ *   rounded to u_f (kept as FP64 numbers for x_0 and the bucketing).  Only
+ *   rows whose least squares fit one wavefront are supported there (|J| <= 64,
+ *   at most 1,024 shadow candidates, a tile of at most 8,192 values): EINVAL
+ *   otherwise.  An overflow of u_f (use `scale`) is ENAN.
+ *   Errors: EINVAL, ENOMEM, EHIP, EZEROROW, ERANK, ENAN (no handle is returned).
  */
 int bspai_build(const bspai_csr *A, const bspai_pattern *P, double eps_b, const bspai_prec *precs, int q,
                 const bspai_opts *opts, bspai_handle **out, void *stream);

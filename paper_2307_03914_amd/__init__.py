@@ -50,7 +50,7 @@ class _Pattern(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("build_T", C.c_int), ("keep_fp64_M", C.c_int), ("scale", C.c_int)]
+    _fields_ = [("build_T", C.c_int), ("keep_fp64_M", C.c_int), ("scale", C.c_int), ("u_f", C.c_int)]
 
 
 class _Tol(C.Structure):
@@ -270,18 +270,24 @@ class Handle:
         return dict(bucket=bk, stored=st, m64=m64)
 
 
-def _opts(build_T, keep_fp64_M, scale):
-    return _Opts(int(build_T), int(keep_fp64_M), int(scale))
+def _opts(build_T, keep_fp64_M, scale, u_f="fp64"):
+    if u_f not in ("fp64", "fp32", "fp16"):
+        raise ValueError("u_f must be 'fp64', 'fp32' or 'fp16'")
+    return _Opts(int(build_T), int(keep_fp64_M), int(scale), PREC[u_f])
 
 
 def build(A: CSRMatrix, P: Optional[CSRMatrix] = None, eps: float = 1e-4, precs: Sequence = ("fp64",),
-          build_T: bool = True, keep_fp64_M: bool = True, scale: bool = False, stream=None) -> Handle:
+          build_T: bool = True, keep_fp64_M: bool = True, scale: bool = False, u_f: str = "fp64",
+          stream=None) -> Handle:
+    """SPAI of A on the pattern P (None: A's), bucketed (bspai_build).  u_f:
+    precision of the least squares ("fp64", "fp32" or "fp16"; use scale=True
+    below fp64)."""
     out = _vp()
     pids, q = _prec_ids(precs)
     a = A._c()
     p = P._p() if P is not None else None
     _check(_lib.bspai_build(C.byref(a), C.byref(p) if p is not None else None, float(eps), pids, q,
-                            C.byref(_opts(build_T, keep_fp64_M, scale)), C.byref(out), _stream(stream)))
+                            C.byref(_opts(build_T, keep_fp64_M, scale, u_f)), C.byref(out), _stream(stream)))
     return Handle(out.value, A.n, P.nnz if P is not None else A.nnz)
 
 

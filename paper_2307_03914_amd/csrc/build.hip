@@ -19,6 +19,29 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// sums and square roots in the construction precision T: shuffled values are
+// widened exactly to float (fp16) and every addition is rounded to T
+template <typename T>
+__device__ __forceinline__ T wave_sum_t(T v) {
+  if constexpr (sizeof(T) == 8) {
+    return wave_sum_d(v);
+  } else {
+    for (int o = 32; o > 0; o >>= 1) v = (T)(v + (T)__shfl_xor((float)v, o));
+    return v;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T sqrt_t(T v) {
+  if constexpr (sizeof(T) == 8) return sqrt(v);
+  else return (T)sqrtf((float)v);  // correctly rounded in float, then in fp16
+}
+
+template <typename T>
+constexpr double unit_roundoff_t() {
+  return sizeof(T) == 8 ? 0x1p-53 : sizeof(T) == 4 ? 0x1p-24 : 0x1p-11;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -80,7 +103,8 @@ struct SpaiArgs {
   double *mval;
   int cand_p2;  // capacity of the index lists (power of two)
   int tile_cap; // capacity of the dense tile in doubles
-  int32_t *err; // [0] first zero row, [1] first rank-deficient row, [2] first oversized row
+  int32_t *err; // [0] first zero row, [1] first rank-deficient row, [2] first oversized row,
+                // [3] first row whose least squares overflows the construction precision
   const int8_t *is_big;  // rows left to the block path
 };
 
@@ -88,6 +112,12 @@ struct SpaiArgs {
 //   J = P(k,:); I = sorted union of the nonzero columns of the rows J of A
 //   (the shadow of J in A^T); Abar(l, c) = a_{J_c, I_l}; ebar = e_k(I);
 //   Householder QR of Abar, mbar = R^{-1} (Q^T ebar)(1:|J|); M(k, J) = mbar.
+// T is the construction precision u_f (Section 4: double, single or half):
+// the tile holds a_{J_c, I_l} d_j rounded to T, every operation of the QR
+// and the back substitution is done in T (the compiler may fuse a multiply
+// and an add into one rounding; sums run as wavefront trees), and M(k, j) is
+// mbar_j d_j rounded to T, stored in FP64.
+template <typename T>
 __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
   extern __shared__ double lds_d[];
   const int k = blockIdx.x;
@@ -96,9 +126,9 @@ __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
   const int ps = a.prp[k], nJ = a.prp[k + 1] - ps;
   int32_t *cand = reinterpret_cast<int32_t *>(lds_d);  // cand_p2
   int32_t *I = cand + a.cand_p2;                        // cand_p2
-  double *Ab = lds_d + a.cand_p2;                       // tile_cap (after the two int lists)
-  double *eb = Ab + a.tile_cap;                         // cand_p2
-  double *mv = eb + a.cand_p2;                          // 64 + nJ
+  T *Ab = reinterpret_cast<T *>(lds_d + a.cand_p2);    // tile_cap (after the two int lists)
+  T *eb = Ab + a.tile_cap;                              // cand_p2
+  T *mv = eb + a.cand_p2;                               // 64 + nJ
 
   // gather candidate columns (nonzero values only), compacted with ballots
   int nc = 0;
@@ -164,45 +194,49 @@ __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
     return;
   }
   // dense tile, column-major with leading dimension nI
-  for (int p = lane; p < nI * nJ; p += 64) Ab[p] = 0.0;
-  for (int p = lane; p < nI; p += 64) eb[p] = (p == lk) ? 1.0 : 0.0;
+  for (int p = lane; p < nI * nJ; p += 64) Ab[p] = (T)0;
+  for (int p = lane; p < nI; p += 64) eb[p] = (p == lk) ? (T)1 : (T)0;
   wave_sync();
   for (int c = 0; c < nJ; c++) {
     int j = a.pcol[ps + c];
     double dj = a.dscale ? a.dscale[j] : 1.0;
     for (int p = a.arp[j] + lane; p < a.arp[j + 1]; p += 64) {
       double v = a.aval[p];
-      if (v != 0.0) Ab[lower_bound_i(I, nI, a.acol[p]) + c * nI] = v * dj;
+      if (v != 0.0) Ab[lower_bound_i(I, nI, a.acol[p]) + c * nI] = (T)(v * dj);
     }
   }
   wave_sync();
-  double fro2 = 0;
+  T fro2 = 0;
   for (int p = lane; p < nI * nJ; p += 64) fro2 += Ab[p] * Ab[p];
-  double fro = sqrt(wave_sum_d(fro2));
-  double *diagR = mv + 64;
+  const double fro = (double)sqrt_t(wave_sum_t(fro2));
+  if (!isfinite(fro)) {  // an entry or ||Abar||_F overflows T
+    if (lane == 0) atomicMin(&a.err[3], k);
+    return;
+  }
+  T *diagR = mv + 64;
   // Householder QR: reflector v = a + sign(a_1) ||a|| e_1 kept in column c
   for (int c = 0; c < nJ; c++) {
-    double *col = Ab + c * nI;
-    double s2 = 0;
+    T *col = Ab + c * nI;
+    T s2 = 0;
     for (int l = c + lane; l < nI; l += 64) s2 += col[l] * col[l];
-    double nrm = sqrt(wave_sum_d(s2));
-    double alpha = col[c];
-    double beta = -copysign(nrm, alpha);
-    if (nrm == 0.0 || fabs(beta) <= (double)nJ * 0x1p-53 * fro) {
+    const T nrm = sqrt_t(wave_sum_t(s2));
+    const T alpha = col[c];
+    const T beta = (T)-copysign((double)nrm, (double)alpha);
+    if (nrm == (T)0 || fabs((double)beta) <= (double)nJ * unit_roundoff_t<T>() * fro) {
       if (lane == 0) atomicMin(&a.err[1], k);
       return;
     }
     wave_sync();
-    if (lane == 0) col[c] = alpha - beta;
+    if (lane == 0) col[c] = (T)(alpha - beta);
     wave_sync();
-    double vt = 0;
+    T vt = 0;
     for (int l = c + lane; l < nI; l += 64) vt += col[l] * col[l];
-    double vtv = wave_sum_d(vt);
+    const T vtv = wave_sum_t(vt);
     for (int jj = c + 1; jj <= nJ; jj++) {  // jj == nJ is the right-hand side
-      double *cj = (jj < nJ) ? Ab + jj * nI : eb;
-      double w = 0;
+      T *cj = (jj < nJ) ? Ab + jj * nI : eb;
+      T w = 0;
       for (int l = c + lane; l < nI; l += 64) w += col[l] * cj[l];
-      double f = 2.0 * wave_sum_d(w) / vtv;
+      const T f = (T)((T)2 * wave_sum_t(w)) / vtv;
       for (int l = c + lane; l < nI; l += 64) cj[l] -= f * col[l];
       wave_sync();
     }
@@ -211,16 +245,19 @@ __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
   }
   // back substitution R m = (Q^T ebar)(1:nJ), one lane
   if (lane == 0) {
+    bool finite = true;
     for (int c = nJ - 1; c >= 0; c--) {
-      double t = eb[c];
+      T t = eb[c];
       for (int jj = c + 1; jj < nJ; jj++) t -= Ab[c + jj * nI] * mv[jj];
       mv[c] = t / diagR[c];
+      finite = finite && isfinite((double)mv[c]);
     }
+    if (!finite) atomicMin(&a.err[3], k);
   }
   wave_sync();
   for (int c = lane; c < nJ; c += 64) {
     double dj = a.dscale ? a.dscale[a.pcol[ps + c]] : 1.0;
-    a.mval[ps + c] = mv[c] * dj;
+    a.mval[ps + c] = (double)(T)((double)mv[c] * dj);
   }
 }
 
@@ -1067,6 +1104,7 @@ static bspai_opts default_opts() {
   o.build_T = 1;
   o.keep_fp64_M = 1;
   o.scale = 0;
+  o.u_f = BSPAI_FP64;
   return o;
 }
 
@@ -1117,6 +1155,8 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
   if ((rc = check_precs(precs, q))) return rc;
   if (!(eps_b >= 0) || !std::isfinite(eps_b)) return fail(BSPAI_EINVAL, "eps_b must be finite and >= 0");
   bspai_opts o = opts ? *opts : default_opts();
+  if (o.u_f != BSPAI_FP64 && o.u_f != BSPAI_FP32 && o.u_f != BSPAI_FP16)
+    return fail(BSPAI_EINVAL, "bspai_build: u_f must be FP64, FP32 or FP16");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = A->n;
   bspai_handle *h = new bspai_handle();
@@ -1137,7 +1177,7 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
     BSPAI_HIP(hipMemcpyAsync(h->m_rp, Pd.row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (Pd.nnz) BSPAI_HIP(hipMemcpyAsync(h->m_col, Pd.col, sizeof(int32_t) * Pd.nnz, hipMemcpyDeviceToDevice, s));
     if (n == 0) return BSPAI_OK;
-    if ((r = dalloc_t(&mx, 5)) || (r = dalloc_t(&err, 3)) || (r = dalloc_t(&isbig, (size_t)n)) ||
+    if ((r = dalloc_t(&mx, 5)) || (r = dalloc_t(&err, 4)) || (r = dalloc_t(&isbig, (size_t)n)) ||
         (r = dalloc_t(&biglist, (size_t)n)) || (r = dalloc_t(&candof, (size_t)n)))
       return r;
     int32_t hmx[5] = {0, 0, 0, 0, 0};
@@ -1149,6 +1189,10 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
     BSPAI_HIP(hipStreamSynchronize(s));
     int nJmax = hmx[0], candmax = hmx[1];
     nbig = hmx[4];
+    if (nbig > 0 && o.u_f != BSPAI_FP64)
+      return fail(BSPAI_EINVAL, "bspai_build: u_f below FP64 covers rows whose least squares fit one wavefront "
+                                "(|J| <= %d, <= %d shadow candidates, tile <= %d values); %d rows need more",
+                  kSmallJ, kSmallCand, kSmallTile, nbig);
     int cand_p2 = 64;
     while (cand_p2 < candmax) cand_p2 <<= 1;
     // the maxima may come from different rows; no row of this path exceeds kSmallTile
@@ -1159,7 +1203,7 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
       hipLaunchKernelGGL(k_row_maxabs_inv, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_ptr, A->val, dsc);
       BSPAI_CHECK_LAUNCH();
     }
-    int32_t herr[3] = {INT_MAX, INT_MAX, INT_MAX};
+    int32_t herr[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
     BSPAI_HIP(hipMemcpyAsync(err, herr, sizeof(herr), hipMemcpyHostToDevice, s));
     SpaiArgs sa;
     sa.n = n;
@@ -1175,9 +1219,13 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
     sa.err = err;
     sa.is_big = isbig;
     if (nbig < n) {
-      if (lds > 64 * 1024)
-        BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL(k_spai, dim3(n), dim3(64), lds, s, sa);
+      const void *fn = o.u_f == BSPAI_FP32   ? (const void *)k_spai<float>
+                       : o.u_f == BSPAI_FP16 ? (const void *)k_spai<_Float16>
+                                             : (const void *)k_spai<double>;
+      if (lds > 64 * 1024) BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      if (o.u_f == BSPAI_FP32) hipLaunchKernelGGL(k_spai<float>, dim3(n), dim3(64), lds, s, sa);
+      else if (o.u_f == BSPAI_FP16) hipLaunchKernelGGL(k_spai<_Float16>, dim3(n), dim3(64), lds, s, sa);
+      else hipLaunchKernelGGL(k_spai<double>, dim3(n), dim3(64), lds, s, sa);
       BSPAI_CHECK_LAUNCH();
     }
     if (nbig > 0) {
@@ -1258,6 +1306,8 @@ extern "C" int bspai_build(const bspai_csr *A, const bspai_pattern *P, double ep
       if (herr[0] < herr[1]) return fail(BSPAI_EZEROROW, "row %d of M is zero: %d is not in its shadow", herr[0], herr[0]);
       return fail(BSPAI_ERANK, "row %d: reduced least-squares problem is rank deficient", herr[1]);
     }
+    if (herr[3] != INT_MAX)
+      return fail(BSPAI_ENAN, "row %d: the least squares overflows u_f (the column scaling avoids this)", herr[3]);
     return BSPAI_OK;
   };
   rc = body();
@@ -1343,6 +1393,7 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
     return fail(BSPAI_EINVAL, "bspai_build_adaptive: need alpha >= 0, beta >= 0 and a finite eps >= 0");
   if ((rc = check_precs(precs, q))) return rc;
   if (!(eps_b >= 0) || !std::isfinite(eps_b)) return fail(BSPAI_EINVAL, "eps_b must be finite and >= 0");
+  if (opts && opts->u_f != BSPAI_FP64) return fail(BSPAI_EINVAL, "bspai_build_adaptive: u_f must be FP64");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = A->n;
   const int64_t nnz = A->nnz;

@@ -174,6 +174,109 @@ def test_build_scaling_matches_unscaled(B):
     assert np.allclose(m, M.val, rtol=1e-8, atol=1e-11 * np.abs(M.val).max())
 
 
+# ------------------------------------------- SPAI built in a lower u_f
+
+UF = {"fp32": (O.FP32, 2.0 ** -24), "fp16": (O.FP16, 2.0 ** -11)}
+
+
+def _low_uf_cases():
+    out = [c for c in _workloads_small() if c[0] in ("cfg2s_eps0.0001", "cfg5s", "cfg4as")]
+    # a random matrix on its own pattern (its A^2 rows need the block path,
+    # which is FP64 only)
+    A = W.random_sparse(333, 0.02, np.random.default_rng(7), dominance=0.8)
+    out.append(("rand333_A", A, A.pattern(), [O.FP64, O.FP32, O.FP16, O.BF16, O.FP8], 1e-3))
+    return out
+
+
+def _check_low_uf_rows(m_gpu, A, P, uf, rows=None):
+    """Both sides solve each row's least squares backward stably in u_f, in
+    different summation orders: per row the GPU's values differ from the
+    oracle's by at most 4x the oracle's own distance from the FP64 row plus
+    64 u_f times the row's size; every value is a u_f number."""
+    prec, u = UF[uf]
+    assert np.array_equal(O.round_to(prec, m_gpu), m_gpu)
+    st, Mo, bad = O.spai(A, P, rows=rows, scale=True, uf=prec)
+    assert st == O.OK, (st, bad)
+    st, M64, bad = O.spai(A, P, rows=rows, scale=True)
+    assert st == O.OK, (st, bad)
+    for i in (range(A.n) if rows is None else rows):
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        size = np.abs(M64[s]).max()
+        tol = 4 * np.abs(Mo[s] - M64[s]).max() + 64 * u * size
+        assert np.abs(m_gpu[s] - Mo[s]).max() <= tol, (i, uf)
+    return Mo
+
+
+@pytest.mark.parametrize("uf", ["fp32", "fp16"])
+@pytest.mark.parametrize("case", _low_uf_cases(), ids=lambda c: c[0])
+def test_build_low_uf_matches_oracle(B, case, uf):
+    name, A, P, precs, eps = case
+    _say("build u_f", uf, name)
+    h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), eps=eps, precs=precs, scale=True, u_f=uf)
+    ex = h.export()
+    _check_low_uf_rows(ex["m64"], A, P, uf)
+    # the bucketing of the GPU's M is the oracle's bucketing of that M
+    ref = O.Bucketed(W.CSR(A.n, P.row_ptr, P.col, ex["m64"]), eps, precs)
+    assert np.array_equal(ex["bucket"], ref.bucket) and np.array_equal(ex["stored"], ref.mt)
+    h.free()
+
+
+def test_solve_with_low_uf_spai(B):
+    """(half, single, double): M built in fp16, GMRES in fp32; the solve
+    agrees with the oracle's refinement on the same M."""
+    import torch
+
+    c = W.config("2", small=True)
+    A, P, b = c["A"], c["P"], c["b"]
+    eps = c["eps"][1]
+    _say("solve with fp16-built M")
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=30)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"], scale=True, u_f="fp16")
+    x, st = B.solve(Ad, _dev(b), h, **kw)
+    torch.cuda.synchronize()
+    M = W.CSR(A.n, P.row_ptr, P.col, h.export()["m64"])
+    ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, dot64=True, **kw)
+    _check_column(st, ref, O.backward_error(A, b, x.cpu().numpy()))
+    h.free()
+
+
+def test_build_low_uf_overflow_and_limits(B):
+    rng = np.random.default_rng(86)
+    n = 300
+    A = W.random_sparse(n, 0.02, rng, dominance=0.8)
+    big = np.repeat(np.where(np.arange(n) % 3 == 0, 1e5, 1.0), np.diff(A.row_ptr))
+    A = W.CSR(n, A.row_ptr, A.col, A.val * big)
+    _say("build u_f overflow")
+    Ad = B.CSRMatrix.from_host(A)
+    with pytest.raises(B.BSPAIError) as e:
+        B.build(Ad, None, precs=["fp32", "fp16"], u_f="fp16")
+    assert e.value.code == B.ENAN
+    h = B.build(Ad, None, precs=["fp32", "fp16"], scale=True, u_f="fp16")
+    _check_low_uf_rows(h.export()["m64"], A, A.pattern(), "fp16")
+    h.free()
+    # rows too large for one wavefront stay FP64-only
+    D = np.ones((80, 80)) + 80 * np.eye(80)
+    Af = W.from_dense(D)
+    with pytest.raises(B.BSPAIError) as e:
+        B.build(B.CSRMatrix.from_host(Af), None, precs=["fp32"], scale=True, u_f="fp32")
+    assert e.value.code == B.EINVAL and "wavefront" in str(e.value)
+    with pytest.raises(ValueError):
+        B.build(Ad, None, u_f="bf16")
+
+
+def test_build_low_uf_full_size_sampled_rows(B):
+    c = W.config("2")
+    A, P = c["A"], c["P"]
+    _say("build u_f full size", A.n)
+    rows = np.sort(np.random.default_rng(5).choice(A.n, 1500, replace=False)).astype(np.int32)
+    for uf in ("fp32", "fp16"):
+        h = B.build(B.CSRMatrix.from_host(A), B.CSRMatrix.from_host(P), eps=1e-4, precs=c["precs"], scale=True,
+                    u_f=uf)
+        _check_low_uf_rows(h.export()["m64"], A, P, uf, rows=rows)
+        h.free()
+
+
 # ---------------------------------------------------------------- apply
 
 def _apply_bound(Mb, x, acc_u, transpose=False):
