@@ -53,7 +53,7 @@ _i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
 class GmresOpts(C.Structure):
     _fields_ = [("ug", C.c_int), ("up", C.c_int), ("tau", C.c_double), ("max_it", C.c_int), ("trans", C.c_int),
                 ("dot64", C.c_int), ("arp_b", C.c_void_p), ("aci_b", C.c_void_p), ("at_b", C.c_void_p),
-                ("ab_b", C.c_void_p), ("qa", C.c_int)]
+                ("ab_b", C.c_void_p), ("qa", C.c_int), ("orth", C.c_int)]
 
 
 class IROpts(C.Structure):
@@ -61,7 +61,7 @@ class IROpts(C.Structure):
                 ("tol_rr", C.c_double), ("tol_be", C.c_double), ("i_max", C.c_int),
                 ("gmres_max", C.c_int), ("x0_mode", C.c_int), ("trans", C.c_int), ("dot64", C.c_int),
                 ("stag", C.c_double), ("arp_b", C.c_void_p), ("aci_b", C.c_void_p), ("at_b", C.c_void_p),
-                ("ab_b", C.c_void_p), ("qa", C.c_int)]
+                ("ab_b", C.c_void_p), ("qa", C.c_int), ("orth", C.c_int)]
 
 
 class IRStats(C.Structure):
@@ -328,6 +328,12 @@ def backward_error(A, b, x, dd: bool = True) -> float:
 
 # ---------------------------------------------------------------- Krylov
 
+def _orth(name: str) -> int:
+    if name not in ("mgs", "cgs2"):
+        raise ValueError("orth must be 'mgs' or 'cgs2'")
+    return 0 if name == "mgs" else 1
+
+
 def _set_ab(o, Ab, trans):
     """Point the option struct at the bucketed A (A^T when trans); returns the
     object that owns the arrays, to be kept alive over the call."""
@@ -341,13 +347,15 @@ def _set_ab(o, Ab, trans):
 
 def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32, max_it: Optional[int] = None,
           trans: bool = False, want_basis: bool = False, dot64: bool = False,
-          Ab: Optional[Bucketed] = None) -> Dict:
+          Ab: Optional[Bucketed] = None, orth: str = "mgs") -> Dict:
     """One preconditioned MGS-GMRES solve (left: M A d = M r; trans: A^T M^T).
     dot64: dots and norms accumulated in FP64 over u_g data (the default sums
-    sequentially in u_g).  Ab: A applied bucketed (eqs. (nbe2), (fe2))."""
+    sequentially in u_g).  Ab: A applied bucketed (eqs. (nbe2), (fe2)).
+    orth: "mgs" (the paper's) or "cgs2" (classical Gram-Schmidt twice)."""
     n = A.n
     m = min(n, max_it if max_it is not None else n)
     o = GmresOpts(ug, up, float(tau), m, int(trans), int(dot64))
+    o.orth = _orth(orth)
     Aop_b = _set_ab(o, Ab, trans)
     d = np.zeros(n)
     its = C.c_int(0)
@@ -376,15 +384,17 @@ def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32,
 def gmres_ir(A, M, Mb: Bucketed, b, ug: int = FP32, up: int = FP32, ur_dd: bool = True, tau: float = 1e-4,
              tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: Optional[int] = None,
              x0_mode: int = 0, trans: bool = False, dot64: bool = False, stag_ratio: Optional[float] = 0.5,
-             Ab: Optional["Bucketed"] = None) -> Dict:
+             Ab: Optional["Bucketed"] = None, orth: str = "mgs") -> Dict:
     """BSPAI-GMRES-IR (Algorithm 4).  M: FP64 SPAI as workloads.CSR (for x_0).
     dot64 as in :func:`gmres`; stag_ratio None: no stagnation stop; Ab: A
     bucketed (Bucketed of A) to apply A inside GMRES as well (eqs. (nbe2),
-    (fe2)); None: A rounded to u_p."""
+    (fe2)); None: A rounded to u_p.  orth: Gram-Schmidt of GMRES ("mgs" or
+    "cgs2")."""
     n = A.n
     gm = min(n, gmres_max if gmres_max is not None else n)
     o = IROpts(ug, up, int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), gm, int(x0_mode),
                int(trans), int(dot64), -1.0 if stag_ratio is None else float(stag_ratio))
+    o.orth = _orth(orth)
     Aop_b = _set_ab(o, Ab, trans)
     st = IRStats()
     x = np.zeros(n)

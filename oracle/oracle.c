@@ -749,6 +749,15 @@ static double vec_norm_inf(int n, const double *x) {
  * adjoint): solves A^T M^T w = r, d = M^T w,  stop when |g_{j+1}| <= tau ||r||_2.
  * In that case (rp, ci, v) and (mrp, mci, mt, mb) describe A^T and M^T.
  *
+ * orth = 1 replaces modified Gram-Schmidt by classical Gram-Schmidt run
+ * twice (CGS2, "twice is enough": Giraud, Langou, Rozloznik and van den
+ * Eshof, Numer. Math. 101, 2005): each pass takes all coefficients
+ * h_i = v_i . z against the same z, then forms z - sum_i h_i v_i (with
+ * dot64: the sum in FP64 by FMAs in the order i = 0..j, rounded once to u_g;
+ * otherwise each term subtracted in u_g); the Hessenberg column is the sum
+ * of both passes' coefficients.  In exact arithmetic it is the same Arnoldi
+ * process; it trades the j dependent reductions of MGS for two.
+ *
  * Stops also on h_{j+1,j} = 0 (the Krylov space is invariant: exact
  * solution) or after max_it iterations.  V_out (n x (max_it+1), column-major)
  * and H_out ((max_it+1) x max_it, column-major) receive the Arnoldi basis and
@@ -767,6 +776,7 @@ typedef struct {
     const double *at_b;
     const signed char *ab_b;
     int qa;
+    int orth;         /* 0: modified Gram-Schmidt (the paper's), 1: CGS2 */
 } orc_gmres_opts;
 
 static inline double wp(int prec, double x) {
@@ -790,7 +800,8 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
     double *w = (double *)malloc(sizeof(double) * (size_t)n);
     double *z = (double *)malloc(sizeof(double) * (size_t)n);
     double *rr = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!V || !H || !cs || !sn || !g || !w || !z || !rr) return ORC_ENOMEM;
+    double *cg = (double *)calloc((size_t)m + 1, sizeof(double)); /* one CGS pass's coefficients */
+    if (!V || !H || !cs || !sn || !g || !w || !z || !rr || !cg) return ORC_ENOMEM;
 
     /* right-hand side of the Krylov solve, in u_g */
     for (int i = 0; i < n; i++) rr[i] = wp(ug, r[i]);
@@ -812,7 +823,7 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
     if (beta == 0.0) {
         *its_out = 0;
         if (relres_out) *relres_out = 0.0;
-        free(V); free(H); free(cs); free(sn); free(g); free(w); free(z); free(rr);
+        free(V); free(H); free(cs); free(sn); free(g); free(w); free(z); free(rr); free(cg);
         return ORC_OK;
     }
     for (int i = 0; i < n; i++) s[i] = wp(ug, s[i] / beta);
@@ -831,6 +842,29 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
             else orc_spmv(n, rp, ci, v, up, w, z, ug);            /* z = A_p^T w   */
         }
         double *hj = H + (size_t)j * ld;
+        if (o->orth == 1) {                                        /* CGS2 */
+            for (int i = 0; i <= j; i++) hj[i] = 0.0;
+            for (int pass = 0; pass < 2; pass++) {
+                for (int i = 0; i <= j; i++) {
+                    const double *vi = V + (size_t)i * n;
+                    double h = 0;
+                    if (d64) for (int l = 0; l < n; l++) h += vi[l] * z[l];
+                    else for (int l = 0; l < n; l++) h = wp(ug, h + wp(ug, vi[l] * z[l]));
+                    cg[i] = h;
+                    hj[i] += h;
+                }
+                for (int l = 0; l < n; l++) {
+                    double t = z[l];
+                    if (d64) {
+                        for (int i = 0; i <= j; i++) t = fma(-cg[i], V[(size_t)i * n + l], t);
+                        z[l] = wp(ug, t);
+                    } else {
+                        for (int i = 0; i <= j; i++) t = wp(ug, t - wp(ug, cg[i] * V[(size_t)i * n + l]));
+                        z[l] = t;
+                    }
+                }
+            }
+        } else
         for (int i = 0; i <= j; i++) {                             /* modified Gram-Schmidt */
             const double *vi = V + (size_t)i * n;
             double h = 0;
@@ -894,7 +928,7 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
     if (V_out) memcpy(V_out, V, sizeof(double) * (size_t)n * (k + 1));
     *its_out = k;
     if (relres_out) *relres_out = res / beta;
-    free(y); free(V); free(H); free(cs); free(sn); free(g); free(w); free(z); free(rr);
+    free(y); free(V); free(H); free(cs); free(sn); free(g); free(w); free(z); free(rr); free(cg);
     return ORC_OK;
 }
 
@@ -928,6 +962,7 @@ typedef struct {
     const double *at_b;
     const signed char *ab_b;
     int qa;
+    int orth;   /* Gram-Schmidt variant of GMRES, as in orc_gmres_opts */
 } orc_ir_opts;
 
 typedef struct {
@@ -956,7 +991,7 @@ int orc_gmres_ir(int n, const int *rp, const int *ci, const double *v,
         for (int i = 0; i < n; i++) x[i] = 0.0;
     }
     orc_gmres_opts go = {o->ug, o->up, o->tau, o->gmres_max, o->trans, o->dot64,
-                         o->arp_b, o->aci_b, o->at_b, o->ab_b, o->qa};
+                         o->arp_b, o->aci_b, o->at_b, o->ab_b, o->qa, o->orth};
     int status = ORC_OK, stagnated = 0;
     double dx_prev = 0;
     int i = 0;
