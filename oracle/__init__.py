@@ -24,7 +24,9 @@ Parity status per function (the pins live in ``tests/test_oracle_*.py``):
 * ``gmres`` / ``gmres_ir``  pinned: termination in <= n steps, Arnoldi relation,
   closed-form spectra, dense solves, backward error reaching O(u).  Their
   bucketed-A option (``Ab``): a one-bucket A_b reproduces the u_p path bit for
-  bit, the first Arnoldi step by hand, the per-row product bound.
+  bit, the first Arnoldi step by hand, the per-row product bound.  Their
+  CGS2 option (``orth``): Arnoldi relation, full orthogonality where MGS
+  loses it, Krylov termination facts, the first fp32 step by hand.
 * ``gradient``  pinned: dense ``numpy.linalg.solve`` adjoint and finite differences.
 """
 from __future__ import annotations
