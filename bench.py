@@ -227,7 +227,8 @@ def main():
         comps = {}
         h64 = B.build(Ad, Pd, eps=2.0 ** -53, precs=["fp64"])
         for name, hh, extra in (("spai_fp64_all", h64, dict(u_g="fp64", tau=1e-8)),
-                                ("spai_fp64M_fp32krylov", h64, {})):
+                                ("spai_fp64M_fp32krylov", h64, {}),
+                                ("bspai_cgs2", h, dict(orth="cgs2"))):
             k2 = dict(kw)
             k2.update(extra)
             for _ in range(2):

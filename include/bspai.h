@@ -145,6 +145,9 @@ typedef struct {
     int trans;      /* 1: solve A^T x = b with (M_b)^T as a right preconditioner (adjoint solve) */
     double stag_ratio; /* stagnation: stop when ||d_i||/||x_{i+1}|| > stag_ratio times the previous ratio
                           (from the second correction on); 0 selects 0.5, a negative value never stops */
+    int orth;          /* Arnoldi orthogonalisation: 0 modified Gram-Schmidt (the paper's), 1 classical
+                          Gram-Schmidt twice (CGS2: two grid-wide reductions per step instead of j + 1;
+                          gmres_ir_solve / gmres_ir_solve_ab with nrhs = 1 only) */
 } gmres_ir_tol;
 
 typedef struct {
@@ -163,6 +166,7 @@ typedef struct {
  *   stored FP64), stopping tests, left-preconditioned MGS-GMRES on
  *   M_b A d = M_b r_i in u_g with A rounded to u_g (right-preconditioned
  *   A^T M_b^T for trans = 1) to relative tolerance tau, x_{i+1} = x_i + d_i in FP64.
+ *   orth = 1 orthogonalises by CGS2 instead of MGS (nrhs = 1; EINVAL otherwise).
  *   Stops on tol_rr, tol_be, stagnation of ||d_i||/||x_{i+1}|| (more than
  *   stag_ratio times the previous ratio after the first correction) or i_max.
  *   A: device CSR; b, x: device FP64 arrays of n x nrhs, row-major (entry
@@ -353,7 +357,8 @@ double bspai_last_solve_kernel_ms(void);
  * `iters` dependent grid-wide FP64 all-reductions by G co-resident blocks of
  * the solver's size with the solver's own exchange, and writes the average
  * time of one to *us_out (microseconds, host pointer).  Synchronises `stream`.
- * bspai_solve_blocks -- the number of blocks gmres_ir_solve uses for n rows.
+ * bspai_solve_blocks -- the number of blocks gmres_ir_solve uses for n rows
+ *   with MGS (orth = 0, one right-hand side).
  */
 int bspai_exchange_latency(int G, int iters, double *us_out, void *stream);
 int bspai_solve_blocks(int n);

@@ -56,7 +56,7 @@ class _Opts(C.Structure):
 class _Tol(C.Structure):
     _fields_ = [("u_g", C.c_int), ("ur_dd", C.c_int), ("tau", C.c_double), ("tol_rr", C.c_double),
                 ("tol_be", C.c_double), ("i_max", C.c_int), ("gmres_max", C.c_int), ("x0_mode", C.c_int),
-                ("trans", C.c_int), ("stag_ratio", C.c_double)]
+                ("trans", C.c_int), ("stag_ratio", C.c_double), ("orth", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -384,14 +384,16 @@ def _stag(r: Optional[float]) -> float:
 def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4,
           tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0,
           trans: bool = False, x: Optional[torch.Tensor] = None, stream=None, raise_noconv: bool = False,
-          stag_ratio: Optional[float] = 0.5, A_b: Optional[Handle] = None):
+          stag_ratio: Optional[float] = 0.5, A_b: Optional[Handle] = None, orth: str = "mgs"):
     """BSPAI-GMRES-IR.  b: [n] or [n, nrhs] (1 <= nrhs <= 64, row-major)
     float64 on the GPU.  Returns (x, stats): one stats dict for a 1-D b, a
     list of them (one per column) for a 2-D b.  ENOCONV is reported in the
     stats (status) unless raise_noconv.  stag_ratio: stop when a correction's
     ||d||/||x|| exceeds stag_ratio times the previous one (None: never).
     A_b: A bucketed (:func:`bucket_a`) for the products inside GMRES
-    (``gmres_ir_solve_ab``); None: A rounded to u_g."""
+    (``gmres_ir_solve_ab``); None: A rounded to u_g.  orth: "mgs" (the
+    paper's modified Gram-Schmidt) or "cgs2" (classical Gram-Schmidt twice,
+    two grid-wide reductions per Arnoldi step; one right-hand side)."""
     if b.dtype != torch.float64 or not b.is_cuda or b.dim() not in (1, 2):
         raise ValueError("b must be a 1-D or 2-D float64 CUDA tensor")
     b = b.contiguous()
@@ -402,8 +404,10 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
         x = torch.zeros_like(b) if x0_mode == 3 else torch.empty_like(b)
     elif x.shape != b.shape or x.dtype != torch.float64 or not x.is_contiguous():
         raise ValueError("x must be a contiguous float64 tensor shaped like b")
+    if orth not in ("mgs", "cgs2"):
+        raise ValueError("orth must be 'mgs' or 'cgs2'")
     tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), int(gmres_max),
-               int(x0_mode), int(trans), _stag(stag_ratio))
+               int(x0_mode), int(trans), _stag(stag_ratio), 0 if orth == "mgs" else 1)
     st = (_Stats * nrhs)()
     a = A._c()
     allow = () if raise_noconv else (ENOCONV,)

@@ -114,9 +114,9 @@ struct SpaiArgs {
 //   Householder QR of Abar, mbar = R^{-1} (Q^T ebar)(1:|J|); M(k, J) = mbar.
 // T is the construction precision u_f (Section 4: double, single or half):
 // the tile holds a_{J_c, I_l} d_j rounded to T, every operation of the QR
-// and the back substitution is done in T (the compiler may fuse a multiply
-// and an add into one rounding; sums run as wavefront trees), and M(k, j) is
-// mbar_j d_j rounded to T, stored in FP64.
+// and the back substitution is done in T and rounded separately (the library
+// is built without implicit multiply-add fusion; sums run as wavefront
+// trees), and M(k, j) is mbar_j d_j rounded to T, stored in FP64.
 template <typename T>
 __global__ void __launch_bounds__(64) k_spai(SpaiArgs a) {
   extern __shared__ double lds_d[];

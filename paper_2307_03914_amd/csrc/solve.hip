@@ -40,8 +40,11 @@ struct Grid {
   unsigned *flags;  // [G] epoch reached by each block
   unsigned *abortf; // set when a wait exceeds the spin bound
   double *slots;    // [kNumSlots][kMaxBlocks][kMaxSlotWidth][2] tagged 64-bit words
+  unsigned long long *wide;  // [kNumSlots][kMaxBlocks][kMaxGmres + 1][2] for vector reductions (or null)
   int G;
 };
+
+constexpr size_t kWideBytes = 16 * (size_t)kNumSlots * kMaxBlocks * (kMaxGmres + 1);
 
 template <typename VT>
 struct SolveParams {
@@ -55,6 +58,7 @@ struct SolveParams {
   const int32_t *f_rp, *f_col;
   const double *f_val;  // FP64 M (M^T for trans), x0_mode 0
   int x0_mode, trans, ur_dd, i_max;
+  int orth;  // 0 MGS, 1 CGS2
   double tau, tol_rr, tol_be;
   double stag;  // stagnation ratio (<= 0: no stagnation stop)
   const double *b;
@@ -90,13 +94,40 @@ __device__ bool grid_sync(const Grid &g, unsigned &epoch, int bid) {
   return !bad;
 }
 
+// DPP move of a double (two 32-bit halves); lanes whose row is masked off or
+// whose source lane is out of range receive 0
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, BOUND);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, BOUND);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront with DPP row shifts and row
+// broadcasts (register-to-register, no LDS permutes): row_shr 1, 2, 4, 8
+// leave each row's sum in its lane 15, row_bcast:15 adds row 0 into row 1 and
+// row 2 into row 3, row_bcast:31 adds lane 31 into rows 2 and 3, and lane 63
+// holds the total, which every lane reads back.  Fixed order: identical bits
+// in every lane and every call.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov<0x111, 0xf, true>(v);
+  v += dpp_mov<0x112, 0xf, true>(v);
+  v += dpp_mov<0x114, 0xf, true>(v);
+  v += dpp_mov<0x118, 0xf, true>(v);
+  v += dpp_mov<0x142, 0xa, false>(v);
+  v += dpp_mov<0x143, 0xc, false>(v);
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                          __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
 template <bool MAX>
 __device__ __forceinline__ double wave_red(double v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    double t = __shfl_xor(v, o);
-    v = MAX ? fmax(v, t) : v + t;
+  if constexpr (!MAX) {
+    return wave_sum_dpp(v);
+  } else {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
   }
-  return v;
 }
 
 // A scalar exchange needs no fences: every block publishes its FP64 partial as
@@ -105,17 +136,20 @@ __device__ __forceinline__ double wave_red(double v) {
 // poll the words with relaxed atomic loads until both tags match.  Atomicity of
 // each word is all the protocol relies on; no cache is written back or
 // invalidated, so the blocks keep their basis slices in L2.
-__device__ __forceinline__ void publish_partial(unsigned long long *w, double v, unsigned tag) {
+// exchange round -> 16-bit tag; never 0, the value of cleared slot words
+__device__ __forceinline__ unsigned long long tag16(unsigned rtag) { return rtag % 65535u + 1u; }
+
+__device__ __forceinline__ void publish_partial(unsigned long long *w, double v, unsigned rtag) {
   unsigned long long b = __double_as_longlong(v);
-  unsigned long long t = tag & 0xFFFFull;
+  unsigned long long t = tag16(rtag);
   __hip_atomic_store(&w[0], (b & ~0xFFFFull) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(&w[1], ((b & 0xFFFFull) << 16) | t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // returns false when the wait exceeds the bound or another block aborted
-__device__ __forceinline__ bool collect_partial(unsigned long long *w, unsigned tag, const unsigned *abortf,
+__device__ __forceinline__ bool collect_partial(unsigned long long *w, unsigned rtag, const unsigned *abortf,
                                                 double *out) {
-  const unsigned long long t = tag & 0xFFFFull;
+  const unsigned long long t = tag16(rtag);
   unsigned long long a, b;
   unsigned spins = 0;
   for (;;) {
@@ -193,6 +227,74 @@ __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], doubl
   return true;
 }
 
+// All-reduction (sum) of W <= kMaxGmres + 1 values over the grid, for CGS2.
+// in: the block's W partials (LDS); out: the grid sums (LDS); tmp: blockDim
+// doubles of LDS.  Thread t*tpv + q sums value t over blocks q, q + tpv, ...
+// (tpv a power of two, the most that fit the block), issuing the loads of
+// kVecBatch blocks at once, and the tpv sums are then added in order q = 0,
+// 1, ...: every block obtains identical bits.  Ends with a workgroup barrier.
+constexpr int kVecBatch = 16;
+__device__ bool grid_reduce_vec(const Grid &g, unsigned &rtag, int W, const double *in, double *out, double *tmp,
+                                int bid) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  rtag++;
+  if (g.G == 1) {
+    for (int t = tid; t < W; t += nt) out[t] = in[t];
+    __syncthreads();
+    return true;
+  }
+  constexpr size_t kStride = kMaxGmres + 1;
+  unsigned long long *set = g.wide + (size_t)(rtag % kNumSlots) * kMaxBlocks * kStride * 2;
+  for (int t = tid; t < W; t += nt) publish_partial(set + ((size_t)bid * kStride + t) * 2, in[t], rtag);
+  int tpv = 1;
+  while (2 * tpv * W <= nt && 2 * tpv <= g.G) tpv *= 2;
+  const int t = tid / tpv, q = tid % tpv;
+  const unsigned long long tg = tag16(rtag);
+  int bad = 0;
+  if (t < W) {
+    double acc = 0.0;
+    for (int b0 = q; b0 < g.G && !bad; b0 += tpv * kVecBatch) {
+      unsigned long long wa[kVecBatch], wb[kVecBatch];
+#pragma unroll
+      for (int u = 0; u < kVecBatch; u++) {
+        const int b = b0 + u * tpv;
+        wa[u] = wb[u] = 0;
+        if (b < g.G) {
+          unsigned long long *w = set + ((size_t)b * kStride + t) * 2;
+          wa[u] = __hip_atomic_load(&w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          wb[u] = __hip_atomic_load(&w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kVecBatch; u++) {
+        const int b = b0 + u * tpv;
+        if (b >= g.G || bad) continue;
+        double x;
+        if ((wa[u] & 0xFFFFull) == tg && (wb[u] & 0xFFFFull) == tg) {
+          x = __longlong_as_double((long long)((wa[u] & ~0xFFFFull) | ((wb[u] >> 16) & 0xFFFFull)));
+        } else if (!collect_partial(set + ((size_t)b * kStride + t) * 2, rtag, g.abortf, &x)) {
+          bad = 1;
+          continue;
+        }
+        acc += x;
+      }
+    }
+    tmp[tid] = acc;
+  }
+  bad = __syncthreads_or(bad);
+  if (bad) {
+    if (tid == 0) __hip_atomic_store(g.abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+  for (int t2 = tid; t2 < W; t2 += nt) {
+    double a = tmp[t2 * tpv];
+    for (int q2 = 1; q2 < tpv; q2++) a += tmp[t2 * tpv + q2];
+    out[t2] = a;
+  }
+  __syncthreads();
+  return true;
+}
+
 // ------------------------------------------------------------------ rows
 
 template <typename XT, typename YT>
@@ -249,7 +351,7 @@ __device__ __forceinline__ double residual_row(const int32_t *rp, const int32_t 
 // Algorithm 4 for one system by the G blocks of `G`; bid is the calling
 // block's index among them.  epoch and rtag carry on from earlier calls by
 // the same blocks.  Returns false when a wait timed out (G.abortf is set).
-template <typename VT, typename PT, int ZR>
+template <typename VT, typename PT, int ZR, bool CGS2 = false>
 __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, unsigned &epoch, unsigned &rtag,
                               double *sm, double *sh, int &s_flag) {
   constexpr int kCap = kTileBytes / sizeof(PT);
@@ -369,59 +471,130 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
         __syncthreads();
         VT zr[ZR];
         OWN_ROWS(k, i) { zr[k] = p.zg[i]; }
-        // modified Gram-Schmidt: pass i removes the v_{i-1} component and
-        // measures the v_i component of the updated z.  The slice of v_{i+1}
-        // does not depend on h_i, so it is loaded before the reduction of
-        // pass i and arrives while the blocks exchange their partials.
-        double hprev = 0.0;
-        VT vprev[ZR], vcur[ZR], vnext[ZR];
-        OWN_ROWS(k, i) { vnext[k] = p.V[i]; }
-        for (int i2 = 0; i2 <= j; i2++) {
+        if constexpr (!CGS2) {
+          // modified Gram-Schmidt: pass i removes the v_{i-1} component and
+          // measures the v_i component of the updated z.  The slice of v_{i+1}
+          // does not depend on h_i, so it is loaded before the reduction of
+          // pass i and arrives while the blocks exchange their partials.
+          double hprev = 0.0;
+          VT vprev[ZR], vcur[ZR], vnext[ZR];
+          OWN_ROWS(k, i) { vnext[k] = p.V[i]; }
+          for (int i2 = 0; i2 <= j; i2++) {
 #pragma unroll
-          for (int k = 0; k < ZR; k++) {
-            vprev[k] = vcur[k];
-            vcur[k] = vnext[k];
+            for (int k = 0; k < ZR; k++) {
+              vprev[k] = vcur[k];
+              vcur[k] = vnext[k];
+            }
+            if (i2 < j) {
+              const VT *vn2 = p.V + (size_t)(i2 + 1) * n;
+              OWN_ROWS(k, i) { vnext[k] = vn2[i]; }
+            }
+            double part[1] = {0.0};
+            OWN_ROWS(k, i) {
+              if (i2 > 0) zr[k] = (VT)fma(-hprev, (double)vprev[k], (double)zr[k]);
+              part[0] = fma((double)vcur[k], (double)zr[k], part[0]);
+            }
+            if (!grid_reduce<1, false>(G, rtag, part, sh, bid)) return false;
+            hprev = part[0];
+            if (tid == 0) hcol[i2] = hprev;
           }
-          if (i2 < j) {
-            const VT *vn2 = p.V + (size_t)(i2 + 1) * n;
-            OWN_ROWS(k, i) { vnext[k] = vn2[i]; }
+          OWN_ROWS(k, i) { zr[k] = (VT)fma(-hprev, (double)vcur[k], (double)zr[k]); }
+        } else {
+          // CGS2: two passes, each taking all j + 1 coefficients against the
+          // same z in one vector all-reduction, then z - V h formed in FP64
+          // (FMAs in the order i = 0..j) and rounded once.  The product tile
+          // is free here and holds the reduction's scratch.
+          const int W = j + 1, lane = tid & 63, wv = tid >> 6;
+          double *wpart = reinterpret_cast<double *>(tprod);  // [kWaves][W]
+          double *bpart = wpart + kWaves * (kMaxGmres + 1);   // [W]
+          double *tmp = bpart + (kMaxGmres + 1);              // [blockDim]
+          double *hv = tmp + kSolveThreads;                   // [W]
+          // basis slices are loaded kCh vectors at a time so that the loads
+          // are in flight together rather than one latency per vector
+          constexpr int kCh = ZR <= 2 ? 8 : (ZR <= 4 ? 4 : 2);    // dot products
+          constexpr int kChU = ZR <= 2 ? 16 : (ZR <= 4 ? 8 : 4);  // update
+          for (int pass = 0; pass < 2; pass++) {
+            for (int i0 = 0; i0 < W; i0 += kCh) {
+              VT vv[kCh][ZR];
+#pragma unroll
+              for (int u = 0; u < kCh; u++) {
+                const VT *vi = p.V + (size_t)(i0 + u) * n;
+                OWN_ROWS(k, i) { vv[u][k] = i0 + u < W ? vi[i] : (VT)0; }
+              }
+              double part[kCh];
+#pragma unroll
+              for (int u = 0; u < kCh; u++) {
+                part[u] = 0.0;
+                OWN_ROWS(k, i) { part[u] = fma((double)vv[u][k], (double)zr[k], part[u]); }
+              }
+#pragma unroll
+              for (int u = 0; u < kCh; u++) part[u] = wave_red<false>(part[u]);
+              if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < kCh; u++)
+                  if (i0 + u < W) wpart[wv * W + i0 + u] = part[u];
+              }
+            }
+            __syncthreads();
+            for (int t = tid; t < W; t += nt) {
+              double a = wpart[t];
+              for (int w = 1; w < kWaves; w++) a += wpart[w * W + t];
+              bpart[t] = a;
+            }
+            __syncthreads();
+            if (!grid_reduce_vec(G, rtag, W, bpart, hv, tmp, bid)) return false;
+            double acc[ZR];
+            OWN_ROWS(k, i) { acc[k] = (double)zr[k]; }
+            for (int i0 = 0; i0 < W; i0 += kChU) {
+              VT vv[kChU][ZR];
+#pragma unroll
+              for (int u = 0; u < kChU; u++) {
+                const VT *vi = p.V + (size_t)(i0 + u) * n;
+                OWN_ROWS(k, i) { vv[u][k] = i0 + u < W ? vi[i] : (VT)0; }
+              }
+#pragma unroll
+              for (int u = 0; u < kChU; u++) {
+                if (i0 + u < W) {
+                  const double h = hv[i0 + u];
+                  OWN_ROWS(k, i) { acc[k] = fma(-h, (double)vv[u][k], acc[k]); }
+                }
+              }
+            }
+            OWN_ROWS(k, i) { zr[k] = (VT)acc[k]; }
+            for (int t = tid; t < W; t += nt) hcol[t] = pass == 0 ? hv[t] : hcol[t] + hv[t];
+            __syncthreads();
           }
-          double part[1] = {0.0};
-          OWN_ROWS(k, i) {
-            if (i2 > 0) zr[k] = (VT)fma(-hprev, (double)vprev[k], (double)zr[k]);
-            part[0] = fma((double)vcur[k], (double)zr[k], part[0]);
-          }
-          if (!grid_reduce<1, false>(G, rtag, part, sh, bid)) return false;
-          hprev = part[0];
-          if (tid == 0) hcol[i2] = hprev;
         }
         double nz[1] = {0.0};
-        OWN_ROWS(k, i) {
-          zr[k] = (VT)fma(-hprev, (double)vcur[k], (double)zr[k]);
-          nz[0] = fma((double)zr[k], (double)zr[k], nz[0]);
-        }
+        OWN_ROWS(k, i) { nz[0] = fma((double)zr[k], (double)zr[k], nz[0]); }
         if (!grid_reduce<1, false>(G, rtag, nz, sh, bid)) return false;
         const double hn = sqrt(nz[0]);
         VT *vn = p.V + (size_t)(j + 1) * n;
         OWN_ROWS(k, i) { vn[i] = hn > 0.0 ? (VT)((double)zr[k] / hn) : (VT)0; }
         // Givens rotations on the new Hessenberg column (identical in every block)
+        // (the rotated entry i2 + 1 is carried to the next rotation in a
+        // register rather than through LDS)
         if (tid == 0) {
-          hcol[j + 1] = hn;
+          double a = hcol[0];
           for (int i2 = 0; i2 < j; i2++) {
-            double a = hcol[i2], bb = hcol[i2 + 1];
+            const double bb = hcol[i2 + 1];
             hcol[i2] = cs[i2] * a + sn[i2] * bb;
-            hcol[i2 + 1] = -sn[i2] * a + cs[i2] * bb;
+            a = -sn[i2] * a + cs[i2] * bb;
           }
-          double a = hcol[j], bb = hcol[j + 1];
+          const double bb = hn;
           double rho2 = hypot(a, bb);
           cs[j] = rho2 == 0.0 ? 1.0 : a / rho2;
           sn[j] = rho2 == 0.0 ? 0.0 : bb / rho2;
           hcol[j] = rho2;
+          hcol[j + 1] = hn;
           g[j + 1] = -sn[j] * g[j];
           g[j] = cs[j] * g[j];
-          double *Rc = Rp + (size_t)j * (j + 1) / 2;
-          for (int i2 = 0; i2 <= j; i2++) Rc[i2] = hcol[i2];
           s_flag = (fabs(g[j + 1]) <= p.tau * beta) || (hn == 0.0);
+        }
+        __syncthreads();
+        {
+          double *Rc = Rp + (size_t)j * (j + 1) / 2;
+          for (int i2 = tid; i2 <= j; i2 += nt) Rc[i2] = hcol[i2];
         }
         __syncthreads();
         kdone = j + 1;
@@ -506,13 +679,13 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
 }
 
 // one system on the whole grid
-template <typename VT, typename PT, int ZR>
+template <typename VT, typename PT, int ZR, bool CGS2>
 __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT> *__restrict__ pp) {
   extern __shared__ double sm[];
   __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
   __shared__ int s_flag;
   unsigned epoch = 0, rtag = 0;
-  (void)gmres_ir_body<VT, PT, ZR>(*pp, pp->grid, blockIdx.x, epoch, rtag, sm, sh, s_flag);
+  (void)gmres_ir_body<VT, PT, ZR, CGS2>(*pp, pp->grid, blockIdx.x, epoch, rtag, sm, sh, s_flag);
 }
 
 template <typename VT>
@@ -541,12 +714,14 @@ constexpr size_t kSlotBytes = 16 * (size_t)kNumSlots * kMaxBlocks * kMaxSlotWidt
 
 // device memory of one system's solve, as offsets from a base address
 struct SysLayout {
-  size_t ap, rv, w, zg, V, dv, dv2, flags, abort, slots, stats, params, acol, trp, tcol, tval, total;
+  size_t ap, rv, w, zg, V, dv, dv2, flags, abort, slots, wide, stats, params, acol, trp, tcol, tval, total;
+  bool has_wide;
 };
 
 template <typename VT>
-static SysLayout sys_layout(int n, int64_t nnz, int m, bool tr) {
+static SysLayout sys_layout(int n, int64_t nnz, int m, bool tr, bool wide_slots = false) {
   SysLayout L{};
+  L.has_wide = wide_slots;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -563,6 +738,7 @@ static SysLayout sys_layout(int n, int64_t nnz, int m, bool tr) {
   L.flags = take(4 * kMaxBlocks);
   L.abort = take(4);
   L.slots = take(kSlotBytes);
+  if (wide_slots) L.wide = take(kWideBytes);
   L.stats = take(sizeof(gmres_ir_stats));
   L.params = take(sizeof(SolveParams<VT>));
   L.acol = take(4 * (size_t)(nnz + 1));
@@ -638,6 +814,7 @@ static int sys_setup(const bspai_csr *A, const bspai_handle *Ab, const double *b
   p.f_col = tr ? M->mT_col : M->m_col;
   p.f_val = tr ? M->mT_val : M->m_val;
   p.x0_mode = tol->x0_mode;
+  p.orth = tol->orth;
   p.trans = tr;
   p.ur_dd = tol->ur_dd;
   p.i_max = tol->i_max;
@@ -656,6 +833,7 @@ static int sys_setup(const bspai_csr *A, const bspai_handle *Ab, const double *b
   p.grid.flags = reinterpret_cast<unsigned *>(base + L.flags);
   p.grid.abortf = reinterpret_cast<unsigned *>(base + L.abort);
   p.grid.slots = reinterpret_cast<double *>(base + L.slots);
+  p.grid.wide = L.has_wide ? reinterpret_cast<unsigned long long *>(base + L.wide) : nullptr;
   p.grid.G = G;
   p.stats = reinterpret_cast<gmres_ir_stats *>(base + L.stats);
   wide = sizeof(VT) == 8;
@@ -676,24 +854,29 @@ static int sys_setup(const bspai_csr *A, const bspai_handle *Ab, const double *b
 // rows per block (a multiple of 64) when n rows are split over g blocks
 static int rows_for(int n, int g) { return ((n + g - 1) / g + kSlice - 1) / kSlice * kSlice; }
 
-template <typename VT>
-static void *pick_single(bool wide, int ZR) {
+template <typename VT, bool CGS2>
+static void *pick_single_o(bool wide, int ZR) {
   if (wide) {
     switch (ZR) {
-      case 1: return (void *)k_gmres_ir<VT, double, 1>;
-      case 2: return (void *)k_gmres_ir<VT, double, 2>;
-      case 4: return (void *)k_gmres_ir<VT, double, 4>;
-      case 8: return (void *)k_gmres_ir<VT, double, 8>;
-      default: return (void *)k_gmres_ir<VT, double, 16>;
+      case 1: return (void *)k_gmres_ir<VT, double, 1, CGS2>;
+      case 2: return (void *)k_gmres_ir<VT, double, 2, CGS2>;
+      case 4: return (void *)k_gmres_ir<VT, double, 4, CGS2>;
+      case 8: return (void *)k_gmres_ir<VT, double, 8, CGS2>;
+      default: return (void *)k_gmres_ir<VT, double, 16, CGS2>;
     }
   }
   switch (ZR) {
-    case 1: return (void *)k_gmres_ir<VT, float, 1>;
-    case 2: return (void *)k_gmres_ir<VT, float, 2>;
-    case 4: return (void *)k_gmres_ir<VT, float, 4>;
-    case 8: return (void *)k_gmres_ir<VT, float, 8>;
-    default: return (void *)k_gmres_ir<VT, float, 16>;
+    case 1: return (void *)k_gmres_ir<VT, float, 1, CGS2>;
+    case 2: return (void *)k_gmres_ir<VT, float, 2, CGS2>;
+    case 4: return (void *)k_gmres_ir<VT, float, 4, CGS2>;
+    case 8: return (void *)k_gmres_ir<VT, float, 8, CGS2>;
+    default: return (void *)k_gmres_ir<VT, float, 16, CGS2>;
   }
+}
+
+template <typename VT>
+static void *pick_single(bool wide, int ZR, bool cgs2) {
+  return cgs2 ? pick_single_o<VT, true>(wide, ZR) : pick_single_o<VT, false>(wide, ZR);
 }
 
 template <typename VT>
@@ -705,8 +888,12 @@ static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double 
   // about two rows per thread: each MGS pass is bound by the latency of
   // loading a basis slice and exchanging a partial, not by bandwidth, and more
   // blocks make every exchange wait for more partials (measured on MI355X at
-  // n = 65,536: 32 blocks 10.5, 64 blocks 13.0, 128 blocks 11.3 solves/s)
-  int G = std::min(kMaxBlocks, std::max(1, (n + 2 * kSolveThreads - 1) / (2 * kSolveThreads)));
+  // n = 65,536: 32 blocks 10.5, 64 blocks 13.0, 128 blocks 11.3 solves/s).
+  // CGS2 has five exchanges per iteration whatever j is, and its basis
+  // sweeps gain from more compute units: about one row per thread (64 blocks
+  // 18.8, 128 blocks 21.6 solves/s)
+  const int rpt = tol->orth ? 1 : 2;
+  int G = std::min(kMaxBlocks, std::max(1, (n + rpt * kSolveThreads - 1) / (rpt * kSolveThreads)));
   if (const char *e = getenv("BSPAI_SOLVE_BLOCKS")) G = std::min(kMaxBlocks, std::max(1, atoi(e)));
   int rpb = rows_for(n, G);
   int zr = (rpb + kSolveThreads - 1) / kSolveThreads;
@@ -721,7 +908,7 @@ static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double 
   G = (n + rpb - 1) / rpb;
   if (G < 1) G = 1;
 
-  const SysLayout L = sys_layout<VT>(n, nnz, m, tol->trans != 0);
+  const SysLayout L = sys_layout<VT>(n, nnz, m, tol->trans != 0, tol->orth != 0);
   std::lock_guard<std::mutex> lock(g_ws.mu);
   int dev = 0;
   BSPAI_HIP(hipGetDevice(&dev));
@@ -746,9 +933,10 @@ static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double 
   BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
   // tags restart at 1 every launch: clear the exchange words of the last one
   BSPAI_HIP(hipMemsetAsync(p.grid.slots, 0, kSlotBytes, s));
+  if (p.grid.wide) BSPAI_HIP(hipMemsetAsync(p.grid.wide, 0, kWideBytes, s));
   BSPAI_HIP(hipMemsetAsync(p.stats, 0, sizeof(gmres_ir_stats), s));
   const size_t lds = solve_lds(m);
-  void *fn = pick_single<VT>(wide, ZR);
+  void *fn = pick_single<VT>(wide, ZR, tol->orth != 0);
   BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   SolveParams<VT> *pdev = reinterpret_cast<SolveParams<VT> *>(base + L.params);
   BSPAI_HIP(hipMemcpyAsync(pdev, &p, sizeof(p), hipMemcpyHostToDevice, s));
@@ -1087,6 +1275,7 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
     grids[g].flags = reinterpret_cast<unsigned *>(mem + o_flags) + (size_t)kMaxBlocks * g;
     grids[g].abortf = aborts + g;
     grids[g].slots = reinterpret_cast<double *>(mem + o_slots + kSlotBytes * g);
+    grids[g].wide = nullptr;  // the multi-system launch runs MGS only
     grids[g].G = csize[gclass[g]];
   }
   MultiParams<VT> mp;
@@ -1168,6 +1357,7 @@ extern "C" int bspai_exchange_latency(int G, int iters, double *us_out, void *st
   if (rc) return rc;
   Grid g;
   g.slots = static_cast<double *>(mem);
+  g.wide = nullptr;
   g.abortf = reinterpret_cast<unsigned *>(static_cast<char *>(mem) + kSlotBytes);
   g.flags = nullptr;
   g.G = G;
@@ -1222,6 +1412,7 @@ static int check_system(const bspai_csr *A, const double *b, const bspai_handle 
   if (tol->u_g != BSPAI_FP32 && tol->u_g != BSPAI_FP64) return fail(BSPAI_EINVAL, "%s: u_g must be FP32 or FP64", who);
   if (tol->x0_mode < 0 || tol->x0_mode > 3) return fail(BSPAI_EINVAL, "%s: x0_mode must be 0..3", who);
   if (tol->i_max < 0) return fail(BSPAI_EINVAL, "%s: i_max < 0", who);
+  if (tol->orth != 0 && tol->orth != 1) return fail(BSPAI_EINVAL, "%s: orth must be 0 (MGS) or 1 (CGS2)", who);
   if (tol->trans && !M->has_T) return fail(BSPAI_EINVAL, "%s: trans needs a handle built with build_T", who);
   if (tol->x0_mode == 0 && !M->has_fp64) return fail(BSPAI_EINVAL, "%s: x0_mode 0 needs keep_fp64_M", who);
   int dev = 0;
@@ -1235,6 +1426,7 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
   if (!plan_out) return fail(BSPAI_EINVAL, "bspai_multi_plan: null plan_out");
   *plan_out = nullptr;
   if (!sys || nsys < 1 || !tol) return fail(BSPAI_EINVAL, "bspai_multi_plan: need at least one system and tolerances");
+  if (tol->orth != 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: orth must be 0 (MGS)");
   if (group_blocks < -1 || max_groups < 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: bad group size or count");
   for (int k = 0; k < nsys; k++) {
     int rc = check_system(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, "bspai_multi_plan");
@@ -1356,6 +1548,7 @@ static int solve_entry(const bspai_csr *A, const bspai_handle *Ab, const double 
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (nrhs > 1) {
+    if (tol->orth != 0) return fail(BSPAI_EINVAL, "%s: orth = 1 (CGS2) needs nrhs = 1", who);
     const int m = std::min(std::max(tol->gmres_max, 1), std::min(A->n, kMaxGmres));
     if (tol->u_g == BSPAI_FP64) return solve_batched<double>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
     return solve_batched<float>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);

@@ -597,6 +597,91 @@ def test_solve_batched_adjoint(B):
     h.free()
 
 
+# ------------------------------------------------------- CGS2 Arnoldi
+
+@pytest.mark.parametrize("key", ["1", "2s", "5s", "4as"])
+def test_solve_cgs2_matches_oracle(B, key):
+    """CGS2 orthogonalisation (one grid, 1, 2, 2 and 4 blocks): against the
+    oracle's CGS2 refinement, to the same bar as the MGS solve."""
+    small = key.endswith("s")
+    c = W.config(key[:-1] if small else key, small=small)
+    A, P = c["A"], c["P"]
+    b = c["b"] if c["b"].ndim == 1 else c["b"][:, 0].copy()
+    eps = c["eps"][min(1, len(c["eps"]) - 1)]
+    _say("solve cgs2", key, eps)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    xg, st, h = _solve_case(B, A, P, b, c["precs"], eps, orth="cgs2", **kw)
+    M = _spai_oracle(A, P)
+    ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, dot64=True, orth="cgs2", **kw)
+    _check_column(st, ref, O.backward_error(A, b, xg))
+    h.free()
+
+
+def test_solve_cgs2_adjoint_and_bucketed_a(B):
+    import torch
+
+    c = W.config("5", small=True)
+    A, P = c["A"], c["P"]
+    eps = c["eps"][0]
+    _say("solve cgs2 adjoint + A_b")
+    kw = dict(tau=1e-4, tol_rr=1e-13, gmres_max=150, i_max=40)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"])
+    g = np.random.default_rng(11).standard_normal(A.n)
+    lam, st = B.solve(Ad, _dev(g), h, trans=True, orth="cgs2", **kw)
+    lam = lam.cpu().numpy()
+    ref = np.linalg.solve(A.dense().T, g)
+    assert st["status"] == 0
+    assert np.abs(lam - ref).max() <= 1e-9 * np.abs(ref).max()
+    hA = B.bucket_a(Ad, eps, c["precs"])
+    kw2 = dict(kw, tol_rr=1e-10)
+    x, st = B.solve(Ad, _dev(c["b"]), h, A_b=hA, orth="cgs2", **kw2)
+    torch.cuda.synchronize()
+    M = _spai_oracle(A, P)
+    ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), c["b"], dot64=True, orth="cgs2",
+                     Ab=O.Bucketed(A, eps, c["precs"]), **kw2)
+    _check_column(st, ref, O.backward_error(A, c["b"], x.cpu().numpy()))
+    hA.free()
+    h.free()
+
+
+def test_solve_cgs2_full_size(B):
+    """The 256^2 convection-diffusion system on 64 blocks: the CGS2 solve
+    against the oracle's CGS2 refinement, and beside the MGS solve."""
+    import torch
+
+    c = W.config("2")
+    A, P, b = c["A"], c["P"], c["b"]
+    eps = c["eps"][1]
+    _say("solve cgs2 full size", A.n)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"])
+    x1, st1 = B.solve(Ad, _dev(b), h, orth="cgs2", **kw)
+    x0, st0 = B.solve(Ad, _dev(b), h, **kw)
+    torch.cuda.synchronize()
+    M = W.CSR(A.n, P.row_ptr, P.col, h.export()["m64"])
+    ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, dot64=True, orth="cgs2", **kw)
+    e1 = O.backward_error(A, b, x1.cpu().numpy())
+    _check_column(st1, ref, e1)
+    assert e1 <= 10 * O.backward_error(A, b, x0.cpu().numpy()) + 1e-17
+    assert abs(st1["steps"] - st0["steps"]) <= 1
+    h.free()
+
+
+def test_solve_cgs2_argument_errors(B):
+    c = W.config("2", small=True)
+    A, P = c["A"], c["P"]
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=1e-4, precs=c["precs"])
+    Bm = np.stack([c["b"], c["b"]], axis=1)
+    with pytest.raises(B.BSPAIError, match="nrhs = 1"):
+        B.solve(Ad, _dev(Bm), h, orth="cgs2")
+    with pytest.raises(ValueError):
+        B.solve(Ad, _dev(c["b"]), h, orth="cgs")
+    h.free()
+
+
 # ------------------------------------------------- bucketed A inside GMRES
 
 def _ab_cases():
