@@ -320,6 +320,23 @@ def multi_bench(B, W, torch, np, kw, replays=3):
            "max_eta": max(q["eta"][-1] for q in sts), "stop_reasons": [q["stop_reason"] for q in sts],
            "all_converged": all(q["status"] == 0 for q in sts)}
     plan.free()
+    # the same launch with CGS2 orthogonalisation, its group size tuned for it
+    t0 = time.perf_counter()
+    plan = B.MultiPlan(systems, group_blocks=-1, orth="cgs2", **kw)
+    tune2 = time.perf_counter() - t0
+    plan.launch()
+    plan.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        plan.launch()
+    sts = plan.wait()
+    el = (time.perf_counter() - t0) / replays
+    res["cgs2"] = {"systems_per_s": len(systems) / el, "ms_per_replay": el * 1e3, "group_blocks": plan.group_blocks,
+                   "autotune_s": tune2,
+                   "its_total": [q["its_total"] for q in sts], "max_relres": max(q["relres"][-1] for q in sts),
+                   "all_converged": all(q["status"] == 0 for q in sts)}
+    plan.free()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for A, b, h in systems:
@@ -330,7 +347,7 @@ def multi_bench(B, W, torch, np, kw, replays=3):
     for _, _, h in systems:
         h.free()
     _log(f"multi-system: {res['systems_per_s']:.2f} systems/s (group {res['group_blocks']}), "
-         f"sequential {res['sequential_systems_per_s']:.2f}")
+         f"CGS2 {res['cgs2']['systems_per_s']:.2f} (group {res['cgs2']['group_blocks']}), sequential {res['sequential_systems_per_s']:.2f}")
     return res
 
 

@@ -147,7 +147,8 @@ typedef struct {
                           (from the second correction on); 0 selects 0.5, a negative value never stops */
     int orth;          /* Arnoldi orthogonalisation: 0 modified Gram-Schmidt (the paper's), 1 classical
                           Gram-Schmidt twice (CGS2: two grid-wide reductions per step instead of j + 1;
-                          gmres_ir_solve / gmres_ir_solve_ab with nrhs = 1 only) */
+                          one right-hand side per system: gmres_ir_solve / gmres_ir_solve_ab with
+                          nrhs = 1, and bspai_multi_plan) */
 } gmres_ir_tol;
 
 typedef struct {

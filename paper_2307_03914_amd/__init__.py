@@ -429,11 +429,13 @@ class MultiPlan:
     (CSRMatrix A, b tensor, Handle M[, x tensor]); b and x are 1-D float64
     CUDA tensors that the plan keeps referenced (each launch reads b and
     writes x).  group_blocks: blocks per group (0 automatic, -1 autotuned by
-    timing one launch per candidate size)."""
+    timing one launch per candidate size).  orth: "mgs" or "cgs2", as in
+    :func:`solve`."""
 
     def __init__(self, systems, u_g: str = "fp32", ur_dd: bool = True, tau: float = 1e-4, tol_rr: float = 1e-10,
                  tol_be: float = 0.0, i_max: int = 20, gmres_max: int = 150, x0_mode: int = 0, trans: bool = False,
-                 group_blocks: int = 0, max_groups: int = 0, stream=None, stag_ratio: Optional[float] = 0.5):
+                 group_blocks: int = 0, max_groups: int = 0, stream=None, stag_ratio: Optional[float] = 0.5,
+                 orth: str = "mgs"):
         self._ptr = None
         self.A, self.b, self.x, self.M = [], [], [], []
         arr = (_System * len(systems))()
@@ -450,8 +452,10 @@ class MultiPlan:
             arr[k].b = b.data_ptr()
             arr[k].x = x.data_ptr()
             arr[k].M = M.ptr
+        if orth not in ("mgs", "cgs2"):
+            raise ValueError("orth must be 'mgs' or 'cgs2'")
         self.tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max),
-                        int(gmres_max), int(x0_mode), int(trans), _stag(stag_ratio))
+                        int(gmres_max), int(x0_mode), int(trans), _stag(stag_ratio), 0 if orth == "mgs" else 1)
         out = _vp()
         _check(_lib.bspai_multi_plan(arr, len(systems), C.byref(self.tol), int(group_blocks), int(max_groups),
                                      C.byref(out), _stream(stream)))

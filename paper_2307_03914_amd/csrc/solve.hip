@@ -40,11 +40,13 @@ struct Grid {
   unsigned *flags;  // [G] epoch reached by each block
   unsigned *abortf; // set when a wait exceeds the spin bound
   double *slots;    // [kNumSlots][kMaxBlocks][kMaxSlotWidth][2] tagged 64-bit words
-  unsigned long long *wide;  // [kNumSlots][kMaxBlocks][kMaxGmres + 1][2] for vector reductions (or null)
+  unsigned long long *wide;  // [kNumSlots][G][kMaxGmres + 1][2] for vector reductions (or null)
   int G;
 };
 
-constexpr size_t kWideBytes = 16 * (size_t)kNumSlots * kMaxBlocks * (kMaxGmres + 1);
+// bytes of the vector-reduction words of a grid of G blocks
+constexpr size_t wide_bytes(int G) { return 16 * (size_t)kNumSlots * G * (kMaxGmres + 1); }
+constexpr size_t kWideBytes = wide_bytes(kMaxBlocks);
 
 template <typename VT>
 struct SolveParams {
@@ -244,7 +246,7 @@ __device__ bool grid_reduce_vec(const Grid &g, unsigned &rtag, int W, const doub
     return true;
   }
   constexpr size_t kStride = kMaxGmres + 1;
-  unsigned long long *set = g.wide + (size_t)(rtag % kNumSlots) * kMaxBlocks * kStride * 2;
+  unsigned long long *set = g.wide + (size_t)(rtag % kNumSlots) * g.G * kStride * 2;
   for (int t = tid; t < W; t += nt) publish_partial(set + ((size_t)bid * kStride + t) * 2, in[t], rtag);
   int tpv = 1;
   while (2 * tpv * W <= nt && 2 * tpv <= g.G) tpv *= 2;
@@ -933,7 +935,7 @@ static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double 
   BSPAI_HIP(hipMemsetAsync(p.grid.abortf, 0, 4, s));
   // tags restart at 1 every launch: clear the exchange words of the last one
   BSPAI_HIP(hipMemsetAsync(p.grid.slots, 0, kSlotBytes, s));
-  if (p.grid.wide) BSPAI_HIP(hipMemsetAsync(p.grid.wide, 0, kWideBytes, s));
+  if (p.grid.wide) BSPAI_HIP(hipMemsetAsync(p.grid.wide, 0, wide_bytes(p.grid.G), s));
   BSPAI_HIP(hipMemsetAsync(p.stats, 0, sizeof(gmres_ir_stats), s));
   const size_t lds = solve_lds(m);
   void *fn = pick_single<VT>(wide, ZR, tol->orth != 0);
@@ -996,7 +998,7 @@ struct MultiParams {
   int ngroups;
 };
 
-template <typename VT, typename PT, int ZR>
+template <typename VT, typename PT, int ZR, bool CGS2>
 __global__ void __launch_bounds__(kSolveThreads) k_gmres_multi(const MultiParams<VT> *__restrict__ mp) {
   extern __shared__ double sm[];
   __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
@@ -1014,7 +1016,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_gmres_multi(const MultiParams
     if (!grid_reduce<1, true>(G, rtag, q, sh, bid)) break;
     const int k = (int)q[0];
     if (k >= count) break;
-    if (!gmres_ir_body<VT, PT, ZR>(mp->sys[mp->order[first + k]], G, bid, epoch, rtag, sm, sh, s_flag)) break;
+    if (!gmres_ir_body<VT, PT, ZR, CGS2>(mp->sys[mp->order[first + k]], G, bid, epoch, rtag, sm, sh, s_flag))
+      break;
   }
   if (bid == 0 && threadIdx.x == 0) {
     unsigned d = atomicAdd(mp->groups_done, 1u);
@@ -1031,24 +1034,29 @@ __global__ void k_multi_clear(unsigned *words, int64_t nwords, unsigned *seq) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *seq += 1u;
 }
 
-template <typename VT>
-static void *pick_multi(bool wide, int ZR) {
+template <typename VT, bool CGS2>
+static void *pick_multi_o(bool wide, int ZR) {
   if (wide) {
     switch (ZR) {
-      case 1: return (void *)k_gmres_multi<VT, double, 1>;
-      case 2: return (void *)k_gmres_multi<VT, double, 2>;
-      case 4: return (void *)k_gmres_multi<VT, double, 4>;
-      case 8: return (void *)k_gmres_multi<VT, double, 8>;
-      default: return (void *)k_gmres_multi<VT, double, 16>;
+      case 1: return (void *)k_gmres_multi<VT, double, 1, CGS2>;
+      case 2: return (void *)k_gmres_multi<VT, double, 2, CGS2>;
+      case 4: return (void *)k_gmres_multi<VT, double, 4, CGS2>;
+      case 8: return (void *)k_gmres_multi<VT, double, 8, CGS2>;
+      default: return (void *)k_gmres_multi<VT, double, 16, CGS2>;
     }
   }
   switch (ZR) {
-    case 1: return (void *)k_gmres_multi<VT, float, 1>;
-    case 2: return (void *)k_gmres_multi<VT, float, 2>;
-    case 4: return (void *)k_gmres_multi<VT, float, 4>;
-    case 8: return (void *)k_gmres_multi<VT, float, 8>;
-    default: return (void *)k_gmres_multi<VT, float, 16>;
+    case 1: return (void *)k_gmres_multi<VT, float, 1, CGS2>;
+    case 2: return (void *)k_gmres_multi<VT, float, 2, CGS2>;
+    case 4: return (void *)k_gmres_multi<VT, float, 4, CGS2>;
+    case 8: return (void *)k_gmres_multi<VT, float, 8, CGS2>;
+    default: return (void *)k_gmres_multi<VT, float, 16, CGS2>;
   }
+}
+
+template <typename VT>
+static void *pick_multi(bool wide, int ZR, bool cgs2) {
+  return cgs2 ? pick_multi_o<VT, true>(wide, ZR) : pick_multi_o<VT, false>(wide, ZR);
 }
 
 }  // namespace bspai
@@ -1134,7 +1142,7 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
       for (int q = 0; q < Mb.nb; q++) wide = wide || Mb.prec[q] == BSPAI_FP64;
     }
     lds = solve_lds(mmax);
-    fn = pick_multi<VT>(wide, ZR);
+    fn = pick_multi<VT>(wide, ZR, tol->orth != 0);
     BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     BSPAI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSolveThreads, lds));
     // every block of the grid must be resident at once (a group waits on its blocks)
@@ -1235,6 +1243,10 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
   const size_t o_stats = take(sizeof(gmres_ir_stats) * nsys);
   const size_t o_flags = take(4 * (size_t)kMaxBlocks * ngroups);
   const size_t o_slots = take(kSlotBytes * ngroups);
+  size_t wide_total = 0;
+  if (tol->orth)
+    for (int g = 0; g < ngroups; g++) wide_total += wide_bytes(csize[gclass[g]]);
+  const size_t o_wide = take(wide_total);
   const size_t state_bytes = off - o_state;
 
   bspai_multi *P = new bspai_multi;
@@ -1271,12 +1283,17 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
   }
   std::vector<Grid> grids(ngroups);
   unsigned *aborts = reinterpret_cast<unsigned *>(mem + o_aborts);
+  size_t wide_off = o_wide;
   for (int g = 0; g < ngroups; g++) {
     grids[g].flags = reinterpret_cast<unsigned *>(mem + o_flags) + (size_t)kMaxBlocks * g;
     grids[g].abortf = aborts + g;
     grids[g].slots = reinterpret_cast<double *>(mem + o_slots + kSlotBytes * g);
-    grids[g].wide = nullptr;  // the multi-system launch runs MGS only
     grids[g].G = csize[gclass[g]];
+    grids[g].wide = nullptr;  // vector-reduction words: CGS2 only
+    if (tol->orth) {
+      grids[g].wide = reinterpret_cast<unsigned long long *>(mem + wide_off);
+      wide_off += wide_bytes(grids[g].G);
+    }
   }
   MultiParams<VT> mp;
   memset(&mp, 0, sizeof(mp));
@@ -1426,7 +1443,6 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
   if (!plan_out) return fail(BSPAI_EINVAL, "bspai_multi_plan: null plan_out");
   *plan_out = nullptr;
   if (!sys || nsys < 1 || !tol) return fail(BSPAI_EINVAL, "bspai_multi_plan: need at least one system and tolerances");
-  if (tol->orth != 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: orth must be 0 (MGS)");
   if (group_blocks < -1 || max_groups < 0) return fail(BSPAI_EINVAL, "bspai_multi_plan: bad group size or count");
   for (int k = 0; k < nsys; k++) {
     int rc = check_system(&sys[k].A, sys[k].b, sys[k].M, tol, sys[k].x, "bspai_multi_plan");

@@ -871,6 +871,39 @@ def test_multi_system_matches_oracle_and_replays(B):
         h.free()
 
 
+@pytest.mark.parametrize("group_blocks", [0, 4])
+def test_multi_system_cgs2_matches_oracle_and_replays(B, group_blocks):
+    """CGS2 in the multi-system launch (size classes, or one group size):
+    each system against the oracle's CGS2 refinement, replays bit-identical."""
+    import torch
+
+    c = W.config("4b", small=True)
+    eps = c["eps"][0]
+    _say("multi-system cgs2", group_blocks)
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
+    systems = _multi_systems(B, c, eps)
+    plan = B.MultiPlan(systems, group_blocks=group_blocks, orth="cgs2", **kw)
+    plan.launch()
+    sts = plan.wait()
+    xs = [x.cpu().numpy().copy() for x in plan.x]
+    for k, sy in enumerate(c["systems"]):
+        A, P, b = sy["A"], sy["P"], sy["b"]
+        M = _spai_oracle(A, P)
+        ref = O.gmres_ir(A, M, O.Bucketed(M, eps, c["precs"]), b, dot64=True, orth="cgs2", **kw)
+        _check_column(sts[k], ref, O.backward_error(A, b, xs[k]))
+    for x in plan.x:
+        x.fill_(float("nan"))
+    plan.launch()
+    plan.launch()
+    assert plan.wait() == sts
+    for k in range(len(xs)):
+        assert np.array_equal(plan.x[k].cpu().numpy(), xs[k])
+    torch.cuda.synchronize()
+    plan.free()
+    for _, _, h in systems:
+        h.free()
+
+
 def test_multi_system_queue_is_deterministic(B):
     """More systems than groups (the queue hands out several systems per
     group): the bits depend on the group size only, not on how many groups
