@@ -164,10 +164,20 @@ __device__ __forceinline__ bool collect_partial(unsigned long long *w, unsigned 
   return true;
 }
 
+// Workgroup barrier that orders LDS only: global loads still in flight (the
+// prefetched basis slice of the next MGS pass) stay in flight across it,
+// where __syncthreads would first wait for every outstanding memory access.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // All-reduction of W values over the grid (sum or max).  Every block combines
 // the same G partials in the same order, so all blocks obtain identical
-// results.  Two workgroup barriers; data other than the scalars is not
-// published (use grid_sync for that).
+// results.  Two LDS-only workgroup barriers: it orders no global memory
+// between the block's threads and publishes nothing but the scalars (use
+// grid_sync or __syncthreads for that).  sh: kWaves W + W + 1 doubles.
 template <int W, bool MAX>
 __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], double *sh, int bid) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -178,7 +188,7 @@ __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], doubl
 #pragma unroll
     for (int c = 0; c < W; c++) sh[wv * W + c] = part[c];
   }
-  __syncthreads();
+  lds_barrier();
   double *res = sh + kWaves * W;
   int bad = 0;
   rtag++;
@@ -219,8 +229,13 @@ __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], doubl
       }
     }
   }
-  bad = __syncthreads_or(bad);
-  if (bad) {
+  // only wave 0 polls: its vote is the block's abort flag
+  if (wv == 0) {
+    const bool any_bad = __any(bad);
+    if (lane == 0) res[W] = any_bad ? 1.0 : 0.0;
+  }
+  lds_barrier();
+  if (res[W] != 0.0) {
     if (threadIdx.x == 0) __hip_atomic_store(g.abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return false;
   }
@@ -684,7 +699,7 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
 template <typename VT, typename PT, int ZR, bool CGS2>
 __global__ void __launch_bounds__(kSolveThreads) k_gmres_ir(const SolveParams<VT> *__restrict__ pp) {
   extern __shared__ double sm[];
-  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth + 1];
   __shared__ int s_flag;
   unsigned epoch = 0, rtag = 0;
   (void)gmres_ir_body<VT, PT, ZR, CGS2>(*pp, pp->grid, blockIdx.x, epoch, rtag, sm, sh, s_flag);
@@ -1001,7 +1016,7 @@ struct MultiParams {
 template <typename VT, typename PT, int ZR, bool CGS2>
 __global__ void __launch_bounds__(kSolveThreads) k_gmres_multi(const MultiParams<VT> *__restrict__ mp) {
   extern __shared__ double sm[];
-  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth + 1];
   __shared__ int s_flag;
   const int group = mp->block_group[blockIdx.x], bid = mp->block_local[blockIdx.x];
   const int cls = mp->group_class[group];
@@ -1353,7 +1368,7 @@ using namespace bspai;
 // Instrumentation: `iters` back-to-back all-reductions of one FP64 value by G
 // blocks of the solver's size, with the solver's own grid_reduce.
 __global__ void __launch_bounds__(kSolveThreads) k_exchange_probe(Grid g, int iters, double *out) {
-  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth];
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth + 1];
   unsigned rtag = 0;
   double acc = 0.0;
   for (int it = 0; it < iters; it++) {
