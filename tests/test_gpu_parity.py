@@ -669,6 +669,28 @@ def test_solve_cgs2_full_size(B):
     h.free()
 
 
+def test_solve_cgs2_at_the_largest_gmres_cap(B):
+    """One correction of 160 Arnoldi steps (the largest cap) on the 256^2
+    system: the vector exchange carries its widest payload (161 values) and
+    both orthogonalisations run to the cap and reach similar residuals."""
+    import torch
+
+    c = W.config("2")
+    A, P, b = c["A"], c["P"], c["b"]
+    _say("solve cgs2 at gmres cap 160")
+    kw = dict(tau=1e-12, tol_rr=1e-14, gmres_max=160, i_max=1)
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=1e-4, precs=c["precs"])
+    x1, st1 = B.solve(Ad, _dev(b), h, orth="cgs2", **kw)
+    x0, st0 = B.solve(Ad, _dev(b), h, **kw)
+    torch.cuda.synchronize()
+    assert st0["its"] == st1["its"] == [160]
+    assert st0["status"] == st1["status"] == B.ENOCONV
+    r0, r1 = st0["relres"][-1], st1["relres"][-1]
+    assert np.isfinite(r1) and r1 <= 10 * r0 and r0 <= 10 * r1
+    h.free()
+
+
 def test_solve_cgs2_argument_errors(B):
     c = W.config("2", small=True)
     A, P = c["A"], c["P"]
@@ -778,6 +800,37 @@ def test_solve_bucketed_a_batched_and_adjoint(B):
     ref = O.gmres_ir(A, M, Mb, g, trans=True, dot64=True, Ab=Ab, **kwt)
     assert abs(st["steps"] - ref["steps"]) <= 1
     assert abs(st["its_total"] - ref["its_total"]) <= max(3, 0.15 * ref["its_total"]), (st["its"], ref["its"])
+    hA.free()
+    h.free()
+
+
+def test_solve_bucketed_a_with_dropped_entries(B):
+    """A bucketed with a DROP bucket: GMRES runs on A without its smallest
+    entries (eq. (nbe2) with u_q = 1), the refinement still uses the exact A;
+    against the oracle's refinement with the same A_b."""
+    import torch
+
+    rng = np.random.default_rng(72)
+    A = W.random_sparse(400, 0.02, rng, dominance=0.8)
+    P = W.pattern_power(A, 2)
+    b = rng.standard_normal(A.n)
+    eps = 3e-3
+    precs = [O.FP32, O.FP16, O.DROP]
+    Ab = O.Bucketed(A, eps, precs)
+    assert Ab.counts[-1] > 0
+    _say("solve bucketed A with drop", list(Ab.counts))
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=40)
+    mprecs = [O.FP64, O.FP32, O.BF16]
+    Ad = B.CSRMatrix.from_host(A)
+    h = B.build(Ad, B.CSRMatrix.from_host(P), eps=1e-4, precs=mprecs)
+    hA = B.bucket_a(Ad, eps, ["fp32", "fp16", "drop"], keep_fp64=True)
+    ex = hA.export()
+    assert np.array_equal(ex["bucket"], Ab.bucket) and np.array_equal(ex["stored"], Ab.mt)
+    x, st = B.solve(Ad, _dev(b), h, A_b=hA, **kw)
+    torch.cuda.synchronize()
+    M = _spai_oracle(A, P)
+    ref = O.gmres_ir(A, M, O.Bucketed(M, 1e-4, mprecs), b, dot64=True, Ab=Ab, **kw)
+    _check_column(st, ref, O.backward_error(A, b, x.cpu().numpy()))
     hA.free()
     h.free()
 
