@@ -33,7 +33,10 @@ constexpr int kMaxSlotWidth = 2;
 // Largest GMRES cap whose packed triangular R and rotation state fit in LDS
 // next to the product tile.
 constexpr int kMaxGmres = 160;
-constexpr int kTileBytes = 49152;  // LDS for the products of one sub-range of rows
+constexpr int kTileBytes = 49152;  // least LDS for the products of one sub-range of rows
+// dynamic LDS of a solver block: all of the CU's 160 KB but 1 KB for the
+// kernels' static arrays; the products take what the GMRES state leaves
+constexpr size_t kLdsBytes = 160 * 1024 - 1024;
 constexpr unsigned kSpinLimit = 1u << 27;  // ~ seconds: a bound, never reached by a healthy run
 
 struct Grid {
@@ -52,7 +55,8 @@ template <typename VT>
 struct SolveParams {
   int n, G, rows_per_block, m_max;
   int lanes_a, lanes_m;
-  int rows_a, rows_m;  // rows per sub-range of the tile products
+  int rows_a, rows_m;  // rows per sub-range of the tile products (up to 2 per thread)
+  int tile_bytes;      // LDS for the products
   const int32_t *a_rp, *a_col;
   const double *a_val;  // A (A^T for trans) in FP64, for the residual and ||A||_inf
   BMat Ap;              // the same matrix with values rounded to u_p = u_g
@@ -371,7 +375,7 @@ __device__ __forceinline__ double residual_row(const int32_t *rp, const int32_t 
 template <typename VT, typename PT, int ZR, bool CGS2 = false>
 __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, unsigned &epoch, unsigned &rtag,
                               double *sm, double *sh, int &s_flag) {
-  constexpr int kCap = kTileBytes / sizeof(PT);
+  const int kCap = p.tile_bytes / (int)sizeof(PT);
   const int m = p.m_max;
   double *cs = sm;            // m
   double *sn = cs + m;        // m
@@ -381,8 +385,15 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
   double *Rp = y + m;         // m (m + 1) / 2, column c holds R(0..c, c) at c (c + 1) / 2
   PT *tprod = reinterpret_cast<PT *>(Rp + (size_t)m * (m + 1) / 2);  // kCap products
   // products of both operators: all buckets of a sub-range of rows at once
-#define SPMV_M(Mat, in, out) bspmv_tile_all<VT, VT, PT>(Mat, in, out, r0, r1, tprod, kCap, p.rows_m)
-#define SPMV_A(Mat, in, out) bspmv_tile_all<VT, VT, PT>(Mat, in, out, r0, r1, tprod, kCap, p.rows_a)
+#define SPMV_ROWS(Mat, in, out, rows)                                                   \
+  do {                                                                                  \
+    if ((rows) > (int)blockDim.x)                                                       \
+      bspmv_tile_all<VT, VT, PT, 2>(Mat, in, out, r0, r1, tprod, kCap, rows);           \
+    else                                                                                \
+      bspmv_tile_all<VT, VT, PT, 1>(Mat, in, out, r0, r1, tprod, kCap, rows);           \
+  } while (0)
+#define SPMV_M(Mat, in, out) SPMV_ROWS(Mat, in, out, p.rows_m)
+#define SPMV_A(Mat, in, out) SPMV_ROWS(Mat, in, out, p.rows_a)
   const int tid = threadIdx.x, nt = blockDim.x;
   const int n = p.n;
   const int r0 = min(n, bid * p.rows_per_block);  // blocks past the last row own none
@@ -415,7 +426,7 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
     }
   } else if (p.x0_mode == 1) {
     bspmv_tile_all<double, double, double>(p.Mb, p.b, p.x, r0, r1, reinterpret_cast<double *>(tprod),
-                                           kTileBytes / 8, p.rows_m / 2 > 0 ? p.rows_m / 2 : 1);
+                                           p.tile_bytes / 8, min(p.rows_m / 2 > 0 ? p.rows_m / 2 : 1, nt));
   } else if (p.x0_mode == 2) {
     OWN_ROWS(k, i) { p.x[i] = 0.0; }
   }
@@ -664,7 +675,7 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
       }
       if (!grid_sync(G, epoch, bid)) return false;
       bspmv_tile_all<double, double, double>(p.Mb, p.dv, p.dv2, r0, r1, reinterpret_cast<double *>(tprod),
-                                             kTileBytes / 8, p.rows_m / 2 > 0 ? p.rows_m / 2 : 1);
+                                             p.tile_bytes / 8, min(p.rows_m / 2 > 0 ? p.rows_m / 2 : 1, nt));
       __syncthreads();
       OWN_ROWS(k, i) {
         double d = p.dv2[i];
@@ -768,7 +779,13 @@ static SysLayout sys_layout(int n, int64_t nnz, int m, bool tr, bool wide_slots 
   return L;
 }
 
-static size_t solve_lds(int m) { return sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2) + kTileBytes; }
+// LDS of the GMRES state (rotations, g, the Hessenberg column, y, packed R)
+constexpr size_t solve_head(int m) { return sizeof(double) * ((size_t)5 * m + 2 + (size_t)m * (m + 1) / 2); }
+// the products get the rest of kLdsBytes, so every block takes kLdsBytes
+// whatever m is (systems of different m share one multi-system launch)
+constexpr size_t tile_bytes(int m) { return (kLdsBytes - solve_head(m)) / 256 * 256; }
+static_assert(tile_bytes(kMaxGmres) >= kTileBytes, "GMRES state leaves too little LDS for the products");
+static size_t solve_lds(int) { return kLdsBytes; }
 
 // Parameters of one system whose workspace starts at `base` (rows split into
 // blocks of rpb rows): A rounded to u_g, A^T and its copy for trans; with Ab
@@ -857,10 +874,16 @@ static int sys_setup(const bspai_csr *A, const bspai_handle *Ab, const double *b
   for (int k = 0; k < p.Mb.nb; k++) wide = wide || p.Mb.prec[k] == BSPAI_FP64;
   for (int k = 0; k < p.Ap.nb; k++) wide = wide || p.Ap.prec[k] == BSPAI_FP64;
   {
-    const int cap = kTileBytes / (wide ? 8 : 4);
+    p.tile_bytes = (int)tile_bytes(m);
+    const int cap = p.tile_bytes / (wide ? 8 : 4);
+    // sub-ranges of up to two rows per thread for short rows (fewer
+    // dependent rounds: A's 5-point rows on the 256^2 system, 10.9 -> 8.3 us
+    // per product); longer rows keep one row per thread, where the longer
+    // per-thread sums cost more than the saved round (M's 13-entry rows:
+    // 13.6 -> 20.3 us with two)
     auto rows_for_avg = [&](double avg) {
       int r = (int)(cap / (1.25 * std::max(avg, 1.0)));
-      return std::max(1, std::min(kSolveThreads, r));
+      return std::max(1, std::min((avg <= 8.0 ? 2 : 1) * kSolveThreads, r));
     };
     p.rows_a = rows_for_avg((double)p.Ap.nnz / n);
     p.rows_m = rows_for_avg((double)p.Mb.nnz / n);

@@ -703,9 +703,11 @@ __device__ __forceinline__ void bspmv_ell_rows(const BMat &M, const XT *__restri
 // the thread's row are fetched meanwhile, and after one barrier each thread
 // adds its row's products bucket by bucket (CSR order, least to most precise
 // bucket).  Three dependent memory rounds per sub-range whatever the number of
-// buckets.  rows_cap <= blockDim.x (one row per thread).  A sub-range whose
-// entries exceed cap is computed row by row from global memory instead.
-template <typename XT, typename YT, typename PT>
+// buckets.  rows_cap <= RPT * blockDim.x (RPT rows per thread: rows s0 + tid
+// and s0 + tid + blockDim.x, each summed exactly as with one row per thread).
+// A sub-range whose entries exceed cap is computed row by row from global
+// memory instead.
+template <typename XT, typename YT, typename PT, int RPT = 1>
 __device__ void bspmv_tile_all(const BMat &M, const XT *__restrict__ x, YT *__restrict__ y, int r0, int r1,
                                PT *prod, int cap, int rows_cap) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -725,13 +727,16 @@ __device__ void bspmv_tile_all(const BMat &M, const XT *__restrict__ x, YT *__re
       }
     }
     const bool fits = off[nb] <= cap;
-    const int i = s0 + tid;
-    int ra[kMaxBuckets], rb[kMaxBuckets];
+    int ra[RPT][kMaxBuckets], rb[RPT][kMaxBuckets];
 #pragma unroll
-    for (int k = 0; k < kMaxBuckets; k++) {
-      bool ok = k < nb && i < s1;
-      ra[k] = ok ? M.rp[k][i] : 0;
-      rb[k] = ok ? M.rp[k][i + 1] : 0;
+    for (int r = 0; r < RPT; r++) {
+      const int i = s0 + tid + r * nt;
+#pragma unroll
+      for (int k = 0; k < kMaxBuckets; k++) {
+        bool ok = k < nb && i < s1;
+        ra[r][k] = ok ? M.rp[k][i] : 0;
+        rb[r][k] = ok ? M.rp[k][i + 1] : 0;
+      }
     }
     if (fits) {
 #pragma unroll
@@ -762,7 +767,10 @@ __device__ void bspmv_tile_all(const BMat &M, const XT *__restrict__ x, YT *__re
       }
     }
     __syncthreads();
-    if (i < s1) {
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+      const int i = s0 + tid + r * nt;
+      if (i >= s1) continue;
       double total = 0.0;
 #pragma unroll
       for (int k = 0; k < kMaxBuckets; k++) {
@@ -772,22 +780,22 @@ __device__ void bspmv_tile_all(const BMat &M, const XT *__restrict__ x, YT *__re
         if (fits) {
           if (wide) {
             double sum = 0.0;
-            for (int q = ra[k]; q < rb[k]; q++) sum += (double)pk[q];
+            for (int q = ra[r][k]; q < rb[r][k]; q++) sum += (double)pk[q];
             total += sum * M.scale[k];
           } else {
             float sum = 0.f;
-            for (int q = ra[k]; q < rb[k]; q++) sum += (float)pk[q];
+            for (int q = ra[r][k]; q < rb[r][k]; q++) sum += (float)pk[q];
             total += (double)sum * M.scale[k];
           }
         } else {
           const int32_t *col = M.col[k];
           if (wide) {
             double sum = 0.0;
-            for (int q = ra[k]; q < rb[k]; q++) sum += (double)(value_at<PT>(M, k, q) * (PT)x[col[q]]);
+            for (int q = ra[r][k]; q < rb[r][k]; q++) sum += (double)(value_at<PT>(M, k, q) * (PT)x[col[q]]);
             total += sum * M.scale[k];
           } else {
             float sum = 0.f;
-            for (int q = ra[k]; q < rb[k]; q++) sum += (float)(value_at<PT>(M, k, q) * (PT)x[col[q]]);
+            for (int q = ra[r][k]; q < rb[r][k]; q++) sum += (float)(value_at<PT>(M, k, q) * (PT)x[col[q]]);
             total += (double)sum * M.scale[k];
           }
         }
