@@ -263,6 +263,18 @@ def test_build_low_uf_overflow_and_limits(B):
     assert e.value.code == B.EINVAL and "wavefront" in str(e.value)
     with pytest.raises(ValueError):
         B.build(Ad, None, u_f="bf16")
+    # the adaptive build is FP64 only: a lower u_f is rejected before any work
+    import ctypes
+
+    o = B._opts(True, True, False, "fp16")
+    ad = B._AdOpts(5, 8, 0.4)
+    ids, q = B._prec_ids(["fp32"])
+    out = ctypes.c_void_p()
+    a = Ad._c()
+    steps = np.zeros(n, dtype=np.int32)
+    rc = B._lib.bspai_build_adaptive(ctypes.byref(a), None, ctypes.byref(ad), 1e-4, ids, q, ctypes.byref(o),
+                                     ctypes.byref(out), steps.ctypes.data_as(ctypes.c_void_p), None)
+    assert rc == B.EINVAL and b"u_f" in B._lib.bspai_last_error()
 
 
 def test_build_low_uf_full_size_sampled_rows(B):
