@@ -181,9 +181,11 @@ __device__ __forceinline__ void lds_barrier() {
 // the same G partials in the same order, so all blocks obtain identical
 // results.  Two LDS-only workgroup barriers: it orders no global memory
 // between the block's threads and publishes nothing but the scalars (use
-// grid_sync or __syncthreads for that).  sh: kWaves W + W + 1 doubles.
+// grid_sync or __syncthreads for that).  sh: kWaves kMaxSlotWidth +
+// kMaxSlotWidth + 1 doubles.
 template <int W, bool MAX>
 __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], double *sh, int bid) {
+  static_assert(W >= 1 && W <= kMaxSlotWidth, "grid_reduce handles 1..kMaxSlotWidth values");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double part[W];
 #pragma unroll
@@ -193,7 +195,10 @@ __device__ bool grid_reduce(const Grid &g, unsigned &rtag, double (&v)[W], doubl
     for (int c = 0; c < W; c++) sh[wv * W + c] = part[c];
   }
   lds_barrier();
-  double *res = sh + kWaves * W;
+  // results and abort flag at a fixed place past every call's wave partials:
+  // the next call's partials (written before its first barrier, while other
+  // waves may still read these results) never overlap them
+  double *res = sh + kWaves * kMaxSlotWidth;
   int bad = 0;
   rtag++;
   if (g.G == 1) {
