@@ -52,7 +52,9 @@ enum {
     BSPAI_EZEROROW = -4, /* a row of M would be zero: k is not in the shadow of its pattern (Section 4) */
     BSPAI_ERANK = -5,    /* a reduced least-squares problem is rank deficient */
     BSPAI_ENOCONV = -6,  /* i_max refinement steps without meeting a tolerance; x and stats are valid */
-    BSPAI_ENAN = -7      /* a NaN or infinity appeared in the residual */
+    BSPAI_ENAN = -7,     /* a NaN or infinity appeared in the residual */
+    BSPAI_ESTAG = -8     /* the corrections stagnated (stop_reason 3) before tol_rr or tol_be was met;
+                            x and stats are valid, x is the last iterate */
 };
 
 typedef struct {
@@ -155,7 +157,8 @@ typedef struct {
     int steps;       /* GMRES calls (corrections) made */
     int its_total;   /* total GMRES iterations */
     int stop_reason; /* 1 relres, 2 backward error, 3 stagnation, 4 i_max, 5 NaN */
-    int status;      /* status code of this right-hand side */
+    int status;      /* status code of this right-hand side: BSPAI_OK only for stop_reason 1 or 2;
+                        ESTAG for 3, ENOCONV for 4, ENAN for 5 */
     int its[64];     /* GMRES iterations per correction */
     double eta[65];  /* normwise backward error before each correction and at the end */
     double relres[65];
@@ -178,8 +181,10 @@ typedef struct {
  *   own tests (a finished column takes no further corrections).  Needs
  *   device workspace of about (gmres_max + 5) n nrhs values of u_g.
  *   M: handle from bspai_build / bspai_import (keep_fp64_M for x0_mode 0,
- *   build_T for trans).  Synchronises `stream`; returns ENOCONV / ENAN when
- *   some right-hand side ends that way (x is still written).
+ *   build_T for trans).  Synchronises `stream`.  Returns BSPAI_OK only when
+ *   every right-hand side met tol_rr or tol_be; otherwise the worst of ENAN,
+ *   ENOCONV (i_max reached) and ESTAG (stagnated first), in that order, with
+ *   x and the stats still written.
  */
 int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
                    double *x, int nrhs, gmres_ir_stats *st_host, void *stream);
@@ -218,7 +223,9 @@ int gmres_ir_solve_ab(const bspai_csr *A, const bspai_handle *A_b, const double 
  *   not fit joining the next larger one.
  *   group_blocks = -1: autotune, i.e. plan size classes and one group size
  *   (the smallest above and its doublings up to 256), run each once, timed
- *   with HIP events, and keep the fastest (this writes every x_k).
+ *   with HIP events, and keep the fastest (this writes every x_k; with
+ *   x0_mode 3 each x_k is saved first and holds the caller's x_0 again when
+ *   the call returns).
  *   max_groups (0: no limit) caps the number of groups.
  *   The launch is captured once into a HIP graph.  Synchronises `stream`.
  *   Results do not depend on which group takes a system, so replays with the
@@ -229,7 +236,8 @@ int gmres_ir_solve_ab(const bspai_csr *A, const bspai_handle *A_b, const double 
  * bspai_multi_poll -- 1 when the last launch has finished (reads one word of
  *   host memory that the kernel writes when its last group leaves), else 0.
  * bspai_multi_wait -- synchronise `stream`, copy the nsys stats to st_host (or
- *   skip if NULL); ENOCONV / ENAN when some system ends that way.
+ *   skip if NULL); ENAN, ENOCONV or ESTAG (worst first, as for
+ *   gmres_ir_solve) when some system met neither tolerance.
  * bspai_multi_free -- release the plan (NULL is ignored); waits for the device.
  */
 typedef struct {
@@ -363,6 +371,13 @@ double bspai_last_solve_kernel_ms(void);
  */
 int bspai_exchange_latency(int G, int iters, double *us_out, void *stream);
 int bspai_solve_blocks(int n);
+
+/* bspai_release_workspace -- free the single-system solver's grow-only
+ * device workspace (the Krylov basis and vectors that gmres_ir_solve with
+ * nrhs = 1 keeps between calls); the next solve allocates it again.  Waits
+ * for the workspace's device.  For callers that tear down the HIP runtime
+ * themselves: call it before the runtime goes away. */
+int bspai_release_workspace(void);
 
 /* bspai_free -- release a handle (NULL is ignored).  Waits for the device. */
 void bspai_free(bspai_handle *M);

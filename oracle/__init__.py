@@ -41,7 +41,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "liboracle.so")
 
 FP64, FP32, FP16, BF16, FP8, DROP = 0, 1, 2, 3, 4, 5
-OK, EINVAL, ENOMEM, EZEROROW, ERANK, ENOCONV, ENAN = 0, -1, -2, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EZEROROW, ERANK, ENOCONV, ENAN, ESTAG = 0, -1, -2, -4, -5, -6, -7, -8
 
 _lib = None
 
@@ -410,6 +410,19 @@ def gmres_ir(A, M, Mb: Bucketed, b, ug: int = FP32, up: int = FP32, ur_dd: bool 
     steps = st.steps
     return dict(status=status, x=x, steps=steps, its=list(st.its[:steps]), its_total=st.its_total,
                 eta=list(st.eta[: steps + 1]), relres=list(st.relres[: steps + 1]), stop_reason=st.stop_reason)
+
+
+def gradient_direct(A, x, g) -> Dict:
+    """The adjoint gradient by its plain definition: lambda solves
+    A^T lambda = g, here by a sparse LU factorisation (a library step, FP64),
+    then dL/db = lambda and dL/da_ij = -lambda_i x_j.  The reference for
+    systems too large for the iterative oracle to finish in seconds; the
+    preconditioner only changes how lambda is found, not lambda."""
+    import scipy.sparse.linalg as spla
+
+    lam = spla.splu(A.to_scipy().T.tocsc()).solve(np.asarray(g, dtype=np.float64))
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    return dict(grad_b=lam, grad_vals=-lam[rows] * np.asarray(x)[A.col])
 
 
 def gradient(A, M, Mb: Bucketed, x, g, **kw) -> Dict:

@@ -32,7 +32,7 @@
 enum { OP_FP64 = 0, OP_FP32 = 1, OP_FP16 = 2, OP_BF16 = 3, OP_FP8 = 4, OP_DROP = 5 };
 enum {
     ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EZEROROW = -4,
-    ORC_ERANK = -5, ORC_ENOCONV = -6, ORC_ENAN = -7
+    ORC_ERANK = -5, ORC_ENOCONV = -6, ORC_ENAN = -7, ORC_ESTAG = -8
 };
 
 int orc_num_threads(int req) {
@@ -1004,7 +1004,7 @@ int orc_gmres_ir(int n, const int *rp, const int *ci, const double *v,
         if (!isfinite(nr)) { status = ORC_ENAN; st->stop_reason = 5; break; }
         if (rho <= o->tol_rr) { st->stop_reason = 1; break; }
         if (eta <= o->tol_be) { st->stop_reason = 2; break; }
-        if (stagnated) { st->stop_reason = 3; break; }
+        if (stagnated) { status = ORC_ESTAG; st->stop_reason = 3; break; }
         if (i >= o->i_max || i >= 64) { status = ORC_ENOCONV; st->stop_reason = 4; break; }
         int its = 0;
         int gs = orc_gmres(n, rp, ci, v, mrp, mci, mt, mb, q, r, d, &its, NULL, &go, NULL, NULL);

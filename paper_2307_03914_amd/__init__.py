@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
@@ -32,9 +33,11 @@ LIBPATH = os.path.join(HERE, "libbspai.so")
 FP64, FP32, FP16, BF16, FP8_E4M3, DROP = 0, 1, 2, 3, 4, 5
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, "fp8": FP8_E4M3, "fp8_e4m3": FP8_E4M3,
         "drop": DROP}
-OK, EINVAL, ENOMEM, EHIP, EZEROROW, ERANK, ENOCONV, ENAN = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EHIP, EZEROROW, ERANK, ENOCONV, ENAN, ESTAG = 0, -1, -2, -3, -4, -5, -6, -7, -8
 _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EZEROROW: "EZEROROW", ERANK: "ERANK",
-             ENOCONV: "ENOCONV", ENAN: "ENAN"}
+             ENOCONV: "ENOCONV", ENAN: "ENAN", ESTAG: "ESTAG"}
+# statuses of a solve that ended without meeting a tolerance but left a valid x
+NOT_CONVERGED = (ENOCONV, ESTAG)
 
 if not os.path.exists(LIBPATH):
     raise ImportError(f"{LIBPATH} is missing: build the HIP library first (__graft_entry__.build())")
@@ -111,6 +114,8 @@ _lib.bspai_multi_wait.argtypes = [_vp, C.POINTER(_Stats), _vp]
 _lib.bspai_multi_group_blocks.argtypes = [_vp]
 _lib.bspai_multi_free.argtypes = [_vp]
 _lib.bspai_multi_free.restype = None
+_lib.bspai_release_workspace.argtypes = []
+_lib.bspai_release_workspace.restype = C.c_int
 for _f in ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres_ir_solve", "gmres_ir_solve_ab",
            "bspai_stats",
            "bspai_export", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll", "bspai_multi_wait",
@@ -122,7 +127,7 @@ SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
            "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
            "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply", "bspai_build_adaptive",
-           "bspai_export_pattern", "gmres_ir_solve_ab")
+           "bspai_export_pattern", "gmres_ir_solve_ab", "bspai_release_workspace")
 
 
 def set_profiling(on: bool) -> None:
@@ -226,6 +231,10 @@ class Handle:
             self._ptr = None
 
     def __del__(self):
+        # during interpreter shutdown the HIP runtime may already be torn
+        # down: free nothing then (call free() before exiting instead)
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
@@ -387,8 +396,10 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
           stag_ratio: Optional[float] = 0.5, A_b: Optional[Handle] = None, orth: str = "mgs"):
     """BSPAI-GMRES-IR.  b: [n] or [n, nrhs] (1 <= nrhs <= 64, row-major)
     float64 on the GPU.  Returns (x, stats): one stats dict for a 1-D b, a
-    list of them (one per column) for a 2-D b.  ENOCONV is reported in the
-    stats (status) unless raise_noconv.  stag_ratio: stop when a correction's
+    list of them (one per column) for a 2-D b.  A solve that met neither
+    tolerance (ENOCONV: i_max reached; ESTAG: the corrections stagnated
+    first) is reported in the stats' status unless raise_noconv, which
+    raises BSPAIError instead.  stag_ratio: stop when a correction's
     ||d||/||x|| exceeds stag_ratio times the previous one (None: never).
     A_b: A bucketed (:func:`bucket_a`) for the products inside GMRES
     (``gmres_ir_solve_ab``); None: A rounded to u_g.  orth: "mgs" (the
@@ -410,7 +421,7 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
                int(x0_mode), int(trans), _stag(stag_ratio), 0 if orth == "mgs" else 1)
     st = (_Stats * nrhs)()
     a = A._c()
-    allow = () if raise_noconv else (ENOCONV,)
+    allow = () if raise_noconv else NOT_CONVERGED
     if A_b is None:
         rc = _lib.gmres_ir_solve(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), nrhs, st,
                                  _stream(stream))
@@ -471,7 +482,7 @@ class MultiPlan:
 
     def wait(self, stream=None, raise_noconv: bool = False) -> List[Dict]:
         st = (_Stats * self.nsys)()
-        allow = () if raise_noconv else (ENOCONV,)
+        allow = () if raise_noconv else NOT_CONVERGED
         _check(_lib.bspai_multi_wait(self._ptr, st, _stream(stream)), allow=allow)
         return [_stats_dict(q) for q in st]
 
@@ -481,13 +492,21 @@ class MultiPlan:
             self._ptr = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.free()
         except Exception:
             pass
 
 
+def release_workspace() -> None:
+    """Free the single-system solver's cached device workspace
+    (bspai_release_workspace); the next solve allocates it again."""
+    _check(_lib.bspai_release_workspace())
+
+
 from .autograd import BSPAISolve  # noqa: E402  (needs the names above)
 
-__all__ = ["CSRMatrix", "Handle", "build", "build_adaptive", "import_m", "apply", "apply_T", "solve", "MultiPlan", "BSPAISolve",
-           "BSPAIError", "SYMBOLS", "PREC"]
+__all__ = ["CSRMatrix", "Handle", "build", "build_adaptive", "import_m", "apply", "apply_T", "solve", "MultiPlan",
+           "BSPAISolve", "BSPAIError", "SYMBOLS", "PREC", "release_workspace", "NOT_CONVERGED"]

@@ -15,7 +15,7 @@ from typing import Dict, Optional
 
 import torch
 
-from . import CSRMatrix, Handle, _check, _lib, _stream, solve
+from . import OK, BSPAIError, CSRMatrix, Handle, _check, _lib, _stream, solve
 
 _lib.bspai_grad_vals.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.bspai_grad_vals.restype = C.c_int
@@ -30,6 +30,16 @@ def grad_vals(A: CSRMatrix, lam: torch.Tensor, x: torch.Tensor, stream=None) -> 
     return out
 
 
+def _require_converged(st, what: str) -> None:
+    """A gradient from a solve that met neither tolerance is not the
+    gradient of the solution: raise instead of returning it."""
+    for q in st if isinstance(st, list) else [st]:
+        if q["status"] != OK:
+            raise BSPAIError(q["status"], f"{what} ended without meeting a tolerance (stop_reason "
+                                          f"{q['stop_reason']}, relres {q['relres'][-1]:.3e}, "
+                                          f"eta {q['eta'][-1]:.3e})")
+
+
 class BSPAISolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, a_vals: torch.Tensor, b: torch.Tensor, A_pattern: CSRMatrix, M: Handle,
@@ -37,6 +47,7 @@ class BSPAISolve(torch.autograd.Function):
         opts = dict(opts or {})
         A = CSRMatrix(A_pattern.row_ptr, A_pattern.col, a_vals.detach(), A_pattern.n)
         x, st = solve(A, b.detach().contiguous(), M, **opts)
+        _require_converged(st, "the forward solve")
         ctx.A = A
         ctx.M = M
         ctx.opts = opts
@@ -49,7 +60,12 @@ class BSPAISolve(torch.autograd.Function):
         (x,) = ctx.saved_tensors
         opts = dict(ctx.opts)
         opts["trans"] = True
+        # an output buffer or starting point given for the forward solve is
+        # the saved x itself: it must not receive lambda (with x0_mode 3 the
+        # adjoint then starts from zero)
+        opts.pop("x", None)
         lam, st = solve(ctx.A, g.contiguous().to(torch.float64), ctx.M, **opts)
+        _require_converged(st, "the adjoint solve")
         ctx.adjoint_stats = st
         ga = grad_vals(ctx.A, lam, x) if ctx.needs_input_grad[0] else None
         gb = lam if ctx.needs_input_grad[1] else None

@@ -124,6 +124,13 @@ namespace bspai {
 void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
+// The more severe of two per-right-hand-side solve statuses, in the order
+// ENAN > ENOCONV > ESTAG > OK (a call reports the worst of its columns).
+inline int worse_status(int a, int b) {
+  auto rank = [](int c) { return c == BSPAI_ENAN ? 3 : c == BSPAI_ENOCONV ? 2 : c == BSPAI_ESTAG ? 1 : 0; };
+  return rank(b) > rank(a) ? b : a;
+}
+
 #define BSPAI_HIP(expr)                                                                          \
   do {                                                                                           \
     hipError_t e_ = (expr);                                                                      \

@@ -461,7 +461,7 @@ __device__ bool gmres_ir_body(const SolveParams<VT> &p, const Grid &G, int bid, 
     if (!isfinite(nr) || !isfinite(nx)) { status = BSPAI_ENAN; reason = 5; break; }
     if (rho <= p.tol_rr) { reason = 1; break; }
     if (eta <= p.tol_be) { reason = 2; break; }
-    if (stag) { reason = 3; break; }
+    if (stag) { status = BSPAI_ESTAG; reason = 3; break; }
     if (it >= p.i_max || it >= 64) { status = BSPAI_ENOCONV; reason = 4; break; }
 
     // ---------------- GMRES on M_b A d = M_b r (left) / A^T M_b^T w = r (right)
@@ -924,9 +924,14 @@ static void *pick_single(bool wide, int ZR, bool cgs2) {
   return cgs2 ? pick_single_o<VT, true>(wide, ZR) : pick_single_o<VT, false>(wide, ZR);
 }
 
+// One system, one right-hand side, as one persistent kernel.  The workspace
+// is the library's grow-only block (g_ws) or, when ext_base is given, the
+// caller-side block of ext_cap bytes at that device address (nothing is
+// allocated then, and the solver kernel is not timed).
 template <typename VT>
 static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
-                       const gmres_ir_tol *tol, double *x, gmres_ir_stats *st_host, hipStream_t s) {
+                       const gmres_ir_tol *tol, double *x, gmres_ir_stats *st_host, hipStream_t s,
+                       char *ext_base = nullptr, size_t ext_cap = 0, const char *who = "gmres_ir_solve") {
   const int n = A->n;
   const int64_t nnz = A->nnz;
   int m = std::min(std::max(tol->gmres_max, 1), std::min(n, kMaxGmres));
@@ -947,29 +952,38 @@ static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double 
     rpb = rows_for(n, G);
     zr = (rpb + kSolveThreads - 1) / kSolveThreads;
   }
-  if (zr > 16) return fail(BSPAI_EINVAL, "gmres_ir_solve: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
+  if (zr > 16) return fail(BSPAI_EINVAL, "%s: n = %d exceeds %d rows", who, n, kMaxBlocks * kSolveThreads * 16);
   int ZR = 1;
   while (ZR < zr) ZR <<= 1;
   G = (n + rpb - 1) / rpb;
   if (G < 1) G = 1;
 
   const SysLayout L = sys_layout<VT>(n, nnz, m, tol->trans != 0, tol->orth != 0);
-  std::lock_guard<std::mutex> lock(g_ws.mu);
-  int dev = 0;
-  BSPAI_HIP(hipGetDevice(&dev));
-  if (g_ws.bytes < L.total || g_ws.device != dev) {
-    if (g_ws.ptr) {
-      (void)hipDeviceSynchronize();
-      dfree(g_ws.ptr);
-      g_ws.ptr = nullptr;
-      g_ws.bytes = 0;
+  std::unique_lock<std::mutex> lock(g_ws.mu, std::defer_lock);
+  char *base = ext_base;
+  if (ext_base) {
+    if (L.total > ext_cap)
+      return fail(BSPAI_EINVAL, "%s: n = %d, nnz = %lld, gmres_max %d need %zu bytes of workspace; the limit is %zu",
+                  who, n, (long long)nnz, m, L.total, ext_cap);
+  } else {
+    lock.lock();
+    int dev = 0;
+    BSPAI_HIP(hipGetDevice(&dev));
+    if (g_ws.bytes < L.total || g_ws.device != dev) {
+      if (g_ws.ptr) {
+        (void)hipDeviceSynchronize();
+        dfree(g_ws.ptr);
+        g_ws.ptr = nullptr;
+        g_ws.bytes = 0;
+      }
+      int rc = dalloc(&g_ws.ptr, L.total);
+      if (rc) return rc;
+      g_ws.bytes = L.total;
+      g_ws.device = dev;
     }
-    int rc = dalloc(&g_ws.ptr, L.total);
-    if (rc) return rc;
-    g_ws.bytes = L.total;
-    g_ws.device = dev;
+    base = static_cast<char *>(g_ws.ptr);
   }
-  char *base = static_cast<char *>(g_ws.ptr);
+  const bool prof = g_profile && !ext_base;
   SolveParams<VT> p;
   bool wide = false;
   int rc = sys_setup<VT>(A, Ab, b, M, tol, x, m, G, rpb, base, L, p, wide, s);
@@ -987,30 +1001,34 @@ static int solve_typed(const bspai_csr *A, const bspai_handle *Ab, const double 
   BSPAI_HIP(hipMemcpyAsync(pdev, &p, sizeof(p), hipMemcpyHostToDevice, s));
   void *args[] = {&pdev};
   hipEvent_t ev[2] = {nullptr, nullptr};
-  if (g_profile) {
+  if (prof) {
     BSPAI_HIP(hipEventCreate(&ev[0]));
     BSPAI_HIP(hipEventCreate(&ev[1]));
     BSPAI_HIP(hipEventRecord(ev[0], s));
   }
   BSPAI_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kSolveThreads), args, (unsigned)lds, s));
-  if (g_profile) BSPAI_HIP(hipEventRecord(ev[1], s));
+  if (prof) BSPAI_HIP(hipEventRecord(ev[1], s));
   gmres_ir_stats hs;
   unsigned aborted = 0;
   BSPAI_HIP(hipMemcpyAsync(&hs, p.stats, sizeof(hs), hipMemcpyDeviceToHost, s));
   BSPAI_HIP(hipMemcpyAsync(&aborted, p.grid.abortf, 4, hipMemcpyDeviceToHost, s));
   BSPAI_HIP(hipStreamSynchronize(s));
-  if (g_profile) {
+  if (prof) {
     float ms = 0.f;
     BSPAI_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
     g_last_ms = ms;
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
   }
-  if (aborted) return fail(BSPAI_EHIP, "gmres_ir_solve: grid synchronisation timed out");
+  if (aborted) return fail(BSPAI_EHIP, "%s: grid synchronisation timed out", who);
   if (st_host) *st_host = hs;
   if (hs.status == BSPAI_ENOCONV)
-    return fail(BSPAI_ENOCONV, "gmres_ir_solve: %d refinement steps without meeting a tolerance", hs.steps);
-  if (hs.status == BSPAI_ENAN) return fail(BSPAI_ENAN, "gmres_ir_solve: NaN or infinity in the residual");
+    return fail(BSPAI_ENOCONV, "%s: %d refinement steps without meeting a tolerance", who, hs.steps);
+  if (hs.status == BSPAI_ENAN) return fail(BSPAI_ENAN, "%s: NaN or infinity in the residual", who);
+  if (hs.status == BSPAI_ESTAG)
+    return fail(BSPAI_ESTAG, "%s: corrections stagnated after %d steps before meeting a tolerance "
+                             "(relres %.3e, eta %.3e)", who, hs.steps, hs.relres[hs.steps < 64 ? hs.steps : 64],
+                hs.eta[hs.steps < 64 ? hs.steps : 64]);
   return hs.status;
 }
 
@@ -1509,9 +1527,36 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
   BSPAI_HIP(hipEventCreate(&e0));
   BSPAI_HIP(hipEventCreate(&e1));
   int rc = BSPAI_OK;
+  // the timed launches write every x_k; with x0_mode 3 x_k is also the
+  // caller's starting point, so it is saved here and put back before each
+  // timed launch and once more at the end
+  double *x0_save = nullptr;
+  std::vector<size_t> x0_off(nsys + 1, 0);
+  for (int k = 0; k < nsys; k++) x0_off[k + 1] = x0_off[k] + (size_t)sys[k].A.n;
+  auto restore_x0 = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nsys && e == hipSuccess; k++)
+      e = hipMemcpyAsync(sys[k].x, x0_save + x0_off[k], 8 * (size_t)sys[k].A.n, hipMemcpyDeviceToDevice, s);
+    return e;
+  };
+  if (tol->x0_mode == 3) {
+    if ((rc = dalloc_t(&x0_save, x0_off[nsys]))) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return rc;
+    }
+    for (int k = 0; k < nsys; k++) {
+      hipError_t e = hipMemcpyAsync(x0_save + x0_off[k], sys[k].x, 8 * (size_t)sys[k].A.n, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) {
+        rc = fail(BSPAI_EHIP, "bspai_multi_plan: saving x_0: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+  }
   std::vector<int> cands = {0};
   for (int gb = gmin; gb <= kMaxBlocks; gb *= 2) cands.push_back(gb);
   for (int gb : cands) {
+    if (rc) break;
     bspai_multi *cand = nullptr;
     rc = plan(gb, &cand);
     if (rc) {
@@ -1522,7 +1567,8 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
       break;
     }
     float ms = 0.f;
-    hipError_t e = hipEventRecord(e0, s);
+    hipError_t e = x0_save ? restore_x0() : hipSuccess;
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
     if (e == hipSuccess) e = hipGraphLaunch(cand->exec, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1543,6 +1589,12 @@ extern "C" int bspai_multi_plan(const bspai_system *sys, int nsys, const gmres_i
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (x0_save) {
+    hipError_t e = restore_x0();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dfree(x0_save);
+    if (e != hipSuccess && !rc) rc = fail(BSPAI_EHIP, "bspai_multi_plan: restoring x_0: %s", hipGetErrorString(e));
+  }
   if (rc) {
     multi_release(best);
     return rc;
@@ -1583,16 +1635,32 @@ extern "C" int bspai_multi_wait(bspai_multi *plan, gmres_ir_stats *st_host, void
   for (unsigned a : ab)
     if (a) return fail(BSPAI_EHIP, "bspai_multi_wait: a group's synchronisation timed out");
   int worst = BSPAI_OK;
-  for (const auto &q : st) {
-    if (q.status == BSPAI_ENAN) worst = BSPAI_ENAN;
-    else if (q.status == BSPAI_ENOCONV && worst == BSPAI_OK) worst = BSPAI_ENOCONV;
-  }
+  for (const auto &q : st) worst = worse_status(worst, q.status);
   if (worst == BSPAI_ENOCONV) return fail(BSPAI_ENOCONV, "bspai_multi_wait: some system reached i_max");
+  if (worst == BSPAI_ESTAG)
+    return fail(BSPAI_ESTAG, "bspai_multi_wait: some system stagnated before meeting a tolerance");
   if (worst == BSPAI_ENAN) return fail(BSPAI_ENAN, "bspai_multi_wait: NaN or infinity in a residual");
   return BSPAI_OK;
 }
 
 extern "C" void bspai_multi_free(bspai_multi *plan) { multi_release(plan); }
+
+extern "C" int bspai_release_workspace(void) {
+  std::lock_guard<std::mutex> lock(g_ws.mu);
+  if (!g_ws.ptr) return BSPAI_OK;
+  int cur = 0;
+  const int dev = g_ws.device;
+  BSPAI_HIP(hipGetDevice(&cur));
+  if (cur != dev) BSPAI_HIP(hipSetDevice(dev));
+  hipError_t e = hipDeviceSynchronize();
+  dfree(g_ws.ptr);
+  g_ws.ptr = nullptr;
+  g_ws.bytes = 0;
+  g_ws.device = -1;
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return fail(BSPAI_EHIP, "bspai_release_workspace: %s", hipGetErrorString(e));
+  return BSPAI_OK;
+}
 
 static int solve_entry(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
                        const gmres_ir_tol *tol, double *x, int nrhs, gmres_ir_stats *st_host, void *stream,

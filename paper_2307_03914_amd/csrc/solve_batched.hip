@@ -539,8 +539,10 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
         status[c] = BSPAI_ENAN;
       } else if (rho <= tol->tol_rr) reason = 1;
       else if (eta <= tol->tol_be) reason = 2;
-      else if (stag[c]) reason = 3;
-      else if (it >= tol->i_max || it >= 64) {
+      else if (stag[c]) {
+        reason = 3;
+        status[c] = BSPAI_ESTAG;
+      } else if (it >= tol->i_max || it >= 64) {
         reason = 4;
         status[c] = BSPAI_ENOCONV;
       }
@@ -654,12 +656,13 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   int worst = BSPAI_OK;
   for (int c = 0; c < R; c++) {
     st[c].status = status[c];
-    if (status[c] == BSPAI_ENAN) worst = BSPAI_ENAN;
-    else if (status[c] == BSPAI_ENOCONV && worst == BSPAI_OK) worst = BSPAI_ENOCONV;
+    worst = worse_status(worst, status[c]);
   }
   if (st_host) memcpy(st_host, st.data(), sizeof(gmres_ir_stats) * R);
   BSPAI_HIP(hipStreamSynchronize(s));
   if (worst == BSPAI_ENOCONV) return fail(BSPAI_ENOCONV, "gmres_ir_solve: some right-hand side reached i_max");
+  if (worst == BSPAI_ESTAG)
+    return fail(BSPAI_ESTAG, "gmres_ir_solve: some right-hand side stagnated before meeting a tolerance");
   if (worst == BSPAI_ENAN) return fail(BSPAI_ENAN, "gmres_ir_solve: NaN or infinity in a residual");
   return BSPAI_OK;
 }

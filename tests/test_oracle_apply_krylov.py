@@ -89,6 +89,66 @@ def test_normwise_backward_error_bound_of_theorem_31(orc, eps, precs):
         assert enw <= bound, (enw, bound)
 
 
+def _scalar_round(prec):
+    """Rounding to a storage format by a library that is not the oracle:
+    NumPy's float16/float32 casts and torch's bfloat16 and float8_e4m3fn casts
+    (all round to nearest, ties to even); FP64 is the identity."""
+    import torch
+
+    if prec == O.FP64:
+        return lambda v: float(v)
+    if prec == O.FP32:
+        return lambda v: float(np.float32(v))
+    if prec == O.FP16:
+        return lambda v: float(np.float16(v))
+    if prec == O.DROP:
+        return None
+    dt = {O.BF16: torch.bfloat16, O.FP8: torch.float8_e4m3fn}[prec]
+    return lambda v: float(torch.tensor(v, dtype=torch.float64).to(dt).to(torch.float64))
+
+
+@pytest.mark.parametrize("eps,precs", [
+    (1e-3, [O.FP64, O.FP32, O.FP16, O.BF16, O.FP8]),
+    (2.0 ** -24, [O.FP32, O.FP16, O.DROP]),
+    (1e-2, [O.FP32, O.FP16, O.BF16]),
+])
+def test_literal_algorithm3_matches_scalar_arithmetic(orc, eps, precs):
+    """Algorithm 3 as printed, entry by entry: in bucket k every product of
+    a stored value and an entry of x (formed in FP64, as the chop emulation of
+    Section 4 forms it) and every addition to the bucket's partial sum is
+    rounded to u_k; the partials are then added in u_1 from bucket q down to
+    bucket 1.  Recomputed here with NumPy / torch scalar roundings, so a
+    partial kept in the wrong precision or a product left unrounded changes
+    the bits (the order of the final u_1 sum rarely does: those few partials
+    add almost exactly)."""
+    A, M, rng = _random_spai(47, n=90)
+    Mb = O.Bucketed(M, eps, precs)
+    # x spans several binades so that the low formats round (and fp8
+    # underflows) on a good share of the products
+    x = rng.standard_normal(M.n) * 2.0 ** rng.integers(-6, 7, M.n)
+    y = orc.apply_paper(Mb, x)
+    rnd = [_scalar_round(p) for p in precs]
+    nround = 0
+    for i in range(M.n):
+        part = [0.0] * len(precs)
+        for e in range(M.row_ptr[i], M.row_ptr[i + 1]):
+            k = int(Mb.bucket[e])
+            if precs[k] == O.DROP:
+                continue
+            exact = float(Mb.mt[e]) * float(x[M.col[e]])
+            prod = rnd[k](exact)
+            nround += prod != exact
+            part[k] = rnd[k](part[k] + prod)
+        acc = 0.0
+        for k in range(len(precs) - 1, -1, -1):
+            acc = rnd[0](acc + part[k])
+        assert y[i] == acc, (i, y[i], acc)
+    assert nround > M.n  # the roundings are exercised, not vacuous
+    # and it is not the decoupled product: that one keeps the low partials
+    # in FP32/FP64
+    assert not np.array_equal(y, orc.apply(Mb, x))
+
+
 def test_tight_per_row_error_bound(orc):
     # |y_i - (M x)_i| <= sum_k u_k sum_{B_ik} max(|m_ij|, 2^emin_k s_k) |x_j| + gamma sum |mt_ij x_j|
     A, M, rng = _random_spai(43, n=70)
@@ -286,7 +346,7 @@ def test_ir_reaches_fp64_backward_error(orc):
     xt = rng.standard_normal(200)
     b = W.matvec_extended(A, xt)
     res = orc.gmres_ir(A, M, Mb, b, tol_rr=0.0, tol_be=0.0, i_max=12)
-    assert res["stop_reason"] in (3, 4)
+    assert res["stop_reason"] in (3, 4) and res["status"] in (O.ESTAG, O.ENOCONV)
     assert res["eta"][-1] <= 4 * U64
     D = A.dense()
     kappa = np.linalg.cond(D, np.inf)
@@ -303,6 +363,8 @@ def test_ir_stagnation_ratio(orc):
     runs = {r: orc.gmres_ir(A, M, Mb, b, tol_rr=0.0, tol_be=0.0, i_max=12, stag_ratio=r)
             for r in (0.5, 0.999, None)}
     assert runs[0.5]["stop_reason"] == 3 and runs[0.5]["steps"] < 12
+    # no tolerance was met: a stagnation stop is not reported as success
+    assert runs[0.5]["status"] == O.ESTAG
     assert runs[0.999]["steps"] >= runs[0.5]["steps"]
     assert runs[None]["stop_reason"] == 4 and runs[None]["steps"] == 12 and runs[None]["status"] == O.ENOCONV
     # the corrections before the stop are the same in every run
@@ -330,6 +392,33 @@ def test_ir_reports_noconvergence(orc):
     Mb = O.Bucketed(M, 2.0 ** -53, [O.FP64])
     res = orc.gmres_ir(A, M, Mb, c["b"], tol_rr=1e-30, i_max=1)
     assert res["status"] == O.ENOCONV and res["steps"] == 1
+
+
+def test_direct_gradient_matches_dense_and_iterative_adjoint(orc):
+    """The sparse-LU gradient equals a dense solve of A^T lambda = g and the
+    refinement-based gradient, and dL/da_ij = -lambda_i x_j is checked
+    against a finite difference in one entry of A."""
+    A, M, rng = _random_spai(55, n=50)
+    Mb = O.Bucketed(M, 1e-3, [O.FP64, O.FP32, O.FP16, O.BF16, O.FP8])
+    b = rng.standard_normal(50)
+    D = A.dense()
+    x = np.linalg.solve(D, b)
+    g = rng.standard_normal(50)
+    out = orc.gradient_direct(A, x, g)
+    lam = np.linalg.solve(D.T, g)
+    assert np.allclose(out["grad_b"], lam, rtol=1e-12, atol=1e-14 * np.abs(lam).max())
+    it = orc.gradient(A, M, Mb, x, g, tol_rr=1e-14, i_max=20)
+    assert np.abs(out["grad_vals"] - it["grad_vals"]).max() <= 1e-9 * np.abs(it["grad_vals"]).max()
+    # d(g . x)/d a_e for the entry e = (i, j): perturb it alone
+    e = int(np.argmax(np.abs(out["grad_vals"])))
+    i = int(np.searchsorted(A.row_ptr, e, side="right") - 1)
+    j = int(A.col[e])
+    h = 1e-6 * abs(D[i, j])
+    Dp, Dm = D.copy(), D.copy()
+    Dp[i, j] += h
+    Dm[i, j] -= h
+    fd = (g @ np.linalg.solve(Dp, b) - g @ np.linalg.solve(Dm, b)) / (2 * h)
+    assert abs(fd - out["grad_vals"][e]) <= 1e-6 * abs(fd)
 
 
 def test_gradient_matches_dense_adjoint(orc):
