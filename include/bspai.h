@@ -190,6 +190,27 @@ int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_handle *M, c
                    double *x, int nrhs, gmres_ir_stats *st_host, void *stream);
 
 /*
+ * gmres_ir_solve_noalloc -- gmres_ir_solve for one right-hand side (nrhs = 1)
+ * that allocates nothing.  For callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments (b, x: device FP64 [n]; st_host: one stats
+ * struct or NULL), same kernels, results and errors as gmres_ir_solve with
+ * nrhs = 1 and the same row split (bit-identical x and stats).  The solver's
+ * workspace (Krylov basis, vectors, A rounded to u_g, exchange words) lives
+ * in a 64 MiB array of device memory that the library holds on every GPU it
+ * runs on until the process ends; EINVAL when the system needs more (about
+ * 4 (gmres_max + 5) n + 8 nnz bytes in FP32 working precision: n = 65,536
+ * with gmres_max 150 takes 44 MB) and for trans = 1 (the transposed solve
+ * forms A^T in temporary storage).  Calls on one GPU share that array: calls
+ * that overlap on one GPU (two streams, two threads) race and must not be
+ * issued.  Every word that must start at zero is cleared by each call.  No
+ * solver kernel timing (bspai_set_profiling is ignored).  Synchronises
+ * `stream`.
+ */
+int gmres_ir_solve_noalloc(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
+                           double *x, gmres_ir_stats *st_host, void *stream);
+
+/*
  * gmres_ir_solve_ab -- gmres_ir_solve with A bucketed inside GMRES too
  * (Section 3, eqs. (nbe2) and (fe2)): every Krylov product with A (A^T for
  * trans) is the bucketed product of A_b (A_b^T), computed as bspai_apply

@@ -127,7 +127,7 @@ SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
            "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
            "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply", "bspai_build_adaptive",
-           "bspai_export_pattern", "gmres_ir_solve_ab", "bspai_release_workspace")
+           "bspai_export_pattern", "gmres_ir_solve_ab", "bspai_release_workspace", "gmres_ir_solve_noalloc")
 
 
 def set_profiling(on: bool) -> None:
@@ -434,6 +434,34 @@ def solve(A: CSRMatrix, b: torch.Tensor, h: Handle, u_g: str = "fp32", ur_dd: bo
     return x, [_stats_dict(q) for q in st]
 
 
+_lib.gmres_ir_solve_noalloc.argtypes = [C.POINTER(_CSR), _vp, _vp, C.POINTER(_Tol), _vp, C.POINTER(_Stats), _vp]
+_lib.gmres_ir_solve_noalloc.restype = C.c_int
+
+
+def solve_noalloc(A: CSRMatrix, b: torch.Tensor, h: Handle, x: torch.Tensor, u_g: str = "fp32", ur_dd: bool = True,
+                  tau: float = 1e-4, tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20,
+                  gmres_max: int = 150, x0_mode: int = 0, stream=None, raise_noconv: bool = False,
+                  stag_ratio: Optional[float] = 0.5, orth: str = "mgs") -> Dict:
+    """gmres_ir_solve_noalloc: one right-hand side, workspace in the library's
+    static device scratch (nothing allocated by the library).  b, x: 1-D
+    float64 CUDA tensors of length n; x is written (and read for x0_mode 3).
+    Returns the stats dict."""
+    if b.dtype != torch.float64 or not b.is_cuda or b.dim() != 1 or not b.is_contiguous():
+        raise ValueError("b must be a contiguous 1-D float64 CUDA tensor")
+    if x.shape != b.shape or x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float64 tensor shaped like b")
+    if orth not in ("mgs", "cgs2"):
+        raise ValueError("orth must be 'mgs' or 'cgs2'")
+    tol = _Tol(PREC[u_g], int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), int(gmres_max),
+               int(x0_mode), 0, _stag(stag_ratio), 0 if orth == "mgs" else 1)
+    st = _Stats()
+    a = A._c()
+    rc = _lib.gmres_ir_solve_noalloc(C.byref(a), b.data_ptr(), h.ptr, C.byref(tol), x.data_ptr(), C.byref(st),
+                                     _stream(stream))
+    _check(rc, allow=() if raise_noconv else NOT_CONVERGED)
+    return _stats_dict(st)
+
+
 class MultiPlan:
     """Independent systems solved in one persistent launch replayed from a
     captured HIP graph (``bspai_multi_*``).  ``systems``: list of
@@ -509,4 +537,4 @@ def release_workspace() -> None:
 from .autograd import BSPAISolve  # noqa: E402  (needs the names above)
 
 __all__ = ["CSRMatrix", "Handle", "build", "build_adaptive", "import_m", "apply", "apply_T", "solve", "MultiPlan",
-           "BSPAISolve", "BSPAIError", "SYMBOLS", "PREC", "release_workspace", "NOT_CONVERGED"]
+           "BSPAISolve", "BSPAIError", "SYMBOLS", "PREC", "release_workspace", "NOT_CONVERGED", "solve_noalloc"]

@@ -1689,6 +1689,48 @@ extern "C" int gmres_ir_solve(const bspai_csr *A, const double *b, const bspai_h
   return solve_entry(A, nullptr, b, M, tol, x, nrhs, st_host, stream, "gmres_ir_solve");
 }
 
+// ---------------------------------------------- solve without allocation
+// Workspace of gmres_ir_solve_noalloc: a file-scope device array.  Every GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses the array's name (a host-side stand-in): the device address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and only that address is passed to kernels and copies.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxScratchDevices];
+
+static int scratch_address(char **out, const char *who) {
+  int dev = 0;
+  BSPAI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(BSPAI_EINVAL, "%s: device %d is out of range", who, dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BSPAI_EHIP, "%s: device address of the scratch array: %s", who, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return BSPAI_OK;
+}
+
+extern "C" int gmres_ir_solve_noalloc(const bspai_csr *A, const double *b, const bspai_handle *M,
+                                      const gmres_ir_tol *tol, double *x, gmres_ir_stats *st_host, void *stream) {
+  const char *who = "gmres_ir_solve_noalloc";
+  int rc = check_system(A, b, M, tol, x, who);
+  if (rc) return rc;
+  if (tol->trans)
+    return fail(BSPAI_EINVAL, "%s: the transposed solve forms A^T in temporary storage; use gmres_ir_solve", who);
+  char *base = nullptr;
+  if ((rc = scratch_address(&base, who))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (tol->u_g == BSPAI_FP64) return solve_typed<double>(A, nullptr, b, M, tol, x, st_host, s, base, kScratchBytes, who);
+  return solve_typed<float>(A, nullptr, b, M, tol, x, st_host, s, base, kScratchBytes, who);
+}
+
 extern "C" int gmres_ir_solve_ab(const bspai_csr *A, const bspai_handle *A_b, const double *b, const bspai_handle *M,
                                  const gmres_ir_tol *tol, double *x, int nrhs, gmres_ir_stats *st_host, void *stream) {
   if (!A_b) return fail(BSPAI_EINVAL, "gmres_ir_solve_ab: null A_b");
