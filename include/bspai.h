@@ -381,6 +381,30 @@ int bspai_grad_vals(const bspai_pattern *A, const double *lam, const double *x, 
  */
 void bspai_set_profiling(int on);
 double bspai_last_solve_kernel_ms(void);
+/* bspai_batched_mgs_profile -- with profiling on, gmres_ir_solve with several
+ * right-hand sides times each launch of its one-launch MGS kernel (see
+ * bspai_set_batch_mode) with HIP events on its stream; this returns the
+ * totals since the last reset: milliseconds, launches and algorithmic bytes
+ * ((j + 3) n c values of u_g for step j of a c-column group: v_0..v_j and z
+ * read, v_{j+1} written).  Any pointer may be NULL; reset clears them. */
+void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes);
+
+/*
+ * bspai_set_batch_mode -- how gmres_ir_solve runs nrhs > 1 columns.
+ *   1: all columns together; each MGS pass of an Arnoldi step is one kernel
+ *      over the n x nrhs vectors (z read and written once per pass).
+ *   2: consecutive groups of 16 bytes of u_g per row (4 columns in FP32, 2 in
+ *      FP64; a trailing group of one more or fewer columns runs as in mode 1),
+ *      each refined on its own; the Arnoldi step's whole MGS is one
+ *      cooperative kernel that keeps the group's z in registers and reads
+ *      each basis vector once (n <= 2,097,152).
+ *   0 (default): mode 2 when it applies and n nrhs values of u_g fill at
+ *      least 64 MiB (there the passes are bound by bytes moved), else mode 1.
+ * Both modes compute the same arithmetic per column (the same MGS passes,
+ * FP64 partial sums) and differ only in the order of the partial sums.
+ * Process-wide setting; EINVAL for another value.
+ */
+int bspai_set_batch_mode(int mode);
 
 /*
  * bspai_exchange_latency -- the latency floor of the persistent solver: runs
@@ -391,6 +415,14 @@ double bspai_last_solve_kernel_ms(void);
  *   with MGS (orth = 0, one right-hand side).
  */
 int bspai_exchange_latency(int G, int iters, double *us_out, void *stream);
+/* bspai_exchange_latency_placed -- the same measurement with the solver's LDS
+ * footprint (one block per compute unit) and a placement: one_xcd = 0 runs G
+ * blocks as the dispatcher spreads them over the XCDs; one_xcd = 1 launches
+ * 8 G blocks (G <= 32), each reads its XCD from the XCC_ID hardware register,
+ * and the first G on one XCD do the exchanges.  xcd_out: NULL or a host array
+ * of G ints that receives the XCD of each participating block.  EHIP when no
+ * XCD holds G blocks.  Synchronises `stream`. */
+int bspai_exchange_latency_placed(int G, int iters, int one_xcd, double *us_out, int *xcd_out, void *stream);
 int bspai_solve_blocks(int n);
 
 /* bspai_release_workspace -- free the single-system solver's grow-only

@@ -386,20 +386,23 @@ def gmres(A, Mb: Bucketed, r, tau: float = 1e-4, ug: int = FP32, up: int = FP32,
 def gmres_ir(A, M, Mb: Bucketed, b, ug: int = FP32, up: int = FP32, ur_dd: bool = True, tau: float = 1e-4,
              tol_rr: float = 1e-10, tol_be: float = 0.0, i_max: int = 20, gmres_max: Optional[int] = None,
              x0_mode: int = 0, trans: bool = False, dot64: bool = False, stag_ratio: Optional[float] = 0.5,
-             Ab: Optional["Bucketed"] = None, orth: str = "mgs") -> Dict:
+             Ab: Optional["Bucketed"] = None, orth: str = "mgs", x0=None) -> Dict:
     """BSPAI-GMRES-IR (Algorithm 4).  M: FP64 SPAI as workloads.CSR (for x_0).
     dot64 as in :func:`gmres`; stag_ratio None: no stagnation stop; Ab: A
     bucketed (Bucketed of A) to apply A inside GMRES as well (eqs. (nbe2),
     (fe2)); None: A rounded to u_p.  orth: Gram-Schmidt of GMRES ("mgs" or
-    "cgs2")."""
+    "cgs2").  x0: the starting vector for x0_mode 3 (Algorithm 4's x_0 given by
+    the caller)."""
     n = A.n
+    if (x0 is not None) != (x0_mode == 3):
+        raise ValueError("x0 is given exactly when x0_mode is 3")
     gm = min(n, gmres_max if gmres_max is not None else n)
     o = IROpts(ug, up, int(ur_dd), float(tau), float(tol_rr), float(tol_be), int(i_max), gm, int(x0_mode),
                int(trans), int(dot64), -1.0 if stag_ratio is None else float(stag_ratio))
     o.orth = _orth(orth)
     Aop_b = _set_ab(o, Ab, trans)
     st = IRStats()
-    x = np.zeros(n)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     if trans:
         Aop, Fop, Mop = transpose_csr(A), transpose_csr(M), Mb.transpose()
     else:

@@ -936,7 +936,8 @@ int orc_gmres(int n, const int *rp, const int *ci, const double *v,
  * BSPAI-GMRES-IR (Algorithm 4).
  *
  * x_0 = M b with the unbucketed FP64 M (x0_mode 0), with the buckets
- * (x0_mode 1) or x_0 = 0 (x0_mode 2).  Each refinement step: r = b - A x in
+ * (x0_mode 1), x_0 = 0 (x0_mode 2) or the x_0 the caller left in x
+ * (x0_mode 3).  Each refinement step: r = b - A x in
  * u_r (double-double when ur_dd, else FP64), stored FP64; the normwise
  * backward error eta = ||r||_inf / (||A||_inf ||x||_inf + ||b||_inf) and
  * rho = ||r||_inf / ||b||_inf are recorded; then GMRES (orc_gmres) gives d
@@ -987,9 +988,9 @@ int orc_gmres_ir(int n, const int *rp, const int *ci, const double *v,
         orc_spmv(n, frp, fci, fv, OP_FP64, b, x, OP_FP64);
     } else if (o->x0_mode == 1) {
         orc_apply(n, mrp, mci, mt, mb, q, b, x, OP_FP64);
-    } else {
+    } else if (o->x0_mode == 2) {
         for (int i = 0; i < n; i++) x[i] = 0.0;
-    }
+    } /* x0_mode 3: x holds the caller's x_0 */
     orc_gmres_opts go = {o->ug, o->up, o->tau, o->gmres_max, o->trans, o->dot64,
                          o->arp_b, o->aci_b, o->at_b, o->ab_b, o->qa, o->orth};
     int status = ORC_OK, stagnated = 0;

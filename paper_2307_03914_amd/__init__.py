@@ -127,7 +127,8 @@ SYMBOLS = ("bspai_build", "bspai_import", "bspai_apply", "bspai_apply_T", "gmres
            "bspai_last_solve_kernel_ms", "bspai_multi_plan", "bspai_multi_launch", "bspai_multi_poll",
            "bspai_multi_wait", "bspai_multi_free", "bspai_multi_group_blocks", "bspai_exchange_latency",
            "bspai_solve_blocks", "bspai_set_apply_kind", "bspai_tune_apply", "bspai_build_adaptive",
-           "bspai_export_pattern", "gmres_ir_solve_ab", "bspai_release_workspace", "gmres_ir_solve_noalloc")
+           "bspai_export_pattern", "gmres_ir_solve_ab", "bspai_release_workspace", "gmres_ir_solve_noalloc", "bspai_exchange_latency_placed",
+           "bspai_batched_mgs_profile", "bspai_set_batch_mode")
 
 
 def set_profiling(on: bool) -> None:
@@ -143,6 +144,23 @@ def exchange_latency_us(G: int, iters: int = 20000, stream=None) -> float:
     return out.value
 
 
+_lib.bspai_exchange_latency_placed.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), _vp, _vp]
+_lib.bspai_exchange_latency_placed.restype = C.c_int
+
+
+def exchange_latency_placed_us(G: int, one_xcd: bool, iters: int = 20000, stream=None):
+    """(microseconds per all-reduction, XCD of each participating block) for
+    G blocks spread by the dispatcher or kept on one XCD
+    (bspai_exchange_latency_placed)."""
+    import numpy as np
+
+    out = C.c_double(0.0)
+    xcd = np.zeros(G, dtype=np.int32)
+    _check(_lib.bspai_exchange_latency_placed(int(G), int(iters), int(one_xcd), C.byref(out),
+                                              xcd.ctypes.data_as(C.c_void_p), _stream(stream)))
+    return out.value, xcd.tolist()
+
+
 def solve_blocks(n: int) -> int:
     """Blocks of the persistent solver for n rows (bspai_solve_blocks)."""
     return _check_int(_lib.bspai_solve_blocks(int(n)))
@@ -150,6 +168,31 @@ def solve_blocks(n: int) -> int:
 
 def last_solve_kernel_ms() -> float:
     return _lib.bspai_last_solve_kernel_ms()
+
+
+_lib.bspai_batched_mgs_profile.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
+                                           C.POINTER(C.c_double)]
+_lib.bspai_batched_mgs_profile.restype = None
+_lib.bspai_set_batch_mode.argtypes = [C.c_int]
+_lib.bspai_set_batch_mode.restype = C.c_int
+
+
+def batched_mgs_profile(reset: bool = False) -> Dict:
+    """Totals of the one-launch MGS kernel timed while profiling is on
+    (bspai_batched_mgs_profile): ms, launches, algorithmic bytes."""
+    ms, n, by = C.c_double(0), C.c_longlong(0), C.c_double(0)
+    _lib.bspai_batched_mgs_profile(int(reset), C.byref(ms), C.byref(n), C.byref(by))
+    return dict(ms=ms.value, launches=n.value, bytes=by.value)
+
+
+BATCH_AUTO, BATCH_ALL_COLUMNS, BATCH_GROUPS = 0, 1, 2
+
+
+def set_batch_mode(mode: int) -> None:
+    """How solves with several right-hand sides run their columns
+    (bspai_set_batch_mode): 0 automatic, 1 all columns in each pass kernel,
+    2 column groups with the one-launch MGS."""
+    _check(_lib.bspai_set_batch_mode(int(mode)))
 
 
 class BSPAIError(RuntimeError):
@@ -230,10 +273,11 @@ class Handle:
             _lib.bspai_free(self._ptr)
             self._ptr = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # during interpreter shutdown the HIP runtime may already be torn
-        # down: free nothing then (call free() before exiting instead)
-        if sys.is_finalizing():
+        # down: free nothing then (call free() before exiting instead); the
+        # check is bound at definition, as module globals may be gone by then
+        if _finalizing():
             return
         try:
             self.free()
@@ -519,8 +563,8 @@ class MultiPlan:
             _lib.bspai_multi_free(self._ptr)
             self._ptr = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.free()

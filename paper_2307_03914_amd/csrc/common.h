@@ -188,11 +188,38 @@ int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, in
 bool apply_kind_ok(const BMat &M, int kind);
 int apply_kind_resolved(const BMat &M);
 
+// One Arnoldi step's MGS over an n x (16 / sizeof(VT)) row-major column
+// group as one cooperative kernel (solve.hip).  mgs_persist_rpt(n) is 0 when
+// n is too large for it; ws needs mgs_persist_ws_bytes() bytes, the abort
+// flag sits at mgs_persist_abort_offset().
+int mgs_persist_rpt(int n);
+size_t mgs_persist_ws_bytes();
+size_t mgs_persist_abort_offset();
+template <typename VT>
+int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn, void *ws,
+                       hipStream_t s);
+
+// Instrumentation shared by the solvers (solve.hip): the profiling switch
+// (bspai_set_profiling) and the totals of the one-launch MGS kernel.
+bool profiling_on();
+void add_mgs_profile(double ms, double bytes);
+// How the many-right-hand-side solve runs its columns (bspai_set_batch_mode):
+// 0 automatic, 1 every column in each pass kernel, 2 column groups with the
+// one-launch MGS.
+int batch_mode();
+
 // gmres_ir_solve for 2 <= R <= 64 right-hand sides (solve_batched.hip);
 // arguments already validated, m the GMRES cap, Ab the bucketed A used inside
-// GMRES (NULL: A rounded to u_g).
+// GMRES (NULL: A rounded to u_g).  solve_many picks between all columns
+// together (solve_batched with the per-pass kernels) and consecutive groups
+// of 16 / sizeof(VT) columns (solve_batched with mgs1, one MGS launch per
+// Arnoldi step).
+template <typename VT>
+int solve_many(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+               const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s);
 template <typename VT>
 int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
-                  const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s);
+                  const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s,
+                  bool mgs1);
 
 }  // namespace bspai

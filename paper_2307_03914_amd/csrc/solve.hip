@@ -177,6 +177,44 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// XCC_ID hardware register (hwreg 20, bits 3:0): the accelerator complex die
+// (XCD) the wave runs on.
+__device__ __forceinline__ unsigned xcd_id() { return __builtin_amdgcn_s_getreg(6164) & 0xFu; }
+
+// Puts a cooperative grid's work on one XCD.  Every block registers its XCD;
+// once all gridDim.x blocks have registered (a cooperative launch keeps them
+// all resident), the lowest-numbered XCD with at least `want` blocks is
+// chosen and its first `want` arrivals take ranks 0..want-1.  Returns the
+// block's rank, or -1 for a block that is not used (all blocks get -1, and
+// the abort flag is set, when no XCD holds `want` blocks or a wait runs out).
+// reg: 9 words cleared before the launch ([0..7] arrivals per XCD, [8] blocks
+// registered).  One-off cost per launch: one registration round trip.
+__device__ int one_xcd_rank(unsigned *reg, int want, unsigned *abortf) {
+  __shared__ int s_rank;
+  if (threadIdx.x == 0) {
+    const unsigned x = xcd_id() & 7u;
+    const unsigned r = __hip_atomic_fetch_add(&reg[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&reg[8], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0;
+    bool ok = true;
+    while (__hip_atomic_load(&reg[8], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+      if (++spins > kSpinLimit || __hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    int target = -1;
+    if (ok)
+      for (int k = 0; k < 8 && target < 0; k++)
+        if (__hip_atomic_load(&reg[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (unsigned)want) target = k;
+    if (target < 0) __hip_atomic_store(abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_rank = ((int)x == target && r < (unsigned)want) ? (int)r : -1;
+  }
+  __syncthreads();
+  return s_rank;
+}
+
 // All-reduction of W values over the grid (sum or max).  Every block combines
 // the same G partials in the same order, so all blocks obtain identical
 // results.  Two LDS-only workgroup barriers: it orders no global memory
@@ -1407,6 +1445,310 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
   return BSPAI_OK;
 }
 
+// ------------------------------------------------- batched MGS, one launch
+// One Arnoldi step's modified Gram-Schmidt for the C columns of an n x C
+// row-major block of u_g values (16 bytes per row: C = 4 in FP32, 2 in FP64)
+// as one cooperative kernel (used by the many-right-hand-side solve, which
+// runs its columns in such groups).  Grid thread t owns rows t, t + T, ...
+// (RPT of them, T threads in the grid).  Its slice of z stays in registers
+// across the j + 2 passes and its slice of v_{i-1} is kept from the pass
+// before, so each basis vector is read once per step.  Pass i <= j subtracts
+// h_{i-1} v_{i-1} from z (i > 0) and forms the dots with v_i, pass j + 1
+// subtracts h_j v_j and forms ||z||^2; every pass is one grid-wide
+// all-reduction of the C column sums.  Then v_{j+1} = z / ||z|| (0 where
+// ||z|| = 0).  The arithmetic is that of the per-pass kernels (each update
+// one FMA rounded to u_g, products summed in FP64), reduced in a fixed order:
+// per thread over its rows, DPP wave sums, waves in order, blocks in order.
+constexpr int kMgsCols = 4;  // column sums per exchange (FP32: 4, FP64: 2 used)
+
+struct MgsGrid {
+  unsigned long long *slots;  // [kNumSlots][kMaxBlocks][kMgsCols][2] tagged words, cleared per launch
+  unsigned *abortf;
+};
+
+template <typename VT>
+struct BMgsParams {
+  int n, j, m;
+  const VT *z;       // n x C: M_b (A v_j) (or A (M_b v_j)) on entry
+  VT *V;             // v_i at V + i * vstride; v_{j+1} is written
+  int64_t vstride;
+  double *H;         // h_{i,j} of column c at H + (c * m + j) * (m + 1) + i, i <= j + 1
+  double *hn;        // [C]: h_{j+1,j}
+  MgsGrid grid;
+};
+
+template <typename VT>
+struct Row16;
+template <>
+struct Row16<float> {
+  __device__ static void load(const float *p, float (&v)[4]) {
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+  }
+  __device__ static void store(float *p, const float (&v)[4]) {
+    *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+};
+template <>
+struct Row16<double> {
+  __device__ static void load(const double *p, double (&v)[2]) {
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    v[0] = a.x, v[1] = a.y;
+  }
+  __device__ static void store(double *p, const double (&v)[2]) {
+    *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
+  }
+};
+
+// Sum over the grid of the C column values `part` (per thread); every block
+// obtains the same bits.  Wave c < C collects column c: lane l adds the
+// partials of blocks l, l + 64, ... in that order, issuing all of its loads
+// before checking any tag.  Returns false when a wait exceeds the bound or a
+// block aborted.
+template <int C>
+__device__ bool mgs_grid_sum(const MgsGrid &g, unsigned &rtag, double (&part)[C], double *wpart, double *res) {
+  constexpr int K = kMaxBlocks / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, G = gridDim.x;
+#pragma unroll
+  for (int c = 0; c < C; c++) {
+    const double w = wave_sum_dpp(part[c]);
+    if (lane == 0) wpart[wv * C + c] = w;
+  }
+  lds_barrier();
+  rtag++;
+  const unsigned long long tg = tag16(rtag);
+  unsigned long long *set = g.slots + (size_t)(rtag % kNumSlots) * kMaxBlocks * kMgsCols * 2;
+  if (threadIdx.x < C) {
+    double a = wpart[threadIdx.x];
+    for (int k = 1; k < kWaves; k++) a += wpart[k * C + threadIdx.x];
+    publish_partial(set + ((size_t)blockIdx.x * kMgsCols + threadIdx.x) * 2, a, rtag);
+  }
+  int bad = 0;
+  if (wv < C) {
+    unsigned long long a[K], b[K];
+    unsigned spins = 0;
+    for (;;) {
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int blk = lane + 64 * k;
+        if (blk < G) {
+          unsigned long long *w = set + ((size_t)blk * kMgsCols + wv) * 2;
+          a[k] = __hip_atomic_load(&w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          b[k] = __hip_atomic_load(&w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < K; k++)
+        if (lane + 64 * k < G) ok = ok && (a[k] & 0xFFFFull) == tg && (b[k] & 0xFFFFull) == tg;
+      if (ok) break;
+      if (++spins > kSpinLimit || __hip_atomic_load(g.abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        bad = 1;
+        break;
+      }
+    }
+    double s = 0.0;
+    if (!bad) {
+#pragma unroll
+      for (int k = 0; k < K; k++)
+        if (lane + 64 * k < G) s += __longlong_as_double((long long)((a[k] & ~0xFFFFull) | ((b[k] >> 16) & 0xFFFFull)));
+    }
+    s = wave_sum_dpp(s);
+    const bool any_bad = __any(bad);
+    if (lane == 0) {
+      res[wv] = s;
+      res[C + wv] = any_bad ? 1.0 : 0.0;
+    }
+  }
+  lds_barrier();
+  bool fail_any = false;
+#pragma unroll
+  for (int c = 0; c < C; c++) fail_any = fail_any || res[C + c] != 0.0;
+  if (fail_any) {
+    if (threadIdx.x == 0) __hip_atomic_store(g.abortf, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+#pragma unroll
+  for (int c = 0; c < C; c++) part[c] = res[c];
+  return true;
+}
+
+// ZL: z lives in LDS (16 rows per thread: z and the basis slice would not
+// both fit in registers); each thread touches only its own 16-byte entries.
+template <typename VT, int RPT, bool ZL>
+__global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> p) {
+  constexpr int C = 16 / (int)sizeof(VT);
+  extern __shared__ double zdyn[];  // ZL: [RPT][blockDim.x] rows of 16 bytes
+  // per-wave partials, then the column sums and abort votes; two halves so
+  // that one exchange's results are never overwritten by the next one's
+  // partials while slower waves still read them
+  __shared__ double wpart[2][kWaves * C];
+  __shared__ double res[2][2 * C];
+  // rows t0 + r T for r < nv, 16 bytes each: byte offsets fit 32 bits
+  // (n <= 2^21).  Every row slot is loaded unconditionally, from row 0 past
+  // the end, and its values then zeroed, so no old register copy is kept
+  const unsigned T = gridDim.x * blockDim.x;
+  const unsigned t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = p.n, j = p.j;
+  const int nv = t0 < (unsigned)n ? (int)(((unsigned)n - t0 + T - 1) / T) : 0;
+  const unsigned b0 = t0 * 16u, bs = T * 16u;
+  auto row_off = [&](int r) -> unsigned { return r < nv ? b0 + (unsigned)r * bs : 0u; };
+  auto load_rows = [&](const VT *base, VT (&dst)[RPT][C]) {
+    const char *cb = reinterpret_cast<const char *>(base);
+#pragma unroll
+    for (int r = 0; r < RPT; r++) Row16<VT>::load(reinterpret_cast<const VT *>(cb + row_off(r)), dst[r]);
+#pragma unroll
+    for (int r = 0; r < RPT; r++)
+#pragma unroll
+      for (int c = 0; c < C; c++) dst[r][c] = r < nv ? dst[r][c] : (VT)0;
+  };
+  // v: the basis slice, loaded in pass i for its dot and kept for the update
+  // of pass i + 1.  z: in registers, or in LDS for ZL (zr is then the
+  // loading area of one row)
+  VT v[RPT][C];
+  VT zreg[ZL ? 1 : RPT][C];
+  VT *zl = reinterpret_cast<VT *>(zdyn);
+  auto zget = [&](int r, VT (&o)[C]) {
+    if constexpr (ZL) {
+      Row16<VT>::load(zl + ((size_t)r * blockDim.x + threadIdx.x) * C, o);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; c++) o[c] = zreg[r][c];
+    }
+  };
+  auto zput = [&](int r, const VT (&o)[C]) {
+    if constexpr (ZL) {
+      Row16<VT>::store(zl + ((size_t)r * blockDim.x + threadIdx.x) * C, o);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; c++) zreg[r][c] = o[c];
+    }
+  };
+  load_rows(p.z, v);  // z enters through the basis-slice registers
+#pragma unroll
+  for (int r = 0; r < RPT; r++) {
+    zput(r, v[r]);
+#pragma unroll
+    for (int c = 0; c < C; c++) v[r][c] = (VT)0;
+  }
+  unsigned rtag = 0;
+  double h[C];
+#pragma unroll
+  for (int c = 0; c < C; c++) h[c] = 0.0;
+  for (int i2 = 0; i2 <= j + 1; i2++) {
+    if (i2 > 0) {
+#pragma unroll
+      for (int r = 0; r < RPT; r++) {
+        VT zr[C];
+        zget(r, zr);
+#pragma unroll
+        for (int c = 0; c < C; c++) zr[c] = (VT)fma(-h[c], (double)v[r][c], (double)zr[c]);
+        zput(r, zr);
+      }
+    }
+    double part[C];
+#pragma unroll
+    for (int c = 0; c < C; c++) part[c] = 0.0;
+    if (i2 <= j) load_rows(p.V + (int64_t)i2 * p.vstride, v);
+#pragma unroll
+    for (int r = 0; r < RPT; r++) {
+      VT zr[C];
+      zget(r, zr);
+#pragma unroll
+      for (int c = 0; c < C; c++) {
+        const double w = i2 <= j ? (double)v[r][c] : (double)zr[c];
+        part[c] = fma(w, (double)zr[c], part[c]);
+      }
+    }
+    if (!mgs_grid_sum<C>(p.grid, rtag, part, wpart[i2 & 1], res[i2 & 1])) return;
+    if (i2 <= j) {
+#pragma unroll
+      for (int c = 0; c < C; c++) h[c] = part[c];
+      if (blockIdx.x == 0 && threadIdx.x < C) p.H[((int64_t)threadIdx.x * p.m + j) * (p.m + 1) + i2] = part[threadIdx.x];
+    } else {
+      double hn[C];
+#pragma unroll
+      for (int c = 0; c < C; c++) hn[c] = sqrt(part[c]);
+      if (blockIdx.x == 0 && threadIdx.x < C) {
+        p.H[((int64_t)threadIdx.x * p.m + j) * (p.m + 1) + j + 1] = hn[threadIdx.x];
+        p.hn[threadIdx.x] = hn[threadIdx.x];
+      }
+      char *vn = reinterpret_cast<char *>(p.V + (int64_t)(j + 1) * p.vstride);
+#pragma unroll
+      for (int r = 0; r < RPT; r++) {
+        if (r < nv) {
+          VT zr[C], o[C];
+          zget(r, zr);
+#pragma unroll
+          for (int c = 0; c < C; c++) o[c] = hn[c] > 0.0 ? (VT)((double)zr[c] / hn[c]) : (VT)0;
+          Row16<VT>::store(reinterpret_cast<VT *>(vn + row_off(r)), o);
+        }
+      }
+    }
+  }
+}
+
+// rows per thread of the batched MGS kernel for n rows: the smallest power of
+// two <= 16 with n <= kMaxBlocks * kSolveThreads * RPT (0: n too large)
+int mgs_persist_rpt(int n) {
+  for (int r = 1; r <= 16; r *= 2)
+    if ((int64_t)n <= (int64_t)kMaxBlocks * kSolveThreads * r) return r;
+  return 0;
+}
+
+size_t mgs_persist_ws_bytes() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols + 256; }
+
+template <typename VT, int RPT>
+static int launch_mgs_rpt(BMgsParams<VT> &p, int G, hipStream_t s) {
+  constexpr bool ZL = RPT >= 16;
+  const unsigned lds = ZL ? (unsigned)(RPT * kSolveThreads * 16) : 0u;
+  void *fn = (void *)k_b_mgs_persist<VT, RPT, ZL>;
+  if (ZL) BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  void *args[] = {&p};
+  BSPAI_HIP(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kSolveThreads), args, lds, s));
+  return BSPAI_OK;
+}
+
+// One Arnoldi step's MGS (see k_b_mgs_persist) for the n x (16 / sizeof(VT))
+// block z, basis V (v_i at V + i * vstride), H columns of step j; ws:
+// mgs_persist_ws_bytes() of device memory (exchange words and the abort flag,
+// cleared here).  Enqueued on s.
+template <typename VT>
+int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn, void *ws,
+                       hipStream_t s) {
+  const int rpt = mgs_persist_rpt(n);
+  if (!rpt) return fail(BSPAI_EINVAL, "batched MGS: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
+  const int G = (int)(((int64_t)n + (int64_t)kSolveThreads * rpt - 1) / ((int64_t)kSolveThreads * rpt));
+  const size_t slot_bytes = 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols;
+  BSPAI_HIP(hipMemsetAsync(ws, 0, mgs_persist_ws_bytes(), s));
+  BMgsParams<VT> p;
+  p.n = n;
+  p.j = j;
+  p.m = m;
+  p.z = z;
+  p.V = V;
+  p.vstride = vstride;
+  p.H = H;
+  p.hn = hn;
+  p.grid.slots = static_cast<unsigned long long *>(ws);
+  p.grid.abortf = reinterpret_cast<unsigned *>(static_cast<char *>(ws) + slot_bytes);
+  switch (rpt) {
+    case 1: return launch_mgs_rpt<VT, 1>(p, G, s);
+    case 2: return launch_mgs_rpt<VT, 2>(p, G, s);
+    case 4: return launch_mgs_rpt<VT, 4>(p, G, s);
+    case 8: return launch_mgs_rpt<VT, 8>(p, G, s);
+    default: return launch_mgs_rpt<VT, 16>(p, G, s);
+  }
+}
+
+// the abort flag's offset in the batched MGS workspace
+size_t mgs_persist_abort_offset() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols; }
+
+template int launch_mgs_persist<float>(int, int, int, const float *, float *, int64_t, double *, double *, void *,
+                                       hipStream_t);
+template int launch_mgs_persist<double>(int, int, int, const double *, double *, int64_t, double *, double *, void *,
+                                        hipStream_t);
+
 }  // namespace bspai
 
 using namespace bspai;
@@ -1423,6 +1765,86 @@ __global__ void __launch_bounds__(kSolveThreads) k_exchange_probe(Grid g, int it
     acc += v[0];
   }
   if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+// The same probe with the solver's LDS footprint (one block per compute
+// unit) and placement: one_xcd = 0 launches G blocks (the dispatcher spreads
+// them over the XCDs), one_xcd = 1 launches 8 G blocks and keeps the G that
+// share one XCD.
+__global__ void __launch_bounds__(kSolveThreads) k_exchange_probe_placed(Grid g, unsigned *reg, int one_xcd,
+                                                                          int iters, double *out) {
+  extern __shared__ double dyn[];
+  __shared__ double sh[kWaves * kMaxSlotWidth + kMaxSlotWidth + 1];
+  int bid = blockIdx.x;
+  if (one_xcd) {
+    bid = one_xcd_rank(reg, g.G, g.abortf);
+    if (bid < 0) return;
+  }
+  if (threadIdx.x == 0) dyn[0] = 0.0;  // the dynamic LDS only sets the occupancy
+  unsigned rtag = 0;
+  double acc = 0.0;
+  for (int it = 0; it < iters; it++) {
+    double v[1] = {(double)((threadIdx.x + it) & 7)};
+    if (!grid_reduce<1, false>(g, rtag, v, sh, bid)) return;
+    acc += v[0];
+  }
+  if (threadIdx.x == 0) {
+    out[bid] = acc;
+    out[kMaxBlocks + bid] = (double)xcd_id();
+  }
+}
+
+extern "C" int bspai_exchange_latency_placed(int G, int iters, int one_xcd, double *us_out, int *xcd_out,
+                                             void *stream) {
+  const int grid = one_xcd ? 8 * G : G;
+  if (G < 1 || iters < 1 || !us_out || grid > kMaxBlocks)
+    return fail(BSPAI_EINVAL, "bspai_exchange_latency_placed: need 1 <= G, iters >= 1 and %d blocks <= %d",
+                grid, kMaxBlocks);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void *mem = nullptr;
+  const size_t bytes = kSlotBytes + 256 + 256 + 16 * (size_t)kMaxBlocks;
+  int rc = dalloc(&mem, bytes);
+  if (rc) return rc;
+  char *base = static_cast<char *>(mem);
+  Grid g;
+  g.slots = reinterpret_cast<double *>(base);
+  g.wide = nullptr;
+  g.abortf = reinterpret_cast<unsigned *>(base + kSlotBytes);
+  g.flags = nullptr;
+  g.G = G;
+  unsigned *reg = reinterpret_cast<unsigned *>(base + kSlotBytes + 256);
+  double *out = reinterpret_cast<double *>(base + kSlotBytes + 512);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto body = [&]() -> int {
+    BSPAI_HIP(hipMemsetAsync(mem, 0, bytes, s));
+    BSPAI_HIP(hipFuncSetAttribute((const void *)k_exchange_probe_placed, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kLdsBytes));
+    BSPAI_HIP(hipEventCreate(&e0));
+    BSPAI_HIP(hipEventCreate(&e1));
+    void *args[] = {&g, &reg, &one_xcd, &iters, &out};
+    BSPAI_HIP(hipEventRecord(e0, s));
+    BSPAI_HIP(hipLaunchCooperativeKernel((void *)k_exchange_probe_placed, dim3(grid), dim3(kSolveThreads), args,
+                                         (unsigned)kLdsBytes, s));
+    BSPAI_HIP(hipEventRecord(e1, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    BSPAI_HIP(hipEventElapsedTime(&ms, e0, e1));
+    unsigned ab = 0;
+    BSPAI_HIP(hipMemcpy(&ab, g.abortf, 4, hipMemcpyDeviceToHost));
+    if (ab) return fail(BSPAI_EHIP, "bspai_exchange_latency_placed: placement or an exchange failed");
+    if (xcd_out) {
+      std::vector<double> h(G);
+      BSPAI_HIP(hipMemcpy(h.data(), out + kMaxBlocks, 8 * (size_t)G, hipMemcpyDeviceToHost));
+      for (int k = 0; k < G; k++) xcd_out[k] = (int)h[k];
+    }
+    *us_out = ms * 1e3 / iters;
+    return BSPAI_OK;
+  };
+  rc = body();
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  dfree(mem);
+  return rc;
 }
 
 extern "C" int bspai_exchange_latency(int G, int iters, double *us_out, void *stream) {
@@ -1478,6 +1900,38 @@ extern "C" int bspai_solve_blocks(int n) {
 }
 
 extern "C" void bspai_set_profiling(int on) { g_profile = on ? 1 : 0; }
+
+static std::mutex g_mgs_mu;
+static double g_mgs_ms = 0.0, g_mgs_bytes = 0.0;
+static long long g_mgs_launches = 0;
+static int g_batch_mode = 0;
+namespace bspai {
+bool profiling_on() { return g_profile != 0; }
+void add_mgs_profile(double ms, double bytes) {
+  std::lock_guard<std::mutex> lock(g_mgs_mu);
+  g_mgs_ms += ms;
+  g_mgs_bytes += bytes;
+  g_mgs_launches++;
+}
+int batch_mode() { return g_batch_mode; }
+}  // namespace bspai
+
+extern "C" void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes) {
+  std::lock_guard<std::mutex> lock(g_mgs_mu);
+  if (ms_total) *ms_total = g_mgs_ms;
+  if (launches) *launches = g_mgs_launches;
+  if (bytes) *bytes = g_mgs_bytes;
+  if (reset) {
+    g_mgs_ms = g_mgs_bytes = 0.0;
+    g_mgs_launches = 0;
+  }
+}
+
+extern "C" int bspai_set_batch_mode(int mode) {
+  if (mode < 0 || mode > 2) return fail(BSPAI_EINVAL, "bspai_set_batch_mode: mode must be 0, 1 or 2");
+  g_batch_mode = mode;
+  return BSPAI_OK;
+}
 extern "C" double bspai_last_solve_kernel_ms(void) { return g_last_ms; }
 
 static int check_system(const bspai_csr *A, const double *b, const bspai_handle *M, const gmres_ir_tol *tol,
@@ -1677,8 +2131,8 @@ static int solve_entry(const bspai_csr *A, const bspai_handle *Ab, const double 
   if (nrhs > 1) {
     if (tol->orth != 0) return fail(BSPAI_EINVAL, "%s: orth = 1 (CGS2) needs nrhs = 1", who);
     const int m = std::min(std::max(tol->gmres_max, 1), std::min(A->n, kMaxGmres));
-    if (tol->u_g == BSPAI_FP64) return solve_batched<double>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
-    return solve_batched<float>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
+    if (tol->u_g == BSPAI_FP64) return solve_many<double>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
+    return solve_many<float>(A, Ab, b, M, tol, x, nrhs, m, st_host, s);
   }
   if (tol->u_g == BSPAI_FP64) return solve_typed<double>(A, Ab, b, M, tol, x, st_host, s);
   return solve_typed<float>(A, Ab, b, M, tol, x, st_host, s);

@@ -415,7 +415,11 @@ struct DevBuf {
 
 template <typename VT>
 int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
-                  const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s) {
+                  const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s,
+                  bool mgs1) {
+  if (mgs1 && (R * (int)sizeof(VT) != 16 || !mgs_persist_rpt(A->n)))
+    return fail(BSPAI_EINVAL, "gmres_ir_solve: the one-launch MGS needs %d columns and at most %d rows",
+                16 / (int)sizeof(VT), 256 * 512 * 16);
   const int n = A->n;
   const int64_t nnz = A->nnz, nr = (int64_t)n * R;
   const bool tr = tol->trans != 0;
@@ -433,8 +437,23 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
 
   // operators: A (or A^T) in FP64 and, inside GMRES, in u_g or bucketed (A_b
   // or A_b^T), M_b (or M_b^T), FP64 M for x_0
-  DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb;
+  DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb, mgsws;
   int rc;
+  if (mgs1 && (rc = dalloc(&mgsws.p, mgs_persist_ws_bytes()))) return rc;
+  // optional timing of the one-launch MGS kernel (HIP events on s)
+  const bool prof = mgs1 && profiling_on();
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (auto &q : e)
+        if (q) (void)hipEventDestroy(q);
+    }
+  } pev;
+  if (prof) {
+    BSPAI_HIP(hipEventCreate(&pev.e[0]));
+    BSPAI_HIP(hipEventCreate(&pev.e[1]));
+  }
+  unsigned mgs_abort = 0;
   const int32_t *arp = A->row_ptr, *acol = A->col;
   const double *aval = A->val;
   if (tr) {
@@ -588,8 +607,17 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
       } else {
         if ((rc = launch_bspmv(Mb, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Apm, W, Z, R, R, fp64, s))) return rc;
       }
+      if (mgs1) {
+        // the whole step's MGS in one cooperative launch (h_{i,j} to H, the
+        // norms to S row 5, v_{j+1} written)
+        if (prof) BSPAI_HIP(hipEventRecord(pev.e[0], s));
+        if ((rc = launch_mgs_persist<VT>(n, j, m, Z, V, nr, H, S + 5 * R, mgsws.p, s))) return rc;
+        if (prof) BSPAI_HIP(hipEventRecord(pev.e[1], s));
+        BSPAI_HIP(hipMemcpyAsync(&mgs_abort, static_cast<char *>(mgsws.p) + mgs_persist_abort_offset(), 4,
+                                 hipMemcpyDeviceToHost, s));
+      }
       // MGS: pass i removes v_{i-1}, measures v_i; h_{i,j} lands in H column j
-      for (int i = 0; i <= j + 1; i++) {
+      for (int i = 0; !mgs1 && i <= j + 1; i++) {
         const VT *vprev = i > 0 ? V + (int64_t)(i - 1) * nr : nullptr;
         const VT *vcur = i <= j ? V + (int64_t)i * nr : nullptr;
         const double *hprev = S + 5 * R;
@@ -603,8 +631,9 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
                          vec4 ? nblk4 : nblk)))
           return rc;
       }
-      // v_{j+1} = z / h_{j+1,j}
-      if (vec4)
+      // v_{j+1} = z / h_{j+1,j} (written by the one-launch MGS itself)
+      if (mgs1) {
+      } else if (vec4)
         hipLaunchKernelGGL(k_b_scale4<VT>, dim3((unsigned)((nr / 4 + 255) / 256)), dim3(256), 0, s, R, nr, Z,
                            S + 5 * R, V + (int64_t)(j + 1) * nr);
       else
@@ -614,6 +643,13 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
       BSPAI_CHECK_LAUNCH();
       std::vector<double> hq;  // row 0: h_{j+1,j}, row 1: |g_{j+1}|
       if ((rc = to_host(S + 5 * R, hq, 2))) return rc;
+      if (mgs_abort) return fail(BSPAI_EHIP, "gmres_ir_solve: a grid exchange of the MGS kernel timed out");
+      if (prof) {
+        float ms = 0.f;
+        BSPAI_HIP(hipEventElapsedTime(&ms, pev.e[0], pev.e[1]));
+        // algorithmic bytes: v_0..v_j and z read, v_{j+1} written
+        add_mgs_profile(ms, (double)(j + 3) * (double)nr * sizeof(VT));
+      }
       const double *hn = hq.data(), *hres = hq.data() + R;
       bool changed = false;
       for (int c = 0; c < R; c++) {
@@ -667,9 +703,70 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   return BSPAI_OK;
 }
 
+// columns [c0, c0 + g) of an n x R row-major array to an n x g one and back
+__global__ void k_gather_cols(int64_t n, int R, int c0, int g, const double *src, double *dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * g) dst[t] = src[(t / g) * R + c0 + t % g];
+}
+__global__ void k_scatter_cols(int64_t n, int R, int c0, int g, const double *src, double *dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n * g) dst[(t / g) * R + c0 + t % g] = src[t];
+}
+
+// n R u_g values from which the column groups pay: below it every pass moves
+// little and the launches of the per-pass kernels are shared by all columns
+constexpr double kGroupBytes = 64.0 * 1024 * 1024;
+
+template <typename VT>
+int solve_many(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
+               const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s) {
+  constexpr int C = 16 / (int)sizeof(VT);
+  const int n = A->n;
+  const int mode = batch_mode();
+  const bool fits = mgs_persist_rpt(n) > 0 && R >= C;
+  const bool grouped = mode == 2 ? fits : (mode == 1 ? false : fits && (double)n * R * sizeof(VT) >= kGroupBytes);
+  if (!grouped) return solve_batched<VT>(A, Ab, b, M, tol, x, R, m, st_host, s, false);
+  if (R == C) return solve_batched<VT>(A, Ab, b, M, tol, x, R, m, st_host, s, true);
+  // consecutive groups of C columns (a trailing C + 1 or fewer than C go
+  // together through the per-pass kernels), each solved on its own
+  std::vector<gmres_ir_stats> st(R);
+  DevBuf bg, xg;
+  int rc;
+  if ((rc = dalloc(&bg.p, 8 * (size_t)n * (C + 1))) || (rc = dalloc(&xg.p, 8 * (size_t)n * (C + 1)))) return rc;
+  int worst = BSPAI_OK;
+  for (int c0 = 0; c0 < R;) {
+    const int left = R - c0;
+    const int g = left == C + 1 ? C + 1 : (left < C ? left : C);
+    const unsigned eg = (unsigned)(((int64_t)n * g + 255) / 256);
+    hipLaunchKernelGGL(k_gather_cols, dim3(eg), dim3(256), 0, s, (int64_t)n, R, c0, g, b, (double *)bg.p);
+    BSPAI_CHECK_LAUNCH();
+    if (tol->x0_mode == 3) {
+      hipLaunchKernelGGL(k_gather_cols, dim3(eg), dim3(256), 0, s, (int64_t)n, R, c0, g, x, (double *)xg.p);
+      BSPAI_CHECK_LAUNCH();
+    }
+    rc = solve_batched<VT>(A, Ab, (const double *)bg.p, M, tol, (double *)xg.p, g, m, st.data() + c0, s, g == C);
+    if (rc != BSPAI_OK && rc != BSPAI_ENOCONV && rc != BSPAI_ESTAG && rc != BSPAI_ENAN) return rc;
+    worst = worse_status(worst, rc);
+    hipLaunchKernelGGL(k_scatter_cols, dim3(eg), dim3(256), 0, s, (int64_t)n, R, c0, g, (const double *)xg.p, x);
+    BSPAI_CHECK_LAUNCH();
+    c0 += g;
+  }
+  BSPAI_HIP(hipStreamSynchronize(s));
+  if (st_host) memcpy(st_host, st.data(), sizeof(gmres_ir_stats) * R);
+  if (worst == BSPAI_ENAN) return fail(BSPAI_ENAN, "gmres_ir_solve: NaN or infinity in a residual");
+  if (worst == BSPAI_ENOCONV) return fail(BSPAI_ENOCONV, "gmres_ir_solve: some right-hand side reached i_max");
+  if (worst == BSPAI_ESTAG)
+    return fail(BSPAI_ESTAG, "gmres_ir_solve: some right-hand side stagnated before meeting a tolerance");
+  return BSPAI_OK;
+}
+
+template int solve_many<float>(const bspai_csr *, const bspai_handle *, const double *, const bspai_handle *,
+                               const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t);
+template int solve_many<double>(const bspai_csr *, const bspai_handle *, const double *, const bspai_handle *,
+                                const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t);
 template int solve_batched<float>(const bspai_csr *, const bspai_handle *, const double *, const bspai_handle *,
-                                  const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t);
+                                  const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t, bool);
 template int solve_batched<double>(const bspai_csr *, const bspai_handle *, const double *, const bspai_handle *,
-                                   const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t);
+                                   const gmres_ir_tol *, double *, int, int, gmres_ir_stats *, hipStream_t, bool);
 
 }  // namespace bspai

@@ -525,13 +525,22 @@ def _check_column(st, ref, eta_g):
     assert np.isclose(st["eta"][-1], eta_g, rtol=1e-12, atol=0)
 
 
-def test_solve_batched_matches_oracle(B):
+@pytest.fixture(params=[1, 2], ids=["all_columns", "groups"])
+def batch_mode(B, request):
+    """Run the test with every column in each pass kernel (1) and with
+    column groups and the one-launch MGS (2); back to automatic after."""
+    B.set_batch_mode(request.param)
+    yield request.param
+    B.set_batch_mode(0)
+
+
+def test_solve_batched_matches_oracle(B, batch_mode):
     """8 right-hand sides of the 16^3 anisotropic problem in one call: every
     column against the oracle's single-RHS solve of that column."""
     c = W.config("4a", small=True)
     A, P, Bm = c["A"], c["P"], c["b"]
     eps = c["eps"][0]
-    _say("solve batched 4a small", Bm.shape)
+    _say("solve batched 4a small", Bm.shape, "mode", batch_mode)
     kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=150, i_max=20)
     xg, sts, h = _solve_case(B, A, P, Bm, c["precs"], eps, **kw)
     assert xg.shape == Bm.shape and len(sts) == Bm.shape[1]
@@ -545,7 +554,7 @@ def test_solve_batched_matches_oracle(B):
 
 
 @pytest.mark.parametrize("ncols", [3, 4])
-def test_solve_batched_columns_independent(B, ncols):
+def test_solve_batched_columns_independent(B, ncols, batch_mode):
     """Three columns (the one-column-per-thread kernels) or four (the
     four-columns-per-thread ones): a repeated column gives the same bits, a
     zero column stops at once, and each column agrees with the single-RHS
@@ -569,7 +578,7 @@ def test_solve_batched_columns_independent(B, ncols):
 
 
 @pytest.mark.parametrize("x0_mode", [1, 2, 3])
-def test_solve_batched_x0_modes_fp64(B, x0_mode):
+def test_solve_batched_x0_modes_fp64(B, x0_mode, batch_mode):
     """FP64 working precision and the other starting vectors, two columns."""
     import torch
 
@@ -591,7 +600,7 @@ def test_solve_batched_x0_modes_fp64(B, x0_mode):
     h.free()
 
 
-def test_solve_batched_adjoint(B):
+def test_solve_batched_adjoint(B, batch_mode):
     """A^T Lambda = G for four columns with the right-preconditioned path."""
     c = W.config("5", small=True)
     A, P = c["A"], c["P"]
@@ -1101,6 +1110,42 @@ def test_multi_system_full_size(B):
         assert st["stop_reason"] == lit["stop_reason"] and st["status"] == lit["status"] == 0
         assert O.backward_error(sy["A"], sy["b"], xs[k]) <= 10 * lit["eta"][-1] + 1e-17
         assert fe_g <= 10 * fe_l + 10 * U64, (k, fe_g, fe_l)
+
+
+@pytest.mark.parametrize("u_g,ncols", [("fp32", 9), ("fp32", 6), ("fp64", 7)])
+def test_solve_column_groups_match_oracle(B, u_g, ncols):
+    """Column groups (4 columns in FP32, 2 in FP64, one MGS launch per
+    Arnoldi step) with a trailing group that runs through the per-pass
+    kernels (9 = 4 + 5, 6 = 4 + 2, 7 = 2 + 2 + 3): every column against the
+    oracle's single-RHS solve, and x_0 given by the caller (x0_mode 3)
+    reaching each group."""
+    import torch
+
+    c = W.config("4a", small=True)
+    A, P = c["A"], c["P"]
+    eps = c["eps"][0]
+    rng = np.random.default_rng(31)
+    Bm = rng.standard_normal((A.n, ncols))
+    X0 = 0.01 * rng.standard_normal((A.n, ncols))
+    _say("column groups", u_g, ncols)
+    kw = dict(tau=1e-4 if u_g == "fp32" else 1e-8, tol_rr=1e-10, gmres_max=150, i_max=20)
+    B.set_batch_mode(2)
+    try:
+        Ad = B.CSRMatrix.from_host(A)
+        h = B.build(Ad, B.CSRMatrix.from_host(P), eps=eps, precs=c["precs"])
+        xg, sts = B.solve(Ad, _dev(Bm), h, u_g=u_g, x0_mode=3, x=_dev(X0), **kw)
+        torch.cuda.synchronize()
+        xg = xg.cpu().numpy()
+    finally:
+        B.set_batch_mode(0)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, eps, c["precs"])
+    ug = O.FP32 if u_g == "fp32" else O.FP64
+    for col in range(ncols):
+        b = Bm[:, col].copy()
+        ref = O.gmres_ir(A, M, Mb, b, dot64=True, ug=ug, up=ug, x0_mode=3, x0=X0[:, col].copy(), **kw)
+        _check_column(sts[col], ref, O.backward_error(A, b, xg[:, col]))
+    h.free()
 
 
 def test_solve_batched_full_size(B):

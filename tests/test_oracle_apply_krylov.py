@@ -384,6 +384,27 @@ def test_ir_config1_converges_to_relative_residual(orc):
     assert 2 <= res["steps"] <= 4
 
 
+def test_ir_caller_starting_vector(orc):
+    """x0_mode 3 starts from the caller's x_0: from zero it repeats x0_mode 2
+    bit for bit, from the solution it stops before any correction, and from
+    elsewhere it still reaches the tolerance."""
+    c = W.config("1", small=True)
+    A, P = c["A"], c["P"]
+    _, Mv, _ = orc.spai(A, P)
+    M = W.CSR(A.n, P.row_ptr, P.col, Mv)
+    Mb = O.Bucketed(M, c["eps"][0], c["precs"])
+    kw = dict(tol_rr=1e-10)
+    z = orc.gmres_ir(A, M, Mb, c["b"], x0_mode=2, **kw)
+    z3 = orc.gmres_ir(A, M, Mb, c["b"], x0_mode=3, x0=np.zeros(A.n), **kw)
+    assert np.array_equal(z["x"], z3["x"]) and z["its"] == z3["its"]
+    at = orc.gmres_ir(A, M, Mb, c["b"], x0_mode=3, x0=np.linalg.solve(A.dense(), c["b"]), **kw)
+    assert at["steps"] == 0 and at["stop_reason"] == 1
+    far = orc.gmres_ir(A, M, Mb, c["b"], x0_mode=3, x0=np.full(A.n, 10.0), **kw)
+    assert far["status"] == O.OK and far["relres"][-1] <= 1e-10
+    with pytest.raises(ValueError):
+        orc.gmres_ir(A, M, Mb, c["b"], x0_mode=3, **kw)
+
+
 def test_ir_reports_noconvergence(orc):
     c = W.config("1", small=True)
     A, P = c["A"], c["P"]
