@@ -98,6 +98,9 @@ def lib():
                            C.POINTER(C.c_int)]
     L.orc_spai_adaptive.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, C.c_void_p, C.c_void_p, C.c_int,
                                     C.c_int, C.c_double, C.c_int, _i32p, _i32p, _f64p, _i32p, C.POINTER(C.c_int)]
+    L.orc_spai_adaptive_prec.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i32p, C.c_void_p, C.c_void_p,
+                                         C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, _i32p, _i32p,
+                                         _f64p, _i32p, C.POINTER(C.c_int)]
     L.orc_norm_inf.argtypes = [C.c_int, _i32p, _f64p]
     L.orc_norm_inf.restype = C.c_double
     L.orc_bucketize.argtypes = [C.c_int, _i32p, _f64p, C.c_double, _i32p, C.c_int, _i8p, _f64p, _f64p, _f64p, _i64p]
@@ -192,11 +195,13 @@ def spai(A, P, rows: Optional[np.ndarray] = None, scale: bool = False, uf: int =
     return st, Mv, bad.value
 
 
-def spai_adaptive(A, alpha: int = 5, beta: int = 8, eps: float = 0.4, J0=None) -> Dict:
+def spai_adaptive(A, alpha: int = 5, beta: int = 8, eps: float = 0.4, J0=None, uf: int = FP64,
+                  scale: bool = False) -> Dict:
     """Adaptive SPAI (Algorithm 1 with augmentation, on A^T).  J0: initial
-    pattern (workloads.CSR; None: the identity).  Returns dict(status, M
-    (workloads.CSR with each row's columns ascending), steps (solves per
-    row), bad_row)."""
+    pattern (workloads.CSR; None: the identity).  uf: precision of the least
+    squares solves, scale: column scaling of A^T (as :func:`spai`).  Returns
+    dict(status, M (workloads.CSR with each row's columns ascending), steps
+    (solves per row), bad_row)."""
     import workloads as W
     n = A.n
     AT = transpose_csr(A)
@@ -214,9 +219,9 @@ def spai_adaptive(A, alpha: int = 5, beta: int = 8, eps: float = 0.4, J0=None) -
         jrp, jcp = jr.ctypes.data_as(C.c_void_p), jc.ctypes.data_as(C.c_void_p)
     else:
         jrp = jcp = None
-    st = lib().orc_spai_adaptive(n, _i32(A.row_ptr), _i32(A.col), _f64(A.val), _i32(AT.row_ptr), _i32(AT.col), jrp,
-                                 jcp, int(alpha), int(beta), float(eps), int(jmax), cnt, cols, vals, steps,
-                                 C.byref(bad))
+    st = lib().orc_spai_adaptive_prec(n, _i32(A.row_ptr), _i32(A.col), _f64(A.val), _i32(AT.row_ptr),
+                                      _i32(AT.col), jrp, jcp, int(alpha), int(beta), float(eps), int(jmax),
+                                      int(scale), int(uf), cnt, cols, vals, steps, C.byref(bad))
     del keep
     rp = np.zeros(n + 1, dtype=np.int32)
     rp[1:] = np.cumsum(cnt)

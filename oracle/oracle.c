@@ -405,12 +405,30 @@ static int cmp_cand(const void *a, const void *b) {
     return (x->j > y->j) - (x->j < y->j);
 }
 
-int orc_spai_adaptive(int n, const int *Arp, const int *Aci, const double *Av,
-                      const int *ATrp, const int *ATci, const int *J0rp, const int *J0ci,
-                      int alpha, int beta, double eps, int jmax,
-                      int *cnt, int *cols, double *vals, int *steps, int *bad_row) {
+/* With a construction precision uf (Section 4's single and half settings,
+ * orc_spai_adaptive_prec) every least squares solve is that of orc_spai_prec:
+ * the reduced matrix a_{J_c, I_l} d_{J_c} rounded to uf (d from the optional
+ * column scaling of A^T), Householder QR and back substitution in uf, and
+ * M(k, J_c) = m_c d_{J_c} rounded to uf.  The residual s and the candidate
+ * scores are then formed in FP64 from the unscaled A and those rounded
+ * values, so the pattern decisions see the uf solution but add no rounding
+ * of their own.  uf = FP64 without scaling is orc_spai_adaptive. */
+int orc_spai_adaptive_prec(int n, const int *Arp, const int *Aci, const double *Av,
+                           const int *ATrp, const int *ATci, const int *J0rp, const int *J0ci,
+                           int alpha, int beta, double eps, int jmax, int scale, int uf,
+                           int *cnt, int *cols, double *vals, int *steps, int *bad_row) {
     int status = ORC_OK;
     int first_bad = n;
+    const int plain = uf == OP_FP64 && !scale;
+    double *dscale = NULL;
+    if (scale) {
+        dscale = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int j = 0; j < n; j++) {
+            double mx = 0;
+            for (int e = Arp[j]; e < Arp[j + 1]; e++) mx = fmax(mx, fabs(Av[e]));
+            dscale[j] = mx > 0 ? 1.0 / mx : 1.0;
+        }
+    }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int k = 0; k < n; k++) {
         int *J = (int *)malloc(sizeof(int) * (size_t)jmax);
@@ -445,16 +463,21 @@ int orc_spai_adaptive(int n, const int *Arp, const int *Aci, const double *Av,
             double *eb = (double *)calloc((size_t)nI, sizeof(double));
             free(m);
             m = (double *)calloc((size_t)nJ, sizeof(double));
-            for (int c = 0; c < nJ; c++)
+            for (int c = 0; c < nJ; c++) {
+                const double dj = scale ? dscale[J[c]] : 1.0;
                 for (int e = Arp[J[c]]; e < Arp[J[c] + 1]; e++) {
                     if (Av[e] == 0.0) continue;
-                    Ab[find_sorted(I, nI, Aci[e]) + (size_t)c * nI] = Av[e];
+                    const size_t at = find_sorted(I, nI, Aci[e]) + (size_t)c * nI;
+                    A0[at] = Av[e];
+                    Ab[at] = plain ? Av[e] : orc_round(uf, Av[e] * dj);
                 }
-            memcpy(A0, Ab, sizeof(double) * (size_t)nI * nJ);
+            }
             eb[kpos] = 1.0;
-            st = orc_householder_ls(nI, nJ, Ab, eb, m);
+            st = plain ? orc_householder_ls(nI, nJ, Ab, eb, m) : orc_householder_ls_prec(nI, nJ, Ab, eb, m, uf);
             nsolve++;
             if (st != ORC_OK) { free(Ab); free(A0); free(eb); free(I); break; }
+            if (!plain)
+                for (int c = 0; c < nJ; c++) m[c] = orc_round(uf, m[c] * (scale ? dscale[J[c]] : 1.0));
             /* residual on the shadow */
             double *sv = (double *)malloc(sizeof(double) * (size_t)nI);
             double ns2 = 0.0;
@@ -528,8 +551,17 @@ int orc_spai_adaptive(int n, const int *Arp, const int *Aci, const double *Av,
             }
         }
     }
+    free(dscale);
     if (bad_row) *bad_row = (status == ORC_OK) ? -1 : first_bad;
     return status;
+}
+
+int orc_spai_adaptive(int n, const int *Arp, const int *Aci, const double *Av,
+                      const int *ATrp, const int *ATci, const int *J0rp, const int *J0ci,
+                      int alpha, int beta, double eps, int jmax,
+                      int *cnt, int *cols, double *vals, int *steps, int *bad_row) {
+    return orc_spai_adaptive_prec(n, Arp, Aci, Av, ATrp, ATci, J0rp, J0ci, alpha, beta, eps, jmax, 0, OP_FP64, cnt,
+                                  cols, vals, steps, bad_row);
 }
 
 /* ------------------------------------------------------------------------

@@ -484,6 +484,7 @@ constexpr int kAdJ = 64;         // pattern entries per row of M
 struct AdaptiveArgs {
   int n, alpha, beta, jmax;
   double eps;
+  const double *dscale;         // column scaling of A^T (null: none)
   const int32_t *arp, *acol;
   const double *aval;
   const int32_t *atrp, *atcol;  // pattern of A^T (columns of A)
@@ -493,8 +494,26 @@ struct AdaptiveArgs {
   double *tiles, *rhs;          // per block: kAdShadow * jmax and kAdShadow doubles
   int32_t *cnt, *cols, *steps;
   double *vals;
-  int32_t *err;                 // [0] zero row, [1] rank, [2] limits: smallest row
+  int32_t *err;                 // [0] zero row, [1] rank, [2] limits, [3] u_f overflow: smallest row
 };
+
+// Sum over the block (kBigThreads) in the construction precision T: FP64 as
+// block_sum_big; fp32 and fp16 as wavefront trees, then the waves in order,
+// every addition rounded to T.
+template <typename T>
+__device__ __forceinline__ T block_sum_t(T v, double *sh) {
+  if constexpr (sizeof(T) == 8) {
+    return block_sum_big(v, sh);
+  } else {
+    v = wave_sum_t<T>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = (double)v;
+    __syncthreads();
+    T t = (T)sh[0];
+    for (int w = 1; w < kBigThreads / 64; w++) t = (T)(t + (T)sh[w]);
+    return t;
+  }
+}
 
 __global__ void k_rownorm2(int n, const int32_t *rp, const double *v, double *out) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -524,6 +543,14 @@ __device__ void block_bitonic(K *S, int len) {
   }
 }
 
+// T: the construction precision u_f of the least squares solves (Section 4:
+// double, single or half).  The tile holds a_{J_c, I_l} d_{J_c} rounded to
+// T, the QR and back substitution round every operation to T, and
+// M(k, J_c) = m_c d_{J_c} rounded to T; the residual and the candidate
+// scores are formed in FP64 from the unscaled A and those values.  With
+// T = double and no scaling this is the FP64 construction, operation for
+// operation.
+template <typename T>
 __global__ void __launch_bounds__(kAdThreads) k_spai_adaptive(AdaptiveArgs a) {
   extern __shared__ double lds_a[];
   unsigned long long *key = reinterpret_cast<unsigned long long *>(lds_a);  // kAdCand
@@ -531,13 +558,16 @@ __global__ void __launch_bounds__(kAdThreads) k_spai_adaptive(AdaptiveArgs a) {
   int32_t *I = reinterpret_cast<int32_t *>(lds_a + kAdCand);                // kAdShadow
   double *sv = lds_a + kAdCand + kAdShadow / 2;                             // kAdShadow
   __shared__ int32_t J[kAdJ], off[kAdJ + 1];
-  __shared__ double yv[kAdJ], diagR[kAdJ];
+  __shared__ T yv[kAdJ], diagR[kAdJ];
+  __shared__ double md[kAdJ];  // M(k, J): the solution rounded to T, in FP64
   __shared__ double sh[kAdThreads / 64];
   __shared__ int s_n, s_nI, s_kpos, s_nJ, s_done, s_nsolve;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int k = a.rows[blockIdx.x];
-  double *tile = a.tiles + (int64_t)blockIdx.x * kAdShadow * a.jmax;
-  double *rhs = a.rhs + (int64_t)blockIdx.x * kAdShadow;
+  // the scratch tile: T values for the least squares, FP64 for the residual
+  double *tiled = a.tiles + (int64_t)blockIdx.x * kAdShadow * a.jmax;
+  T *tile = reinterpret_cast<T *>(tiled);
+  T *rhs = reinterpret_cast<T *>(a.rhs + (int64_t)blockIdx.x * kAdShadow);
   auto fail_row = [&](int slot) {
     if (tid == 0) atomicMin(&a.err[slot], k);
   };
@@ -605,63 +635,80 @@ __global__ void __launch_bounds__(kAdThreads) k_spai_adaptive(AdaptiveArgs a) {
     const int kpos = s_kpos;
     if (kpos < 0) return fail_row(0);
     if (nI < nJ) return fail_row(1);
-    // ---- tile A(J, I)^T in scratch, column c = row J[c] of A
-    auto scatter = [&]() {
-      for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) tile[p] = 0.0;
+    // ---- tile A(J, I)^T in scratch, column c = row J[c] of A: for the least
+    // squares scaled and rounded to T, for the residual the FP64 values
+    auto scatter_t = [&]() {
+      for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) tile[p] = (T)0;
+      __syncthreads();
+      for (int c = tid; c < nJ; c += kAdThreads) {
+        const double dj = a.dscale ? a.dscale[J[c]] : 1.0;
+        for (int p = a.arp[J[c]]; p < a.arp[J[c] + 1]; p++)
+          if (a.aval[p] != 0.0) tile[lower_bound_i(I, nI, a.acol[p]) + (int64_t)c * nI] = (T)(a.aval[p] * dj);
+      }
+      __syncthreads();
+    };
+    auto scatter_d = [&]() {
+      for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) tiled[p] = 0.0;
       __syncthreads();
       for (int c = tid; c < nJ; c += kAdThreads)
         for (int p = a.arp[J[c]]; p < a.arp[J[c] + 1]; p++)
-          if (a.aval[p] != 0.0) tile[lower_bound_i(I, nI, a.acol[p]) + (int64_t)c * nI] = a.aval[p];
+          if (a.aval[p] != 0.0) tiled[lower_bound_i(I, nI, a.acol[p]) + (int64_t)c * nI] = a.aval[p];
       __syncthreads();
     };
-    scatter();
-    for (int l = tid; l < nI; l += kAdThreads) rhs[l] = (l == kpos) ? 1.0 : 0.0;
-    double fl = 0.0;
-    for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) fl += tile[p] * tile[p];
-    const double fro = sqrt(block_sum_big(fl, sh));
+    scatter_t();
+    for (int l = tid; l < nI; l += kAdThreads) rhs[l] = (l == kpos) ? (T)1 : (T)0;
+    T fl = (T)0;
+    for (int64_t p = tid; p < (int64_t)nI * nJ; p += kAdThreads) fl = fl + tile[p] * tile[p];
+    const T fro = sqrt_t<T>(block_sum_t<T>(fl, sh));
+    if (!isfinite((double)fro)) return fail_row(3);
     for (int c = 0; c < nJ; c++) {
-      double *col = tile + (int64_t)c * nI;
-      double s2 = 0.0;
-      for (int l = c + tid; l < nI; l += kAdThreads) s2 += col[l] * col[l];
-      double nrm = sqrt(block_sum_big(s2, sh));
-      double al = col[c];
-      double be = -copysign(nrm, al);
-      if (nrm == 0.0 || fabs(be) <= (double)nJ * 0x1p-53 * fro) return fail_row(1);
+      T *col = tile + (int64_t)c * nI;
+      T s2 = (T)0;
+      for (int l = c + tid; l < nI; l += kAdThreads) s2 = s2 + col[l] * col[l];
+      T nrm = sqrt_t<T>(block_sum_t<T>(s2, sh));
+      T al = col[c];
+      T be = (T)(-copysign((double)nrm, (double)al));
+      if (nrm == (T)0 || fabs((double)be) <= (double)nJ * unit_roundoff_t<T>() * (double)fro) return fail_row(1);
       __syncthreads();
       if (tid == 0) {
         col[c] = al - be;
         diagR[c] = be;
       }
       __syncthreads();
-      double vt = 0.0;
-      for (int l = c + tid; l < nI; l += kAdThreads) vt += col[l] * col[l];
-      const double vtv = block_sum_big(vt, sh);
+      T vt = (T)0;
+      for (int l = c + tid; l < nI; l += kAdThreads) vt = vt + col[l] * col[l];
+      const T vtv = block_sum_t<T>(vt, sh);
       for (int jj = c + 1 + w; jj <= nJ; jj += kAdThreads / 64) {
-        double *cj = (jj < nJ) ? tile + (int64_t)jj * nI : rhs;
-        double d = 0.0;
-        for (int l = c + lane; l < nI; l += 64) d += col[l] * cj[l];
-        double f = 2.0 * wave_sum_d(d) / vtv;
-        for (int l = c + lane; l < nI; l += 64) cj[l] -= f * col[l];
+        T *cj = (jj < nJ) ? tile + (int64_t)jj * nI : rhs;
+        T d = (T)0;
+        for (int l = c + lane; l < nI; l += 64) d = d + col[l] * cj[l];
+        T f = (T)2 * wave_sum_t<T>(d) / vtv;
+        for (int l = c + lane; l < nI; l += 64) cj[l] = cj[l] - f * col[l];
       }
       __syncthreads();
     }
     for (int c = tid; c < nJ; c += kAdThreads) yv[c] = rhs[c];
     __syncthreads();
     for (int c = nJ - 1; c >= 0; c--) {
-      double yc = yv[c] / diagR[c];
+      T yc = yv[c] / diagR[c];
       __syncthreads();
       if (tid == 0) yv[c] = yc;
-      const double *Rc = tile + (int64_t)c * nI;
-      for (int i = tid; i < c; i += kAdThreads) yv[i] -= Rc[i] * yc;
+      const T *Rc = tile + (int64_t)c * nI;
+      for (int i = tid; i < c; i += kAdThreads) yv[i] = yv[i] - Rc[i] * yc;
       __syncthreads();
     }
+    for (int c = tid; c < nJ; c += kAdThreads) {
+      const double dj = a.dscale ? a.dscale[J[c]] : 1.0;
+      md[c] = (double)(T)((double)yv[c] * dj);
+    }
     if (tid == 0) s_nsolve++;
-    // ---- residual s = Abar m - e_k on the shadow (tile rebuilt)
-    scatter();
+    __syncthreads();
+    // ---- residual s = Abar m - e_k on the shadow (FP64 tile rebuilt)
+    scatter_d();
     double q2 = 0.0;
     for (int l = tid; l < nI; l += kAdThreads) {
       double t = 0.0;
-      for (int c = 0; c < nJ; c++) t += tile[l + (int64_t)c * nI] * yv[c];
+      for (int c = 0; c < nJ; c++) t += tiled[l + (int64_t)c * nI] * md[c];
       t -= (l == kpos) ? 1.0 : 0.0;
       sv[l] = t;
       q2 += t * t;
@@ -767,7 +814,7 @@ __global__ void __launch_bounds__(kAdThreads) k_spai_adaptive(AdaptiveArgs a) {
   const int nJ = s_nJ;
   for (int c = tid; c < nJ; c += kAdThreads) {
     a.cols[(int64_t)k * a.jmax + c] = J[c];
-    a.vals[(int64_t)k * a.jmax + c] = yv[c];
+    a.vals[(int64_t)k * a.jmax + c] = md[c];
   }
   if (tid == 0) {
     a.cnt[k] = nJ;
@@ -1393,7 +1440,10 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
     return fail(BSPAI_EINVAL, "bspai_build_adaptive: need alpha >= 0, beta >= 0 and a finite eps >= 0");
   if ((rc = check_precs(precs, q))) return rc;
   if (!(eps_b >= 0) || !std::isfinite(eps_b)) return fail(BSPAI_EINVAL, "eps_b must be finite and >= 0");
-  if (opts && opts->u_f != BSPAI_FP64) return fail(BSPAI_EINVAL, "bspai_build_adaptive: u_f must be FP64");
+  const int uf = opts ? (int)opts->u_f : (int)BSPAI_FP64;
+  if (uf != BSPAI_FP64 && uf != BSPAI_FP32 && uf != BSPAI_FP16)
+    return fail(BSPAI_EINVAL, "bspai_build_adaptive: u_f must be FP64, FP32 or FP16");
+  const bool scale = opts && opts->scale;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = A->n;
   const int64_t nnz = A->nnz;
@@ -1412,13 +1462,14 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
   const int batch = std::min(n, 512);
   int32_t *trp = nullptr, *tcol = nullptr, *iota = nullptr, *cnt = nullptr, *cols = nullptr, *stp = nullptr,
           *err = nullptr, *mrp = nullptr, *mcol = nullptr;
-  double *rn2 = nullptr, *vals = nullptr, *tiles = nullptr, *rhs = nullptr, *mval = nullptr;
+  double *rn2 = nullptr, *vals = nullptr, *tiles = nullptr, *rhs = nullptr, *mval = nullptr, *dsc = nullptr;
   void *tmp = nullptr;
   auto body = [&]() -> int {
     int r;
     if ((r = dalloc_t(&trp, (size_t)n + 1)) || (r = dalloc_t(&tcol, (size_t)nnz + 1)) ||
         (r = dalloc_t(&iota, (size_t)n)) || (r = dalloc_t(&cnt, (size_t)n)) ||
-        (r = dalloc_t(&cols, (size_t)n * jmax)) || (r = dalloc_t(&stp, (size_t)n)) || (r = dalloc_t(&err, 3)) ||
+        (r = dalloc_t(&cols, (size_t)n * jmax)) || (r = dalloc_t(&stp, (size_t)n)) || (r = dalloc_t(&err, 4)) ||
+        (scale && (r = dalloc_t(&dsc, (size_t)n))) ||
         (r = dalloc_t(&rn2, (size_t)n)) || (r = dalloc_t(&vals, (size_t)n * jmax)) ||
         (r = dalloc_t(&tiles, (size_t)batch * kAdShadow * jmax)) || (r = dalloc_t(&rhs, (size_t)batch * kAdShadow)))
       return r;
@@ -1426,18 +1477,23 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
     const unsigned g = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_rownorm2, dim3(g), dim3(256), 0, s, n, A->row_ptr, A->val, rn2);
     hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, s, n, iota);
+    if (scale) hipLaunchKernelGGL(k_row_maxabs_inv, dim3(g), dim3(256), 0, s, n, A->row_ptr, A->val, dsc);
     BSPAI_CHECK_LAUNCH();
     BSPAI_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * n, s));
-    const int32_t init[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+    const int32_t init[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
     BSPAI_HIP(hipMemcpyAsync(err, init, sizeof(init), hipMemcpyHostToDevice, s));
     const size_t lds = sizeof(double) * ((size_t)kAdCand + kAdShadow / 2 + kAdShadow);
-    BSPAI_HIP(hipFuncSetAttribute((const void *)k_spai_adaptive, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const void *kern = uf == BSPAI_FP32   ? (const void *)k_spai_adaptive<float>
+                       : uf == BSPAI_FP16 ? (const void *)k_spai_adaptive<_Float16>
+                                          : (const void *)k_spai_adaptive<double>;
+    BSPAI_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     AdaptiveArgs a;
     a.n = n;
     a.alpha = ad->alpha;
     a.beta = ad->beta;
     a.jmax = jmax;
     a.eps = ad->eps;
+    a.dscale = dsc;
     a.arp = A->row_ptr;
     a.acol = A->col;
     a.aval = A->val;
@@ -1456,10 +1512,10 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
     for (int r0 = 0; r0 < n; r0 += batch) {
       a.rows = iota + r0;
       const int nb = std::min(batch, n - r0);
-      hipLaunchKernelGGL(k_spai_adaptive, dim3(nb), dim3(kAdThreads), lds, s, a);
-      BSPAI_CHECK_LAUNCH();
+      void *args[] = {&a};
+      BSPAI_HIP(hipLaunchKernel(kern, dim3(nb), dim3(kAdThreads), args, lds, s));
     }
-    int32_t he[3];
+    int32_t he[4];
     BSPAI_HIP(hipMemcpyAsync(he, err, sizeof(he), hipMemcpyDeviceToHost, s));
     BSPAI_HIP(hipStreamSynchronize(s));
     if (he[0] != INT32_MAX) return fail(BSPAI_EZEROROW, "bspai_build_adaptive: row %d of M is zero (a_kk = 0?)", he[0]);
@@ -1467,6 +1523,8 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
     if (he[2] != INT32_MAX)
       return fail(BSPAI_EINVAL, "bspai_build_adaptive: row %d exceeds %d shadow rows or %d candidates", he[2],
                   kAdShadow, kAdCand / 2);
+    if (he[3] != INT32_MAX)
+      return fail(BSPAI_ENAN, "bspai_build_adaptive: the least squares of row %d overflow u_f (use scale)", he[3]);
     if (steps_host) BSPAI_HIP(hipMemcpy(steps_host, stp, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
     // CSR of M
     if ((r = dalloc_t(&mrp, (size_t)n + 1)) || (r = dalloc(&tmp, scan_tmp_bytes(n)))) return r;
@@ -1489,7 +1547,7 @@ extern "C" int bspai_build_adaptive(const bspai_csr *A, const bspai_pattern *J0,
   rc = body();
   (void)hipStreamSynchronize(s);
   dfree(trp), dfree(tcol), dfree(iota), dfree(cnt), dfree(cols), dfree(stp), dfree(err), dfree(rn2), dfree(vals);
-  dfree(tiles), dfree(rhs), dfree(mrp), dfree(mcol), dfree(mval), dfree(tmp);
+  dfree(tiles), dfree(rhs), dfree(mrp), dfree(mcol), dfree(mval), dfree(tmp), dfree(dsc);
   return rc;
 }
 

@@ -109,3 +109,48 @@ def test_rows_stopping_early_meet_the_tolerance():
     assert np.all((res[early] <= eps * (1 + 1e-12)) | (lens[early] < 1 + beta * (r["steps"][early] - 1) + 1))
     assert np.mean(res[early] <= eps) > 0.9
     assert np.all(lens <= 1 + alpha * beta)
+
+
+@pytest.mark.parametrize("uf", [O.FP32, O.FP16])
+def test_adaptive_in_a_lower_construction_precision(uf):
+    """Table 4's setting, the SPAI built in single (or half) precision: every
+    row's values are the u_f least squares solution on the pattern the row
+    ended with (the fixed-pattern u_f construction, pinned on its own against
+    IEEE scalar arithmetic), bit for bit, and are u_f numbers; most rows find
+    the FP64 build's pattern (the decisions see only u_f's effect on the
+    fit)."""
+    A = W.config("2", small=True)["A"]
+    ref = O.spai_adaptive(A, alpha=5, beta=8, eps=0.4)
+    r = O.spai_adaptive(A, alpha=5, beta=8, eps=0.4, uf=uf, scale=True)
+    assert ref["status"] == r["status"] == O.OK
+    M = r["M"]
+    st, Mv, _ = O.spai(A, M.pattern(), scale=True, uf=uf)
+    assert st == O.OK and np.array_equal(Mv, M.val)
+    assert np.array_equal(O.round_to(uf, M.val), M.val)
+    same = [np.array_equal(M.col[M.row_ptr[k]:M.row_ptr[k + 1]], ref["M"].col[ref["M"].row_ptr[k]:ref["M"].row_ptr[k + 1]])
+            for k in range(A.n)]
+    assert np.mean(same) >= 0.9, np.mean(same)
+    # where the patterns agree the values agree to the construction precision
+    u = 2.0 ** -24 if uf == O.FP32 else 2.0 ** -11
+    for k in np.flatnonzero(same)[:200]:
+        a, b = M.val[M.row_ptr[k]:M.row_ptr[k + 1]], ref["M"].val[ref["M"].row_ptr[k]:ref["M"].row_ptr[k + 1]]
+        assert np.abs(a - b).max() <= 200 * u * np.abs(b).max(), k
+
+
+def test_adaptive_half_precision_overflow_without_scaling():
+    """Entries of 1e5 exceed fp16's 65,504: unscaled, the half-precision
+    least squares overflow and the build reports ENAN; scaled, it succeeds."""
+    rng = np.random.default_rng(91)
+    A = W.random_sparse(120, 0.05, rng, dominance=0.8)
+    A = W.CSR(A.n, A.row_ptr, A.col, A.val * 1e5)
+    assert O.spai_adaptive(A, alpha=2, beta=4, eps=0.1, uf=O.FP16)["status"] == O.ENAN
+    assert O.spai_adaptive(A, alpha=2, beta=4, eps=0.1, uf=O.FP16, scale=True)["status"] == O.OK
+
+
+def test_adaptive_fp64_scaling_changes_little():
+    """Column scaling in FP64 only changes the rounding of each solve."""
+    A = W.config("2", small=True)["A"]
+    a = O.spai_adaptive(A, alpha=3, beta=4, eps=0.2)
+    b = O.spai_adaptive(A, alpha=3, beta=4, eps=0.2, scale=True)
+    assert np.array_equal(a["M"].col, b["M"].col)
+    assert np.abs(a["M"].val - b["M"].val).max() <= 1e-10 * np.abs(a["M"].val).max()
