@@ -1,17 +1,25 @@
 #!/usr/bin/env python
-"""BSPAI-GMRES-IR on one MI355X: solves/s and bucketed M-apply bandwidth.
+"""BSPAI-GMRES-IR on one MI355X: right-hand-side solves/s and bucketed M-apply
+bandwidth, BSPAI against all-FP64 SPAI at equal stopping tests.
 
-A step is one full gmres_ir_solve (Algorithm 4 after the SPAI build: x_0,
-refinement residuals in double-double, left-preconditioned MGS-GMRES with the
-bucketed SPAI applied in FP32, updates) on the 256 x 256 upwind
-convection-diffusion system (n = 65,536, Peclet 50), SPAI on the pattern of
-A^2 built in FP64, buckets {fp64, fp32, fp16, bf16} at eps_b = 1e-4,
-b = A x_true.  A, M and b are resident on the GPU before timing starts.
+Headline workload: the 128^3 anisotropic 7-point diffusion operator
+(1:10:100, n = 2,097,152) with 64 right-hand sides N(0,1) sharing one BSPAI
+M (SPAI on the pattern of A, buckets fp32/fp16/bf16 at eps_b = 1e-2),
+u_g = u_p = fp32, u = fp64, residuals in double-double, tau = 1e-4, refinement
+to relative residual 1e-10, GMRES cap 150.  The library solves many
+right-hand sides in column groups (4 columns in FP32, one cooperative MGS
+launch per Arnoldi step); a step is one gmres_ir_solve call on one such group
+of 4 of the 64 columns, the steps cycling through the 16 groups.  value =
+right-hand sides solved per second.  A, M and b are resident on the GPU
+before timing starts.
 
-Printed (one JSON line): solves/s, the solver kernel's roofline (algorithmic
-bytes / kernel time measured with HIP events on its stream), the CPU oracle
-timed on the host, the all-FP64 SPAI-GMRES-IR comparator at equal stopping
-tolerance, and the bucketed apply's HBM bandwidth on a cold 2.1M-row operator.
+Printed (one JSON line): the headline with the MGS kernel's roofline
+(algorithmic bytes / kernel time, HIP events recorded by the library on the
+solve's stream), the all-FP64 SPAI-GMRES-IR comparator at the same stopping
+test, the CPU oracle timed on the host, and secondary blocks (the 256^2
+convection-diffusion solve and its latency floor, the cold bucketed apply,
+the 32-system launch, the power-law matrix, the gradient, adaptive SPAI,
+bucketed A, low-u_f SPAI).
 """
 import argparse
 import hashlib
@@ -25,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 VALUE_BYTES = {0: 8, 1: 4, 2: 2, 3: 2, 4: 1, 5: 0}
+GROUP = 4  # columns per step: the library's FP32 column group (16 bytes of u_g per row)
 
 
 def _log(*a):
@@ -84,33 +93,53 @@ def _traffic(kernel_src, record="solve_kernel_traffic.json"):
     return None
 
 
+def _converged(st):
+    """A solve counts as converged only when it met tol_rr or tol_be."""
+    return st["status"] == 0 and st["stop_reason"] in (1, 2)
+
+
+def _timed_solve(B, torch, Ad, b, h, reps, **kw):
+    B.solve(Ad, b, h, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, st = B.solve(Ad, b, h, **kw)
+    torch.cuda.synchronize()
+    return x, st, (time.perf_counter() - t0) / reps
+
+
+def _cols_summary(sts):
+    return {"its_col0": sts[0]["its"], "max_steps": max(q["steps"] for q in sts),
+            "max_relres": max(q["relres"][-1] for q in sts), "max_eta": max(q["eta"][-1] for q in sts),
+            "all_converged": all(_converged(q) for q in sts)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--gmres-max", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-apply-bench", action="store_true")
-    ap.add_argument("--no-comparators", action="store_true")
-    ap.add_argument("--no-batched", action="store_true",
-                    help="skip the 64-RHS and the 32-system measurements")
+    ap.add_argument("--no-secondary", action="store_true", help="only the headline (and its comparators)")
+    ap.add_argument("--no-comparators", action="store_true",
+                    help="the headline's timed steps only (no one-call and FP64 comparator runs): profiling")
     ap.add_argument("--only-apply", action="store_true", help="run only the cold bucketed-apply measurement")
-    ap.add_argument("--only-batched", action="store_true", help="run only the 64-RHS measurement")
+    ap.add_argument("--only-convdiff", action="store_true", help="run only the 256^2 convection-diffusion block")
     ap.add_argument("--only-multi", action="store_true", help="run only the 32-system measurement")
     ap.add_argument("--only-powerlaw", action="store_true", help="run only the power-law matrix measurement")
     ap.add_argument("--only-gradient", action="store_true", help="run only the 512^2 gradient measurement")
     ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive-SPAI measurement")
     ap.add_argument("--only-bucketed-a", action="store_true", help="run only the bucketed-A measurement")
     ap.add_argument("--only-low-uf", action="store_true", help="run only the low-u_f SPAI measurement")
+    ap.add_argument("--only-cpu-baseline", action="store_true", help="run only the oracle on the host")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy first (calibration of hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the solver is one persistent kernel per "
-                                   "system; run with --gpus 1"}), flush=True)
+        print(json.dumps({"error": "this build runs on one GPU only (every kernel works on one GPU's memory); "
+                                   "run with --gpus 1"}), flush=True)
         sys.exit(2)
 
     import numpy as np
@@ -131,13 +160,12 @@ def main():
         torch.cuda.synchronize()
         del a, b2
         torch.cuda.empty_cache()
-    if args.only_apply:
-        res = apply_bench(B, W, torch, np)
-        _emit(B, torch, {"m_apply": res})
-        return
     kw0 = dict(tau=1e-4, tol_rr=1e-10, gmres_max=args.gmres_max, i_max=20)
-    if args.only_batched:
-        _emit(B, torch, {"batched_rhs": batched_bench(B, W, torch, np, kw0)})
+    if args.only_apply:
+        _emit(B, torch, {"m_apply": apply_bench(B, W, torch, np)})
+        return
+    if args.only_convdiff:
+        _emit(B, torch, {"convdiff_256": convdiff_bench(B, W, torch, np, kw0, args.steps, args.warmup)})
         return
     if args.only_multi:
         _emit(B, torch, {"multi_system": multi_bench(B, W, torch, np, kw0)})
@@ -157,145 +185,214 @@ def main():
     if args.only_low_uf:
         _emit(B, torch, {"low_uf_spai": low_uf_bench(B, W, torch, np, kw0)})
         return
-    _log("generating workload")
+    if args.only_cpu_baseline:
+        _emit(B, torch, {"cpu_baseline": cpu_baseline(W, np, kw0, [150, 150, 150, 150])})
+        return
+
+    out, its_per_col = headline(B, W, torch, np, kw0, args.steps, args.warmup, not args.no_comparators)
+    if not args.no_secondary:
+        out["convdiff_256"] = convdiff_bench(B, W, torch, np, kw0, 20, 3)
+        out["m_apply"] = apply_bench(B, W, torch, np)
+        out["multi_system"] = multi_bench(B, W, torch, np, kw0)
+        out["powerlaw"] = powerlaw_bench(B, W, torch, np, kw0)
+        out["gradient"] = gradient_bench(B, W, torch, np)
+        out["adaptive_spai"] = adaptive_bench(B, W, torch, np, kw0)
+        out["bucketed_a"] = bucketed_a_bench(B, W, torch, np, kw0)
+        out["low_uf_spai"] = low_uf_bench(B, W, torch, np, kw0)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, np, kw0, its_per_col)
+    _emit(B, torch, out)
+
+
+def headline(B, W, torch, np, kw, steps, warmup, comparators=True):
+    """The 64-RHS 128^3 workload: K timed steps of one 4-column group each
+    (cycling over the 16 groups), the MGS kernel's roofline, and the all-FP64
+    SPAI-GMRES-IR comparator at the same stopping test."""
+    _log("headline: generating the 128^3 operator and 64 right-hand sides")
+    c = W.config("4a")
+    A, P = c["A"], c["P"]
+    n = A.n
+    Ad = B.CSRMatrix.from_host(A)
+    Pd = B.CSRMatrix.from_host(P)
+    Bm = torch.as_tensor(np.ascontiguousarray(c["b"]), device="cuda")
+    nr = Bm.shape[1]
+    groups = [Bm[:, k:k + GROUP].contiguous() for k in range(0, nr, GROUP)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = B.build(Ad, Pd, eps=c["eps"][0], precs=c["precs"])
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    mst = h.stats()
+    _log(f"built M: counts {mst['count']} storage {mst['storage_pct']:.1f}% in {build_s * 1e3:.0f} ms")
+    for w in range(warmup):
+        B.solve(Ad, groups[w % len(groups)], h, **kw)
+    torch.cuda.synchronize()
+    B.set_profiling(True)
+    B.batched_mgs_profile(reset=True)
+    sts_all = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _, sts = B.solve(Ad, groups[k % len(groups)], h, **kw)
+        sts_all.extend(sts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    B.set_profiling(False)
+    prof = B.batched_mgs_profile(reset=True)
+    rhs_per_s = GROUP * steps / elapsed
+    summ = _cols_summary(sts_all)
+    _log(f"BSPAI: {rhs_per_s:.2f} RHS/s ({elapsed * 1e3 / steps:.0f} ms per {GROUP}-column step), "
+         f"its {summ['its_col0']}, max relres {summ['max_relres']:.2e}, all converged {summ['all_converged']}")
+    mgs_gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    roofline = {"kernel": "k_b_mgs_persist (one Arnoldi step's MGS for a 4-column group)", "bound": "hbm",
+                "achieved": mgs_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": mgs_gbs / PEAK_HBM_GBS,
+                "traffic": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "solve.hip"),
+                                    "batched_mgs_traffic.json"),
+                "launches": prof["launches"], "avg_launch_us": 1e3 * prof["ms"] / max(1, prof["launches"]),
+                "algorithmic_bytes_per_launch": prof["bytes"] / max(1, prof["launches"]),
+                "kernel_share_of_step": prof["ms"] * 1e-3 / elapsed}
+    out = {"metric": "GMRES-IR solves/s & M-apply HBM GB/s, BSPAI vs fp64 SPAI at equal backward error",
+           "value": rhs_per_s, "unit": "RHS solves/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"aniso3d 128^3 7-point 1:10:100 (n={n}), {nr} RHS N(0,1) sharing one BSPAI M "
+                                  f"(SPAI pattern(A) FP64, buckets fp32/fp16/bf16 eps=1e-2), u_g=u_p=fp32, "
+                                  f"u_r=double-double, tau=1e-4, refine to 1e-10 rel. residual, GMRES cap "
+                                  f"{kw['gmres_max']}; a step solves one {GROUP}-column group, cycling over the "
+                                  f"{nr // GROUP} groups",
+                      "n": n, "nnz_A": A.nnz, "nnz_M": int(sum(mst["count"])), "bucket_counts": mst["count"],
+                      "storage_pct": mst["storage_pct"], "rhs": nr, "columns_per_step": GROUP},
+           "solve": dict(summ, build_ms=build_s * 1e3),
+           "roofline": roofline}
+
+    if not comparators:
+        h.free()
+        return out, sts_all[0]["its"]
+    # the same 64 columns in one call (the library runs its 16 groups)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sts = B.solve(Ad, Bm, h, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["one_call_64_rhs"] = dict(_cols_summary(sts), s_per_call=el, rhs_per_s=nr / el)
+    _log(f"one call, 64 RHS: {el:.2f} s ({nr / el:.2f} RHS/s)")
+
+    # comparators at the same stopping test: the all-FP64 SPAI-GMRES-IR (one
+    # fp64 bucket, u_g = u_p = fp64, tau = 1e-8) and the FP64 M with the FP32
+    # Krylov solve (isolates the bucketing)
+    ex = h.export()
+    Md = B.CSRMatrix.from_host(W.CSR(n, P.row_ptr, P.col, ex["m64"]))
+    h64 = B.import_m(Md, 2.0 ** -53, ["fp64"], build_T=False)
+    del Md, ex
+    comps = {}
+    for name, extra, reps in (("spai_fp64_all", dict(u_g="fp64", tau=1e-8), 3),
+                              ("spai_fp64M_fp32krylov", {}, 3)):
+        k2 = dict(kw, **extra)
+        B.solve(Ad, groups[0], h64, **k2)
+        torch.cuda.synchronize()
+        sts_c = []
+        t0 = time.perf_counter()
+        for k in range(reps):
+            _, sts = B.solve(Ad, groups[k % len(groups)], h64, **k2)
+            sts_c.extend(sts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        comps[name] = dict(_cols_summary(sts_c), rhs_per_s=GROUP * reps / el, rhs_timed=GROUP * reps)
+        _log(f"{name}: {GROUP * reps / el:.2f} RHS/s, its {sts_c[0]['its']}, max eta {comps[name]['max_eta']:.2e}")
+    h64.free()
+    out["comparators"] = comps
+    out["speedup_vs_fp64_spai"] = rhs_per_s / comps["spai_fp64_all"]["rhs_per_s"]
+    h.free()
+    del groups, Bm
+    torch.cuda.empty_cache()
+    its_per_col = sts_all[0]["its"]
+    return out, its_per_col
+
+
+def convdiff_bench(B, W, torch, np, kw, steps, warmup):
+    """The 256 x 256 upwind convection-diffusion system (n = 65,536, Peclet
+    50), SPAI on the pattern of A^2 in FP64, buckets {fp64, fp32, fp16, bf16}
+    at eps_b = 1e-4, b = A x_true: solves/s of the persistent single-system
+    solver, its roofline and latency floor, comparators and the eps_b sweep."""
     c = W.config("2")
     A, P = c["A"], c["P"]
     n = A.n
     Ad = B.CSRMatrix.from_host(A)
     Pd = B.CSRMatrix.from_host(P)
-    b = torch.as_tensor(c["b"], device=dev)
+    b = torch.as_tensor(c["b"], device="cuda")
     precs = c["precs"]
-    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=args.gmres_max, i_max=20)
-
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = B.build(Ad, Pd, eps=args.eps, precs=precs)
+    h = B.build(Ad, Pd, eps=1e-4, precs=precs)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     mst = h.stats()
-    _log(f"built M: counts {mst['count']} storage {mst['storage_pct']:.1f}% in {build_ms:.1f} ms")
-
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         x, st = B.solve(Ad, b, h, **kw)
     torch.cuda.synchronize()
     B.set_profiling(True)
     kernel_ms = []
-    stats = None
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         x, stats = B.solve(Ad, b, h, **kw)
         kernel_ms.append(B.last_solve_kernel_ms())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     B.set_profiling(False)
-    ms_per_step = elapsed * 1e3 / args.steps
-    solves_per_s = args.steps / elapsed
+    solves_per_s = steps / elapsed
     xh = x.cpu().numpy()
     fwd = float(np.abs(xh - c["x_true"]).max() / np.abs(c["x_true"]).max())
-    _log(f"BSPAI: {solves_per_s:.2f} solves/s, its {stats['its']}, relres {stats['relres'][-1]:.2e}")
-
+    _log(f"convdiff 256^2: {solves_per_s:.2f} solves/s, its {stats['its']}, relres {stats['relres'][-1]:.2e}")
     kern_ms = float(np.mean(kernel_ms))
     nbytes = solve_bytes(stats, n, A.nnz, mst)
-    kernel_src = os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "solve.hip")
-    roofline = {"kernel": "k_gmres_ir (persistent solver)", "bound": "hbm",
-                "achieved": nbytes / (kern_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": nbytes / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "traffic": _traffic(kernel_src),
-                "algorithmic_bytes": nbytes, "kernel_ms": kern_ms}
-
-    # the latency bound of the persistent solver: its dependent grid-wide
-    # exchanges (each MGS pass and norm is an all-reduction, each published
-    # vector a barrier) times the measured cost of one exchange
     G = B.solve_blocks(n)
     ex_us = B.exchange_latency_us(G)
     n_ex = 3 + sum(6 + sum(j + 4 for j in range(k)) for k in stats["its"])
-    latency = {"blocks": G, "exchange_us": ex_us, "exchanges_per_solve": n_ex,
-               "floor_ms": n_ex * ex_us * 1e-3, "frac": n_ex * ex_us * 1e-3 / kern_ms}
+    res = {"workload": "convdiff2d 256x256 upwind Pe=50 (n=65536), SPAI pattern(A^2) FP64, buckets "
+                       "fp64/fp32/fp16/bf16 eps=1e-4, u_g=u_p=fp32, u_r=double-double, tau=1e-4, refine to 1e-10",
+           "solves_per_s": solves_per_s, "ms_per_solve": elapsed * 1e3 / steps, "steps": steps,
+           "bucket_counts": mst["count"], "storage_pct": mst["storage_pct"], "its": stats["its"],
+           "relres": stats["relres"][-1], "eta": stats["eta"][-1], "forward_error": fwd,
+           "converged": _converged(stats), "build_ms": build_ms,
+           "roofline": {"kernel": "k_gmres_ir (persistent solver)", "bound": "hbm",
+                        "achieved": nbytes / (kern_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": nbytes / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                        "traffic": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "solve.hip")),
+                        "algorithmic_bytes": nbytes, "kernel_ms": kern_ms},
+           "latency_floor": {"blocks": G, "exchange_us": ex_us, "exchanges_per_solve": n_ex,
+                             "floor_ms": n_ex * ex_us * 1e-3, "frac": n_ex * ex_us * 1e-3 / kern_ms}}
     _log(f"latency floor: {n_ex} exchanges x {ex_us:.2f} us = {n_ex * ex_us * 1e-3:.1f} ms "
-         f"({100 * latency['frac']:.0f}% of the kernel time)")
-    roofline["latency_floor"] = latency
-
-    out = {"metric": "GMRES-IR solves/s & M-apply HBM GB/s, BSPAI vs fp64 SPAI at equal backward error",
-           "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "fp32", "data": "synthetic",
-           "config": {"workload": f"convdiff2d 256x256 upwind Pe=50 (n=65536), SPAI pattern(A^2) FP64, "
-                                  f"buckets fp64/fp32/fp16/bf16 eps={args.eps:g}, u_g=u_p=fp32, u_r=double-double, "
-                                  f"tau=1e-4, refine to 1e-10 rel. residual, GMRES cap {args.gmres_max}",
-                      "n": n, "nnz_A": A.nnz, "nnz_M": int(sum(mst["count"])), "bucket_counts": mst["count"],
-                      "storage_pct": mst["storage_pct"]},
-           "solve": {"its": stats["its"], "its_total": stats["its_total"], "relres": stats["relres"][-1],
-                     "eta": stats["eta"][-1], "forward_error": fwd, "build_ms": build_ms},
-           "roofline": roofline}
-
-    if not args.no_comparators:
-        # all-FP64 SPAI-GMRES-IR (u_g = u_p = fp64, tau = 1e-8, one fp64 bucket) at the same stopping test,
-        # and the fp64 M with FP32 Krylov (isolates the effect of bucketing)
-        comps = {}
-        h64 = B.build(Ad, Pd, eps=2.0 ** -53, precs=["fp64"])
-        for name, hh, extra in (("spai_fp64_all", h64, dict(u_g="fp64", tau=1e-8)),
-                                ("spai_fp64M_fp32krylov", h64, {}),
-                                ("bspai_cgs2", h, dict(orth="cgs2"))):
-            k2 = dict(kw)
-            k2.update(extra)
-            for _ in range(2):
-                x2, s2 = B.solve(Ad, b, hh, **k2)
-            reps = max(3, args.steps // 4)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(reps):
-                x2, s2 = B.solve(Ad, b, hh, **k2)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t1
-            comps[name] = {"solves_per_s": reps / el, "its": s2["its"], "relres": s2["relres"][-1],
-                           "eta": s2["eta"][-1]}
-            _log(f"{name}: {reps / el:.2f} solves/s its {s2['its']}")
-        out["comparators"] = comps
-        # the workload's sweep over eps_b: occupancy, storage and iterations
-        # per eps against the unbucketed fp64 SPAI (plain SPAI-GMRES-IR with
-        # the same fp32 Krylov)
-        sweep = []
-        for eps in (1e-6, 1e-4, 1e-2):
-            he = B.build(Ad, Pd, eps=eps, precs=precs)
-            se = he.stats()
-            B.solve(Ad, b, he, **kw)
-            torch.cuda.synchronize()
-            reps = 3
-            t1 = time.perf_counter()
-            for _ in range(reps):
-                xe, ste = B.solve(Ad, b, he, **kw)
-            torch.cuda.synchronize()
-            el = (time.perf_counter() - t1) / reps
-            sweep.append({"eps": eps, "bucket_counts": se["count"], "storage_pct": se["storage_pct"],
-                          "its": ste["its"], "its_total": ste["its_total"], "eta": ste["eta"][-1],
-                          "relres": ste["relres"][-1], "solves_per_s": 1.0 / el})
-            he.free()
-            _log(f"eps {eps:g}: counts {se['count']} storage {se['storage_pct']:.1f}% its {ste['its']} "
-                 f"{1.0 / el:.2f} solves/s")
-        out["eps_sweep"] = {"plain_spai_its": comps["spai_fp64M_fp32krylov"]["its"], "points": sweep}
-        h64.free()
-
-    if not args.no_apply_bench:
-        out["m_apply"] = apply_bench(B, W, torch, np)
-
-    if not args.no_batched:
-        out["multi_system"] = multi_bench(B, W, torch, np, kw)
-        out["batched_rhs"] = batched_bench(B, W, torch, np, kw)
-        out["powerlaw"] = powerlaw_bench(B, W, torch, np, kw)
-        out["gradient"] = gradient_bench(B, W, torch, np)
-        out["adaptive_spai"] = adaptive_bench(B, W, torch, np, kw)
-        out["bucketed_a"] = bucketed_a_bench(B, W, torch, np, kw)
-        out["low_uf_spai"] = low_uf_bench(B, W, torch, np, kw)
-
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c, args.eps, kw)
-
-    # every device object is released before the interpreter exits (a free
-    # during interpreter shutdown could run after the HIP runtime's teardown)
+         f"({100 * n_ex * ex_us * 1e-3 / kern_ms:.0f}% of the kernel time)")
+    # the exchange with the blocks on one XCD against the dispatcher's spread
+    place = {}
+    for G2 in (16, 32):
+        one, xo = B.exchange_latency_placed_us(G2, True)
+        spread, _ = B.exchange_latency_placed_us(G2, False)
+        place[str(G2)] = {"one_xcd_us": one, "spread_us": spread, "xcds_one": sorted(set(xo))}
+    res["exchange_placement"] = place
+    comps = {}
+    h64 = B.build(Ad, Pd, eps=2.0 ** -53, precs=["fp64"])
+    for name, hh, extra in (("spai_fp64_all", h64, dict(u_g="fp64", tau=1e-8)),
+                            ("spai_fp64M_fp32krylov", h64, {}),
+                            ("bspai_cgs2", h, dict(orth="cgs2"))):
+        _, s2, el = _timed_solve(B, torch, Ad, b, hh, 5, **dict(kw, **extra))
+        comps[name] = {"solves_per_s": 1.0 / el, "its": s2["its"], "relres": s2["relres"][-1], "eta": s2["eta"][-1],
+                       "converged": _converged(s2)}
+        _log(f"{name}: {1.0 / el:.2f} solves/s its {s2['its']}")
+    h64.free()
+    res["comparators"] = comps
+    sweep = []
+    for eps in (1e-6, 1e-4, 1e-2):
+        he = B.build(Ad, Pd, eps=eps, precs=precs)
+        se = he.stats()
+        _, ste, el = _timed_solve(B, torch, Ad, b, he, 3, **kw)
+        sweep.append({"eps": eps, "bucket_counts": se["count"], "storage_pct": se["storage_pct"], "its": ste["its"],
+                      "its_total": ste["its_total"], "eta": ste["eta"][-1], "relres": ste["relres"][-1],
+                      "converged": _converged(ste), "solves_per_s": 1.0 / el})
+        he.free()
+    res["eps_sweep"] = {"plain_spai_its": comps["spai_fp64M_fp32krylov"]["its"], "points": sweep}
     h.free()
-    B.release_workspace()
-    torch.cuda.synchronize()
-    print(json.dumps(out), flush=True)
+    return res
 
 
 def multi_bench(B, W, torch, np, kw, replays=3):
@@ -363,62 +460,6 @@ def multi_bench(B, W, torch, np, kw, replays=3):
     return res
 
 
-def batched_bench(B, W, torch, np, kw):
-    """64 right-hand sides of the 128^3 anisotropic diffusion operator in one
-    gmres_ir_solve call (one timed call), against column 0 alone."""
-    c = W.config("4a")
-    A = c["A"]
-    Ad = B.CSRMatrix.from_host(A)
-    h = B.build(Ad, B.CSRMatrix.from_host(c["P"]), eps=c["eps"][0], precs=c["precs"])
-    Bm = torch.as_tensor(np.ascontiguousarray(c["b"]), device="cuda")
-    b0 = Bm[:, 0].contiguous()
-    B.solve(Ad, b0, h, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x1, s1 = B.solve(Ad, b0, h, **kw)
-    torch.cuda.synchronize()
-    single = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    x, sts = B.solve(Ad, Bm, h, **kw)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    nr = Bm.shape[1]
-    # the MGS passes of the call: a correction runs as many Arnoldi steps as
-    # its slowest column; step j makes j + 2 passes over n x R values of u_g:
-    # z and v_0 read; z, v_{i-1}, v_i read and z written; z and v_j read and
-    # z written
-    steps = max(q["steps"] for q in sts)
-    per_step = [max(q["its"][i] for q in sts if q["steps"] > i) for i in range(steps)]
-    vec = A.n * nr * 4
-    mgs_passes = sum(j + 2 for k in per_step for j in range(k))
-    mgs_bytes = sum((4 * j + 5) * vec for k in per_step for j in range(k))
-    res = {"workload": f"aniso3d 128^3 (1:10:100, n={A.n}), {nr} RHS N(0,1), buckets fp32/bf16/fp16 eps=1e-2",
-           "rhs_per_s": nr / el, "s_per_call": el, "single_rhs_per_s": 1.0 / single,
-           "arnoldi_steps_per_correction": per_step, "mgs_passes": mgs_passes, "mgs_algorithmic_bytes": mgs_bytes,
-           "its_col0": sts[0]["its"], "max_steps": max(q["steps"] for q in sts),
-           "max_relres": max(q["relres"][-1] for q in sts), "all_converged": all(q["status"] == 0 for q in sts)}
-    del x, Bm
-    h.free()
-    torch.cuda.empty_cache()
-    _log(f"batched: {res['rhs_per_s']:.2f} rhs/s vs single {res['single_rhs_per_s']:.2f}")
-    return res
-
-
-def _converged(st):
-    """A solve counts as converged only when it met tol_rr or tol_be."""
-    return st["status"] == 0 and st["stop_reason"] in (1, 2)
-
-
-def _timed_solve(B, torch, Ad, b, h, reps, **kw):
-    B.solve(Ad, b, h, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        x, st = B.solve(Ad, b, h, **kw)
-    torch.cuda.synchronize()
-    return x, st, (time.perf_counter() - t0) / reps
-
-
 def _bucket_damage(P, ex, q):
     """Entries that a bucket's format flushed to zero (stored 0, FP64 value not
     0), per bucket, and the zero diagonal entries of M_b."""
@@ -478,7 +519,7 @@ def powerlaw_bench(B, W, torch, np, kw, reps=50):
     kws = dict(kw, tol_rr=0.0, tol_be=2.0 ** -51)
     Md = B.CSRMatrix.from_host(W.CSR(n, P.row_ptr, P.col, ex["m64"]))
     points = []
-    for eps in (1e-6, 1e-5, 1e-4, 1e-3):
+    for eps in (1e-9, 1e-8, 1e-7, 1e-6, 1e-5, 1e-3):
         he = B.import_m(Md, eps, c["precs"], build_T=False)
         se = he.stats()
         flushed, zdiag = _bucket_damage(P, he.export(), se["q"])
@@ -669,23 +710,12 @@ def low_uf_bench(B, W, torch, np, kw, reps=5):
     return res
 
 
-def apply_bench(B, W, torch, np):
-    """bspai_apply on the 128^3 anisotropic operator (n = 2,097,152, M on the
-    pattern of A, all entries in the bf16 bucket at eps = 1e-2), cold in HBM:
-    the product rotates over 8 copies of M and of x/y (about 0.9 GB)."""
-    _log("apply bench: building 128^3 operator")
-    c = W.config("4a")
-    A = c["A"]
-    Ad = B.CSRMatrix.from_host(A)
-    h0 = B.build(Ad, B.CSRMatrix.from_host(c["P"]), eps=1e-2, precs=c["precs"], build_T=False, keep_fp64_M=True)
-    ex = h0.export()
-    h0.free()
-    M = W.CSR(A.n, c["P"].row_ptr, c["P"].col, ex["m64"])
-    Md = B.CSRMatrix.from_host(M)
-    copies = 8
-    hs = [B.import_m(Md, 1e-2, c["precs"], build_T=False, keep_fp64_M=False) for _ in range(copies)]
+def _apply_cold(B, torch, Md, precs, eps, n, copies=8):
+    """Cold bspai_apply: the product rotates over `copies` independently
+    bucketed copies of M and of x/y (more than the 256 MiB Infinity Cache),
+    launches replayed from a captured graph."""
+    hs = [B.import_m(Md, eps, precs, build_T=False, keep_fp64_M=False) for _ in range(copies)]
     st = hs[0].stats()
-    n = A.n
     xs = [torch.randn(n, device="cuda", dtype=torch.float32) for _ in range(copies)]
     ys = [torch.empty(n, device="cuda", dtype=torch.float32) for _ in range(copies)]
     nb = sum(1 for cc, p in zip(st["count"], st["precs"]) if cc > 0 and p != 5)
@@ -703,8 +733,6 @@ def apply_bench(B, W, torch, np):
     torch.cuda.synchronize()
     reps = int(os.environ.get("BSPAI_APPLY_REPS", "200"))
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    # launches captured in a graph: the replay times the kernels, not the
-    # Python-side call overhead of each apply
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
@@ -723,46 +751,112 @@ def apply_bench(B, W, torch, np):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    # the same launches issued one by one from Python, for reference
-    e0.record()
-    for r in range(reps):
-        B.apply(hs[r % copies], xs[r % copies], ys[r % copies])
-    e1.record()
-    torch.cuda.synchronize()
-    ms_eager = e0.elapsed_time(e1) / reps
+    del graph
     for hh in hs:
         hh.free()
     gbs = bytes_per / (ms * 1e-3) / 1e9
-    _log(f"apply: {ms * 1e3:.1f} us per launch, {gbs:.0f} GB/s (issued from Python one by one: {ms_eager * 1e3:.1f} us)")
-    return {"workload": "aniso3d 128^3 7-point (n=2097152), M on pattern(A), bf16 bucket (eps=1e-2), fp32 x/y, "
-                        "8 rotating copies (cold HBM), launches replayed from a captured graph", "bucket_counts": st["count"],
-            "us_per_launch": ms * 1e3, "us_per_launch_python_issued": ms_eager * 1e3,
-            "algorithmic_bytes": bytes_per, "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
+    _log(f"apply eps {eps:g}: counts {st['count']}, {ms * 1e3:.1f} us per launch, {gbs:.0f} GB/s algorithmic, "
+         f"{moved / (ms * 1e-3) / 1e9:.0f} GB/s of stored bytes")
+    return {"eps": eps, "bucket_counts": st["count"], "us_per_launch": ms * 1e3, "algorithmic_bytes": bytes_per,
+            "achieved_GBs": gbs, "frac_of_peak": gbs / PEAK_HBM_GBS,
             "bytes_per_nnz": bytes_per / max(1, sum(st["count"])), "ell_width": st["ell_width"],
-            "col_bytes": st["col_bytes"], "moved_bytes": moved, "moved_GBs": moved / (ms * 1e-3) / 1e9,
-            "traffic": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "apply.hip"),
-                                "apply_kernel_traffic.json")}
+            "col_bytes": st["col_bytes"], "apply_kind": st["apply_kind"], "moved_bytes": moved,
+            "moved_GBs": moved / (ms * 1e-3) / 1e9, "moved_frac_of_peak": moved / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
 
 
-def cpu_baseline(c, eps, kw):
-    """The CPU oracle (plain C, OpenMP over rows, sequential dot products
-    accumulated in FP64, the realisation the GPU computes) on the same
-    workload: one full solve from the FP64 SPAI (SPAI build not timed)."""
+def apply_bench(B, W, torch, np):
+    """bspai_apply on the 128^3 anisotropic operator (n = 2,097,152, M on the
+    pattern of A), cold in HBM: at eps_b = 1e-2 (every entry in the bf16
+    bucket) and at 1e-4 (fp32, fp16 and bf16 buckets all non-empty).  Two
+    rates: algorithmic bytes (an int32 column per entry) and the bytes the
+    product's copies actually hold (1-byte column codes where they apply);
+    the counters' HBM traffic is recorded for the single-bucket case."""
+    _log("apply bench: building 128^3 operator")
+    c = W.config("4a")
+    A = c["A"]
+    Ad = B.CSRMatrix.from_host(A)
+    h0 = B.build(Ad, B.CSRMatrix.from_host(c["P"]), eps=1e-2, precs=c["precs"], build_T=False, keep_fp64_M=True)
+    ex = h0.export()
+    h0.free()
+    Md = B.CSRMatrix.from_host(W.CSR(A.n, c["P"].row_ptr, c["P"].col, ex["m64"]))
+    res = {"workload": "aniso3d 128^3 7-point (n=2097152), M on pattern(A), buckets fp32/fp16/bf16, fp32 x/y, "
+                       "8 rotating copies (cold HBM), launches replayed from a captured graph",
+           "points": [_apply_cold(B, torch, Md, c["precs"], eps, A.n) for eps in (1e-2, 1e-4)],
+           "traffic_eps_1e-2": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "apply.hip"),
+                                        "apply_kernel_traffic.json")}
+    del Md
+    return res
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, np, kw, its_per_col):
+    """The CPU oracle (plain C, OpenMP over rows, dot products sequential and
+    accumulated in FP64, the realisation the GPU computes) on the headline
+    workload, one column.  A full solve of one column is 4 corrections of
+    ~150 GMRES iterations (minutes on the host), so the sample is bounded:
+    MGS-GMRES corrections of 20 and 40 iterations on M_b A d = M_b r fix
+    t(k) = a k + b k (k + 1) / 2 (the products per iteration, the
+    Gram-Schmidt growing with k), which is summed over the column's GPU
+    iteration counts.  The 1-thread figure fits corrections of 10 and 20
+    iterations at 1 thread.  Also the oracle's bucketed apply on the same M."""
     import oracle as O
-    import workloads as W
 
+    c = W.config("4a")
     A, P = c["A"], c["P"]
     threads = O.num_threads(0)
     st, Mv, _ = O.spai(A, P)
     M = W.CSR(A.n, P.row_ptr, P.col, Mv)
-    Mb = O.Bucketed(M, eps, c["precs"])
+    Mb = O.Bucketed(M, c["eps"][0], c["precs"])
+    r = np.ascontiguousarray(c["b"][:, 0])
+    # the oracle's M-apply rate (FP64-mode product of the stored values)
+    x = np.random.default_rng(0).standard_normal(A.n)
+    O.apply(Mb, x)
     t0 = time.perf_counter()
-    res = O.gmres_ir(A, M, Mb, c["b"], dot64=True, **kw)
-    el = time.perf_counter() - t0
-    _log(f"oracle: {el:.1f} s per solve on {threads} threads, its {res['its']}")
-    return {"value": 1.0 / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"one full solve of the same workload (its {res['its']}, {el:.1f} s)",
-            "eta": res["eta"][-1]}
+    for _ in range(3):
+        O.apply(Mb, x)
+    t_apply = (time.perf_counter() - t0) / 3
+    nb = sum(1 for cc in Mb.counts if cc > 0)
+    alg = sum(int(cc) * (VALUE_BYTES[p] + 4) for cc, p in zip(Mb.counts, Mb.precs)) + 4 * (A.n + 1) * nb + 8 * A.n
+
+    def timed(k):
+        t0 = time.perf_counter()
+        g = O.gmres(A, Mb, r, tau=0.0, max_it=k, dot64=True)
+        assert g["its"] == k, g["its"]
+        return time.perf_counter() - t0
+
+    def per_rhs(k1, k2):
+        t1, t2 = timed(k1), timed(k2)
+        q = lambda k: k * (k + 1) / 2.0
+        det = k1 * q(k2) - k2 * q(k1)
+        a = (t1 * q(k2) - t2 * q(k1)) / det
+        b = (k1 * t2 - k2 * t1) / det
+        return sum(a * k + b * q(k) for k in its_per_col), (t1, t2)
+
+    sec, (t20, t40) = per_rhs(20, 40)
+    O.num_threads(1)
+    sec1, (t10_1, t20_1) = per_rhs(10, 20)
+    O.num_threads(threads)
+    _log(f"oracle: 20/40 iterations {t20:.1f}/{t40:.1f} s on {threads} threads -> {sec:.0f} s per RHS; 1 thread "
+         f"10/20 iterations {t10_1:.1f}/{t20_1:.1f} s -> {sec1:.0f} s per RHS; apply {t_apply * 1e3:.0f} ms")
+    return {"value": 1.0 / sec, "unit": "RHS solves/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"one column of the 128^3 64-RHS workload: GMRES corrections of 20 and 40 iterations "
+                      f"({t20:.1f} s, {t40:.1f} s on {threads} threads) fitting t(k) = a k + b k(k+1)/2, summed "
+                      f"over the column's GPU iteration counts {its_per_col}",
+            "value_1_thread": 1.0 / sec1,
+            "sample_1_thread": f"corrections of 10 and 20 iterations on 1 thread ({t10_1:.1f} s, {t20_1:.1f} s), "
+                               f"the same fit",
+            "apply_GBs": alg / t_apply / 1e9, "apply_ms": t_apply * 1e3}
 
 
 if __name__ == "__main__":

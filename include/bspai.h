@@ -77,8 +77,8 @@ typedef struct {
     int keep_fp64_M; /* keep the unbucketed FP64 M on the device (x_0 = M b, Algorithm 4 step 2) */
     int scale;       /* one-sided column scaling of A^T before the least squares (Section 4) */
     bspai_prec u_f;  /* precision of the SPAI least squares (Section 4's settings): BSPAI_FP64 (0,
-                      * the default), BSPAI_FP32 or BSPAI_FP16; see bspai_build.  Ignored by
-                      * bspai_import; bspai_build_adaptive takes FP64 only */
+                      * the default), BSPAI_FP32 or BSPAI_FP16; see bspai_build and
+                      * bspai_build_adaptive.  Ignored by bspai_import */
 } bspai_opts;
 
 typedef struct bspai_handle bspai_handle;
@@ -296,7 +296,13 @@ int bspai_multi_group_blocks(const bspai_multi *plan);
  * Limits: initial entries + alpha * beta <= 64 per row; at most 4096 shadow
  * rows and 4096 distinct candidates per round (EINVAL names the row).
  * steps_host: NULL or a host array of n ints (least squares solves per row).
- * Errors: EZEROROW, ERANK, EINVAL, ENOMEM, EHIP.  Synchronises `stream`.
+ * opts->u_f (FP64, FP32 or FP16; Section 4's double, single and half
+ * settings) and opts->scale: every least squares solve is then that of
+ * bspai_build with the same u_f and scaling (the reduced matrix rounded to
+ * u_f, the QR and back substitution in u_f, M's values m_c d_c rounded to
+ * u_f); the residual and the candidate scores are formed in FP64 from the
+ * unscaled A and those values.  An overflow of u_f (use scale) is ENAN.
+ * Errors: EZEROROW, ERANK, EINVAL, ENOMEM, EHIP, ENAN.  Synchronises `stream`.
  */
 typedef struct {
     int alpha;      /* augmentation rounds: at most alpha + 1 solves per row */
@@ -385,8 +391,8 @@ double bspai_last_solve_kernel_ms(void);
  * right-hand sides times each launch of its one-launch MGS kernel (see
  * bspai_set_batch_mode) with HIP events on its stream; this returns the
  * totals since the last reset: milliseconds, launches and algorithmic bytes
- * ((j + 3) n c values of u_g for step j of a c-column group: v_0..v_j and z
- * read, v_{j+1} written).  Any pointer may be NULL; reset clears them. */
+ * ((j + 2) n c values of u_g for step j of a c-column group: v_0..v_j read,
+ * v_{j+1} written).  Any pointer may be NULL; reset clears them. */
 void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes);
 
 /*
@@ -398,8 +404,9 @@ void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches,
  *      each refined on its own; the Arnoldi step's whole MGS is one
  *      cooperative kernel that keeps the group's z in registers and reads
  *      each basis vector once (n <= 2,097,152).
- *   0 (default): mode 2 when it applies and n nrhs values of u_g fill at
- *      least 64 MiB (there the passes are bound by bytes moved), else mode 1.
+ *   0 (default): mode 2 when it applies and either n nrhs values of u_g
+ *      fill at least 64 MiB (there the passes are bound by bytes moved) or
+ *      there are at most four groups, else mode 1.
  * Both modes compute the same arithmetic per column (the same MGS passes,
  * FP64 partial sums) and differ only in the order of the partial sums.
  * Process-wide setting; EINVAL for another value.

@@ -357,13 +357,15 @@ _lib.bspai_export_pattern.restype = C.c_int
 
 def build_adaptive(A: CSRMatrix, J0: Optional[CSRMatrix] = None, alpha: int = 5, beta: int = 8,
                    eps_spai: float = 0.4, eps: float = 1e-4, precs: Sequence = ("fp64",), build_T: bool = True,
-                   keep_fp64_M: bool = True, stream=None):
+                   keep_fp64_M: bool = True, u_f: str = "fp64", scale: bool = False, stream=None):
     """SPAI with Algorithm 1's augmentation loop (bspai_build_adaptive), then
-    bucketing.  J0 None: identity start.  Returns (Handle, steps per row)."""
+    bucketing.  J0 None: identity start.  u_f: precision of the least squares
+    solves ("fp64", "fp32", "fp16"; use scale=True below fp64).  Returns
+    (Handle, steps per row)."""
     import numpy as np
 
     ids, q = _prec_ids(precs)
-    o = _opts(build_T, keep_fp64_M, False)
+    o = _opts(build_T, keep_fp64_M, scale, u_f)
     ad = _AdOpts(int(alpha), int(beta), float(eps_spai))
     out = _vp()
     steps = np.zeros(A.n, dtype=np.int32)

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -1488,6 +1489,12 @@ struct Row16<float> {
   __device__ static void store(float *p, const float (&v)[4]) {
     *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
   }
+  __device__ static void unpack(const unsigned (&u)[4], float (&v)[4]) {
+    for (int c = 0; c < 4; c++) v[c] = __uint_as_float(u[c]);
+  }
+  __device__ static void pack(const float (&v)[4], unsigned (&u)[4]) {
+    for (int c = 0; c < 4; c++) u[c] = __float_as_uint(v[c]);
+  }
 };
 template <>
 struct Row16<double> {
@@ -1498,17 +1505,50 @@ struct Row16<double> {
   __device__ static void store(double *p, const double (&v)[2]) {
     *reinterpret_cast<double2 *>(p) = make_double2(v[0], v[1]);
   }
+  __device__ static void unpack(const unsigned (&u)[4], double (&v)[2]) {
+    for (int c = 0; c < 2; c++)
+      v[c] = __longlong_as_double((long long)(((unsigned long long)u[2 * c + 1] << 32) | u[2 * c]));
+  }
+  __device__ static void pack(const double (&v)[2], unsigned (&u)[4]) {
+    for (int c = 0; c < 2; c++) {
+      const unsigned long long b = (unsigned long long)__double_as_longlong(v[c]);
+      u[2 * c] = (unsigned)b, u[2 * c + 1] = (unsigned)(b >> 32);
+    }
+  }
 };
 
+// A buffer resource over `bytes` bytes at p (raw: no stride, no swizzle):
+// loads through it take a uniform row offset in an SGPR and the thread's
+// offset in one VGPR, instead of a 64-bit address per row.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const void *p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename VT, int C>
+__device__ __forceinline__ void load_row16(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, VT (&o)[C]) {
+  const auto w = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+  const unsigned u[4] = {w[0], w[1], w[2], w[3]};
+  Row16<VT>::unpack(u, o);
+}
+
+template <typename VT, int C>
+__device__ __forceinline__ void store_row16(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, const VT (&v)[C]) {
+  unsigned u[4];
+  Row16<VT>::pack(v, u);
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 w = {u[0], u[1], u[2], u[3]};
+  __builtin_amdgcn_raw_buffer_store_b128(w, rs, voff, soff, 0);
+}
+
 // Sum over the grid of the C column values `part` (per thread); every block
-// obtains the same bits.  Wave c < C collects column c: lane l adds the
-// partials of blocks l, l + 64, ... in that order, issuing all of its loads
-// before checking any tag.  Returns false when a wait exceeds the bound or a
-// block aborted.
+// obtains the same bits.  Two halves, so that a caller can issue independent
+// loads while the other blocks' partials arrive: mgs_post publishes this
+// block's sums, mgs_collect waits for all of them.  Wave c < C collects column
+// c: lane l adds the partials of blocks l, l + 64, ... in that order, issuing
+// all of its loads before checking any tag.
 template <int C>
-__device__ bool mgs_grid_sum(const MgsGrid &g, unsigned &rtag, double (&part)[C], double *wpart, double *res) {
-  constexpr int K = kMaxBlocks / 64;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, G = gridDim.x;
+__device__ void mgs_post(const MgsGrid &g, unsigned &rtag, const double (&part)[C], double *wpart) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < C; c++) {
     const double w = wave_sum_dpp(part[c]);
@@ -1516,13 +1556,22 @@ __device__ bool mgs_grid_sum(const MgsGrid &g, unsigned &rtag, double (&part)[C]
   }
   lds_barrier();
   rtag++;
-  const unsigned long long tg = tag16(rtag);
   unsigned long long *set = g.slots + (size_t)(rtag % kNumSlots) * kMaxBlocks * kMgsCols * 2;
   if (threadIdx.x < C) {
     double a = wpart[threadIdx.x];
     for (int k = 1; k < kWaves; k++) a += wpart[k * C + threadIdx.x];
     publish_partial(set + ((size_t)blockIdx.x * kMgsCols + threadIdx.x) * 2, a, rtag);
   }
+}
+
+// Returns false (and raises the abort flag) when a wait exceeds the bound or
+// a block aborted; otherwise part holds the grid sums.
+template <int C>
+__device__ bool mgs_collect(const MgsGrid &g, unsigned rtag, double (&part)[C], double *res) {
+  constexpr int K = kMaxBlocks / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, G = gridDim.x;
+  const unsigned long long tg = tag16(rtag);
+  const unsigned long long *set = g.slots + (size_t)(rtag % kNumSlots) * kMaxBlocks * kMgsCols * 2;
   int bad = 0;
   if (wv < C) {
     unsigned long long a[K], b[K];
@@ -1532,7 +1581,7 @@ __device__ bool mgs_grid_sum(const MgsGrid &g, unsigned &rtag, double (&part)[C]
       for (int k = 0; k < K; k++) {
         const int blk = lane + 64 * k;
         if (blk < G) {
-          unsigned long long *w = set + ((size_t)blk * kMgsCols + wv) * 2;
+          const unsigned long long *w = set + ((size_t)blk * kMgsCols + wv) * 2;
           a[k] = __hip_atomic_load(&w[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           b[k] = __hip_atomic_load(&w[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1573,44 +1622,49 @@ __device__ bool mgs_grid_sum(const MgsGrid &g, unsigned &rtag, double (&part)[C]
   return true;
 }
 
-// ZL: z lives in LDS (16 rows per thread: z and the basis slice would not
-// both fit in registers); each thread touches only its own 16-byte entries.
+// ZL: z lives in LDS (16 rows per thread: z and two basis slices would not
+// all fit in registers); each thread touches only its own 16-byte entries.
+//
+// Pass i (0 <= i <= j + 1) of the step: z -= h_{i-1,j} v_{i-1} (i > 0), then
+// the grid sum of v_i . z (i <= j) or of z . z (i = j + 1), one row at a time
+// in that order.  The basis slices alternate between two register sets: while
+// pass i's sums travel between the blocks, v_{i+1} is already being loaded
+// into the set that held v_{i-1}.
 template <typename VT, int RPT, bool ZL>
 __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> p) {
   constexpr int C = 16 / (int)sizeof(VT);
-  extern __shared__ double zdyn[];  // ZL: [RPT][blockDim.x] rows of 16 bytes
+  extern __shared__ double zdyn[];  // ZL: [RPT][kSolveThreads] rows of 16 bytes
   // per-wave partials, then the column sums and abort votes; two halves so
   // that one exchange's results are never overwritten by the next one's
   // partials while slower waves still read them
   __shared__ double wpart[2][kWaves * C];
   __shared__ double res[2][2 * C];
-  // rows t0 + r T for r < nv, 16 bytes each: byte offsets fit 32 bits
-  // (n <= 2^21).  Every row slot is loaded unconditionally, from row 0 past
-  // the end, and its values then zeroed, so no old register copy is kept
-  const unsigned T = gridDim.x * blockDim.x;
-  const unsigned t0 = blockIdx.x * blockDim.x + threadIdx.x;
+  // rows t0 + r T, 16 bytes each (byte offsets fit 32 bits: n <= 2^21).
+  // Rows r < RPT - 1 exist for every thread (the launcher checks
+  // (RPT - 1) T <= n), so they are loaded unconditionally, all in flight
+  // together; only the last slot can lie past row n - 1, where it is zero.
+  const unsigned T = gridDim.x * kSolveThreads;
+  const unsigned t0 = blockIdx.x * kSolveThreads + threadIdx.x;
   const int n = p.n, j = p.j;
-  const int nv = t0 < (unsigned)n ? (int)(((unsigned)n - t0 + T - 1) / T) : 0;
-  const unsigned b0 = t0 * 16u, bs = T * 16u;
-  auto row_off = [&](int r) -> unsigned { return r < nv ? b0 + (unsigned)r * bs : 0u; };
+  const bool last_ok = (int64_t)t0 + (int64_t)(RPT - 1) * T < n;
+  const unsigned b0 = t0 * 16u, bs = T * 16u, nbytes = (unsigned)n * 16u;
   auto load_rows = [&](const VT *base, VT (&dst)[RPT][C]) {
-    const char *cb = reinterpret_cast<const char *>(base);
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc(base, nbytes);
 #pragma unroll
-    for (int r = 0; r < RPT; r++) Row16<VT>::load(reinterpret_cast<const VT *>(cb + row_off(r)), dst[r]);
+    for (int r = 0; r < RPT - 1; r++) load_row16<VT, C>(rs, b0, (unsigned)r * bs, dst[r]);
+    if (last_ok) {
+      load_row16<VT, C>(rs, b0, (unsigned)(RPT - 1) * bs, dst[RPT - 1]);
+    } else {
 #pragma unroll
-    for (int r = 0; r < RPT; r++)
-#pragma unroll
-      for (int c = 0; c < C; c++) dst[r][c] = r < nv ? dst[r][c] : (VT)0;
+      for (int c = 0; c < C; c++) dst[RPT - 1][c] = (VT)0;
+    }
   };
-  // v: the basis slice, loaded in pass i for its dot and kept for the update
-  // of pass i + 1.  z: in registers, or in LDS for ZL (zr is then the
-  // loading area of one row)
-  VT v[RPT][C];
+  VT va[RPT][C], vb[RPT][C];
   VT zreg[ZL ? 1 : RPT][C];
-  VT *zl = reinterpret_cast<VT *>(zdyn);
+  VT *zl = reinterpret_cast<VT *>(zdyn) + threadIdx.x * C;
   auto zget = [&](int r, VT (&o)[C]) {
     if constexpr (ZL) {
-      Row16<VT>::load(zl + ((size_t)r * blockDim.x + threadIdx.x) * C, o);
+      Row16<VT>::load(zl + r * kSolveThreads * C, o);
     } else {
 #pragma unroll
       for (int c = 0; c < C; c++) o[c] = zreg[r][c];
@@ -1618,49 +1672,45 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
   };
   auto zput = [&](int r, const VT (&o)[C]) {
     if constexpr (ZL) {
-      Row16<VT>::store(zl + ((size_t)r * blockDim.x + threadIdx.x) * C, o);
+      Row16<VT>::store(zl + r * kSolveThreads * C, o);
     } else {
 #pragma unroll
       for (int c = 0; c < C; c++) zreg[r][c] = o[c];
     }
   };
-  load_rows(p.z, v);  // z enters through the basis-slice registers
+  // z enters through the first register set while v_0 loads into the second
+  load_rows(p.z, va);
+  load_rows(p.V, vb);
 #pragma unroll
-  for (int r = 0; r < RPT; r++) {
-    zput(r, v[r]);
-#pragma unroll
-    for (int c = 0; c < C; c++) v[r][c] = (VT)0;
-  }
+  for (int r = 0; r < RPT; r++) zput(r, va[r]);
   unsigned rtag = 0;
   double h[C];
 #pragma unroll
   for (int c = 0; c < C; c++) h[c] = 0.0;
-  for (int i2 = 0; i2 <= j + 1; i2++) {
-    if (i2 > 0) {
-#pragma unroll
-      for (int r = 0; r < RPT; r++) {
-        VT zr[C];
-        zget(r, zr);
-#pragma unroll
-        for (int c = 0; c < C; c++) zr[c] = (VT)fma(-h[c], (double)v[r][c], (double)zr[c]);
-        zput(r, zr);
-      }
-    }
+  // one pass; vp holds v_{i-1} (refilled with v_{i+1}), vc holds v_i.  The
+  // first pass (no update) is a separate instance.
+  auto pass = [&](auto first, int i2, VT (&vp)[RPT][C], const VT (&vc)[RPT][C]) -> bool {
     double part[C];
 #pragma unroll
     for (int c = 0; c < C; c++) part[c] = 0.0;
-    if (i2 <= j) load_rows(p.V + (int64_t)i2 * p.vstride, v);
 #pragma unroll
     for (int r = 0; r < RPT; r++) {
       VT zr[C];
       zget(r, zr);
+      if constexpr (!decltype(first)::value) {
+#pragma unroll
+        for (int c = 0; c < C; c++) zr[c] = (VT)fma(-h[c], (double)vp[r][c], (double)zr[c]);
+        zput(r, zr);
+      }
 #pragma unroll
       for (int c = 0; c < C; c++) {
-        const double w = i2 <= j ? (double)v[r][c] : (double)zr[c];
+        const double w = i2 <= j ? (double)vc[r][c] : (double)zr[c];
         part[c] = fma(w, (double)zr[c], part[c]);
       }
     }
-    if (!mgs_grid_sum<C>(p.grid, rtag, part, wpart[i2 & 1], res[i2 & 1])) return;
+    mgs_post<C>(p.grid, rtag, part, wpart[i2 & 1]);
+    if (i2 + 1 <= j) load_rows(p.V + (int64_t)(i2 + 1) * p.vstride, vp);
+    if (!mgs_collect<C>(p.grid, rtag, part, res[i2 & 1])) return false;
     if (i2 <= j) {
 #pragma unroll
       for (int c = 0; c < C; c++) h[c] = part[c];
@@ -1673,18 +1723,24 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
         p.H[((int64_t)threadIdx.x * p.m + j) * (p.m + 1) + j + 1] = hn[threadIdx.x];
         p.hn[threadIdx.x] = hn[threadIdx.x];
       }
-      char *vn = reinterpret_cast<char *>(p.V + (int64_t)(j + 1) * p.vstride);
+      const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.V + (int64_t)(j + 1) * p.vstride, nbytes);
 #pragma unroll
       for (int r = 0; r < RPT; r++) {
-        if (r < nv) {
+        if (r < RPT - 1 || last_ok) {
           VT zr[C], o[C];
           zget(r, zr);
 #pragma unroll
           for (int c = 0; c < C; c++) o[c] = hn[c] > 0.0 ? (VT)((double)zr[c] / hn[c]) : (VT)0;
-          Row16<VT>::store(reinterpret_cast<VT *>(vn + row_off(r)), o);
+          store_row16<VT, C>(rs, b0, (unsigned)r * bs, o);
         }
       }
     }
+    return true;
+  };
+  if (!pass(std::true_type{}, 0, va, vb)) return;
+  for (int i2 = 1; i2 <= j + 1; i2 += 2) {
+    if (!pass(std::false_type{}, i2, vb, va)) return;
+    if (i2 + 1 <= j + 1 && !pass(std::false_type{}, i2 + 1, va, vb)) return;
   }
 }
 
@@ -1719,6 +1775,10 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
   const int rpt = mgs_persist_rpt(n);
   if (!rpt) return fail(BSPAI_EINVAL, "batched MGS: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
   const int G = (int)(((int64_t)n + (int64_t)kSolveThreads * rpt - 1) / ((int64_t)kSolveThreads * rpt));
+  // the kernel loads rows t + r T, r < rpt - 1, of every grid thread t
+  // without a bounds test: they must all lie below n
+  if ((int64_t)(rpt - 1) * G * kSolveThreads > n)
+    return fail(BSPAI_EINVAL, "batched MGS: %d rows per thread on %d blocks overrun n = %d", rpt, G, n);
   const size_t slot_bytes = 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols;
   BSPAI_HIP(hipMemsetAsync(ws, 0, mgs_persist_ws_bytes(), s));
   BMgsParams<VT> p;

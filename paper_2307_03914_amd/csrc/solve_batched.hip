@@ -647,8 +647,10 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
       if (prof) {
         float ms = 0.f;
         BSPAI_HIP(hipEventElapsedTime(&ms, pev.e[0], pev.e[1]));
-        // algorithmic bytes: v_0..v_j and z read, v_{j+1} written
-        add_mgs_profile(ms, (double)(j + 3) * (double)nr * sizeof(VT));
+        // algorithmic bytes of MGS step j: v_0..v_j read and v_{j+1} written,
+        // (j + 2) vectors of u_g per column (z, read once more by the kernel,
+        // is not counted)
+        add_mgs_profile(ms, (double)(j + 2) * (double)nr * sizeof(VT));
       }
       const double *hn = hq.data(), *hres = hq.data() + R;
       bool changed = false;
@@ -713,9 +715,13 @@ __global__ void k_scatter_cols(int64_t n, int R, int c0, int g, const double *sr
   if (t < n * g) dst[(t / g) * R + c0 + t % g] = src[t];
 }
 
-// n R u_g values from which the column groups pay: below it every pass moves
-// little and the launches of the per-pass kernels are shared by all columns
+// When the column groups pay: from n R u_g values of 64 MiB every pass is
+// bound by the bytes it moves (the groups move a quarter of them); below,
+// a pass of the per-pass kernels costs two launches shared by all columns and
+// a group pass one grid exchange, so the groups pay while there are at most
+// four of them
 constexpr double kGroupBytes = 64.0 * 1024 * 1024;
+constexpr int kMaxLaunchBoundGroups = 4;
 
 template <typename VT>
 int solve_many(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
@@ -724,7 +730,8 @@ int solve_many(const bspai_csr *A, const bspai_handle *Ab, const double *b, cons
   const int n = A->n;
   const int mode = batch_mode();
   const bool fits = mgs_persist_rpt(n) > 0 && R >= C;
-  const bool grouped = mode == 2 ? fits : (mode == 1 ? false : fits && (double)n * R * sizeof(VT) >= kGroupBytes);
+  const bool big = (double)n * R * sizeof(VT) >= kGroupBytes;
+  const bool grouped = mode == 2 ? fits : (mode == 1 ? false : fits && (big || R <= kMaxLaunchBoundGroups * C));
   if (!grouped) return solve_batched<VT>(A, Ab, b, M, tol, x, R, m, st_host, s, false);
   if (R == C) return solve_batched<VT>(A, Ab, b, M, tol, x, R, m, st_host, s, true);
   // consecutive groups of C columns (a trailing C + 1 or fewer than C go

@@ -263,18 +263,14 @@ def test_build_low_uf_overflow_and_limits(B):
     assert e.value.code == B.EINVAL and "wavefront" in str(e.value)
     with pytest.raises(ValueError):
         B.build(Ad, None, u_f="bf16")
-    # the adaptive build is FP64 only: a lower u_f is rejected before any work
-    import ctypes
-
-    o = B._opts(True, True, False, "fp16")
-    ad = B._AdOpts(5, 8, 0.4)
-    ids, q = B._prec_ids(["fp32"])
-    out = ctypes.c_void_p()
-    a = Ad._c()
-    steps = np.zeros(n, dtype=np.int32)
-    rc = B._lib.bspai_build_adaptive(ctypes.byref(a), None, ctypes.byref(ad), 1e-4, ids, q, ctypes.byref(o),
-                                     ctypes.byref(out), steps.ctypes.data_as(ctypes.c_void_p), None)
-    assert rc == B.EINVAL and b"u_f" in B._lib.bspai_last_error()
+    # the adaptive build in half precision: unscaled, the 1e5 entries
+    # overflow fp16 (ENAN, as the oracle reports); scaled it succeeds
+    with pytest.raises(B.BSPAIError) as e:
+        B.build_adaptive(Ad, alpha=2, beta=4, eps_spai=0.1, precs=["fp32"], u_f="fp16")
+    assert e.value.code == B.ENAN
+    assert O.spai_adaptive(A, alpha=2, beta=4, eps=0.1, uf=O.FP16)["status"] == O.ENAN
+    h, _ = B.build_adaptive(Ad, alpha=2, beta=4, eps_spai=0.1, precs=["fp32"], u_f="fp16", scale=True)
+    h.free()
 
 
 def test_build_low_uf_full_size_sampled_rows(B):
@@ -1458,6 +1454,34 @@ def test_build_adaptive_matches_oracle(B, case, alpha, beta, eps):
         s_, e_ = rp[k], rp[k + 1]
         assert np.abs(m[s_:e_] - ref["M"].val[s_:e_]).max() <= 1e-10 * np.abs(ref["M"].val[s_:e_]).max(), k
     h.free()
+
+
+@pytest.mark.parametrize("uf", ["fp32", "fp16"])
+@pytest.mark.parametrize("case", _adaptive_cases(), ids=lambda c: c[0])
+def test_build_adaptive_low_uf_matches_oracle(B, case, uf):
+    """Table 4's setting on the GPU: the adaptive SPAI with its least squares
+    in u_f (with Section 4's column scaling).  The two sides round the
+    solves in different summation orders, so a candidate whose score ties
+    another's to within u_f may go either way: the patterns must agree on
+    nearly every row, every row's values must be the u_f least squares
+    solution on the GPU's own pattern (the fixed-pattern bound), and the
+    per-row solve counts must agree wherever the patterns do."""
+    name, A = case
+    prec, u = UF[uf]
+    _say("adaptive u_f", uf, name)
+    ref = O.spai_adaptive(A, alpha=5, beta=8, eps=0.4, uf=prec, scale=True)
+    assert ref["status"] == O.OK
+    h, steps = B.build_adaptive(B.CSRMatrix.from_host(A), alpha=5, beta=8, eps_spai=0.4, precs=["fp64"],
+                                eps=2.0 ** -53, u_f=uf, scale=True)
+    rp, col = h.export_pattern()
+    m = h.export()["m64"]
+    h.free()
+    same = np.array([np.array_equal(col[rp[k]:rp[k + 1]], ref["M"].col[ref["M"].row_ptr[k]:ref["M"].row_ptr[k + 1]])
+                     for k in range(A.n)])
+    _say("rows with the oracle's pattern:", same.mean())
+    assert same.mean() >= (0.99 if uf == "fp32" else 0.95)
+    assert np.array_equal(steps[same], ref["steps"][same])
+    _check_low_uf_rows(m, A, W.CSR(A.n, rp, col, None), uf)
 
 
 def test_solve_with_adaptive_spai(B):
