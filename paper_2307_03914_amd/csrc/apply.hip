@@ -454,6 +454,83 @@ static int launch_one(const BMat &M, const XT *x, XT *y, int kind, hipStream_t s
   }
 }
 
+// Many right-hand sides (R a multiple of 4, as k_bspmm4) when every stored
+// bucket has an ELL copy: a row's column codes and values arrive in the ELL
+// copies' vector loads (byte or int16 codes where the bucket has them: 1 or
+// 2 bytes per entry instead of 4), then their 16-byte gathers of x.  Same
+// order of operations as k_bspmm4; padding entries add +0.
+template <int U, typename PT, typename XT>
+__device__ __forceinline__ void bspmm4_ell_chunk(const BMat &M, int k, int64_t e, int row, const int32_t *dict,
+                                                 const XT *__restrict__ x, int64_t ld, int c0, PT (&acc)[4]) {
+  int cc[U];
+  PT vv[U];
+  ell_cols<U>(M, k, e, row, dict, cc);
+  if constexpr (U == 4)
+    ell_vals4<PT>(M, k, e, vv);
+  else
+    ell_vals8<PT>(M, k, e, vv);
+  double xv[U][4];
+#pragma unroll
+  for (int t = 0; t < U; t++) ld4<XT>(x + (int64_t)cc[t] * ld + c0, xv[t]);
+#pragma unroll
+  for (int t = 0; t < U; t++)
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if constexpr (sizeof(PT) == 8)
+        acc[u] = fma(vv[t], xv[t][u], acc[u]);
+      else
+        acc[u] = fmaf(vv[t], (float)xv[t][u], acc[u]);
+    }
+}
+
+template <typename XT>
+__global__ void __launch_bounds__(kApplyThreads) k_bspmm4_ell(BMat M, const XT *__restrict__ x, XT *__restrict__ y,
+                                                              int64_t ld, int nrhs) {
+  __shared__ int32_t sdict[kMaxBuckets * 256];
+  bool staged = false;
+  for (int k = 0; k < M.nb; k++) {
+    if (M.ell_cw[k] == 1) {
+      for (int t = threadIdx.x; t < 256; t += blockDim.x) sdict[256 * k + t] = M.ell_dict[k][t];
+      staged = true;
+    }
+  }
+  if (staged) __syncthreads();
+  const int tpr = nrhs / 4, rpb = kApplyThreads / tpr;
+  const int g = threadIdx.x / tpr, c0 = 4 * (threadIdx.x % tpr);
+  const int i = xcd_block(blockIdx.x, gridDim.x) * rpb + g;
+  if (g >= rpb || i >= M.n) return;
+  double total[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < M.nb; k++) {
+    const int ew = M.ell_w[k];
+    const int64_t e0 = (int64_t)i * ew;
+    const int32_t *dict = sdict + 256 * k;
+    if (M.prec[k] == BSPAI_FP64 || sizeof(XT) == 8) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (ew == 4)
+        bspmm4_ell_chunk<4, double, XT>(M, k, e0, i, dict, x, ld, c0, acc);
+      else
+        for (int q = 0; q < ew; q += 8) bspmm4_ell_chunk<8, double, XT>(M, k, e0 + q, i, dict, x, ld, c0, acc);
+#pragma unroll
+      for (int u = 0; u < 4; u++) total[u] += acc[u] * M.scale[k];
+    } else {
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+      if (ew == 4)
+        bspmm4_ell_chunk<4, float, XT>(M, k, e0, i, dict, x, ld, c0, acc);
+      else
+        for (int q = 0; q < ew; q += 8) bspmm4_ell_chunk<8, float, XT>(M, k, e0 + q, i, dict, x, ld, c0, acc);
+#pragma unroll
+      for (int u = 0; u < 4; u++) total[u] += (double)acc[u] * M.scale[k];
+    }
+  }
+  XT *yp = y + (int64_t)i * ld + c0;
+  if (sizeof(XT) == 4) {
+    *reinterpret_cast<float4 *>(yp) = make_float4((float)total[0], (float)total[1], (float)total[2], (float)total[3]);
+  } else {
+    reinterpret_cast<double2 *>(yp)[0] = make_double2(total[0], total[1]);
+    reinterpret_cast<double2 *>(yp)[1] = make_double2(total[2], total[3]);
+  }
+}
+
 int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s) {
   if (M.n == 0) return BSPAI_OK;
   if (nrhs == 1) {
@@ -467,12 +544,13 @@ int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, in
       (reinterpret_cast<uintptr_t>(y) & 15) == 0) {
     const int rpb = kApplyThreads / (nrhs / 4);
     const int64_t nblk = (M.n + rpb - 1) / rpb;
+    const bool ell = all_ell(M);
     if (fp64)
-      hipLaunchKernelGGL(k_bspmm4<double>, dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M,
-                         static_cast<const double *>(x), static_cast<double *>(y), ld, nrhs);
+      hipLaunchKernelGGL(ell ? k_bspmm4_ell<double> : k_bspmm4<double>, dim3((unsigned)nblk), dim3(kApplyThreads),
+                         0, s, M, static_cast<const double *>(x), static_cast<double *>(y), ld, nrhs);
     else
-      hipLaunchKernelGGL(k_bspmm4<float>, dim3((unsigned)nblk), dim3(kApplyThreads), 0, s, M,
-                         static_cast<const float *>(x), static_cast<float *>(y), ld, nrhs);
+      hipLaunchKernelGGL(ell ? k_bspmm4_ell<float> : k_bspmm4<float>, dim3((unsigned)nblk), dim3(kApplyThreads), 0,
+                         s, M, static_cast<const float *>(x), static_cast<float *>(y), ld, nrhs);
     BSPAI_CHECK_LAUNCH();
     return BSPAI_OK;
   }

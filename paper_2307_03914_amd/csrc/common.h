@@ -196,8 +196,8 @@ int mgs_persist_rpt(int n);
 size_t mgs_persist_ws_bytes();
 size_t mgs_persist_abort_offset();
 template <typename VT>
-int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn, void *ws,
-                       hipStream_t s);
+int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn,
+                       const int *gma, void *ws, hipStream_t s);
 
 // Instrumentation shared by the solvers (solve.hip): the profiling switch
 // (bspai_set_profiling) and the totals of the one-launch MGS kernel.

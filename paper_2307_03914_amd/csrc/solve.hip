@@ -1463,7 +1463,11 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
 constexpr int kMgsCols = 4;  // column sums per exchange (FP32: 4, FP64: 2 used)
 
 struct MgsGrid {
-  unsigned long long *slots;  // [kNumSlots][kMaxBlocks][kMgsCols][2] tagged words, cleared per launch
+  // [kNumSlots][kMaxBlocks][kMgsCols][2] tagged words, cleared per launch:
+  // each block's words share one 64-byte line, written by one instruction
+  // (column-major slots, whose polls coalesce, measured 4% slower per pass:
+  // four blocks then write into every line)
+  unsigned long long *slots;
   unsigned *abortf;
 };
 
@@ -1475,6 +1479,7 @@ struct BMgsParams {
   int64_t vstride;
   double *H;         // h_{i,j} of column c at H + (c * m + j) * (m + 1) + i, i <= j + 1
   double *hn;        // [C]: h_{j+1,j}
+  const int *gma;    // [C] GMRES-active flags, or null: with none set the launch does nothing
   MgsGrid grid;
 };
 
@@ -1622,8 +1627,8 @@ __device__ bool mgs_collect(const MgsGrid &g, unsigned rtag, double (&part)[C], 
   return true;
 }
 
-// ZL: z lives in LDS (16 rows per thread: z and two basis slices would not
-// all fit in registers); each thread touches only its own 16-byte entries.
+// ZL: z lives in LDS (8 or more rows per thread: z and two basis slices would
+// not all fit in registers); each thread touches only its own 16-byte entries.
 //
 // Pass i (0 <= i <= j + 1) of the step: z -= h_{i-1,j} v_{i-1} (i > 0), then
 // the grid sum of v_i . z (i <= j) or of z . z (i = j + 1), one row at a time
@@ -1681,6 +1686,12 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
   // z enters through the first register set while v_0 loads into the second
   load_rows(p.z, va);
   load_rows(p.V, vb);
+  if (p.gma) {  // a step queued after every column stopped: nothing to do
+    int any = 0;
+#pragma unroll
+    for (int c = 0; c < C; c++) any |= p.gma[c];
+    if (!any) return;
+  }
 #pragma unroll
   for (int r = 0; r < RPT; r++) zput(r, va[r]);
   unsigned rtag = 0;
@@ -1688,8 +1699,12 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
 #pragma unroll
   for (int c = 0; c < C; c++) h[c] = 0.0;
   // one pass; vp holds v_{i-1} (refilled with v_{i+1}), vc holds v_i.  The
-  // first pass (no update) is a separate instance.
+  // first pass (no update) is a separate instance.  Each row of v_{i+1} is
+  // requested as soon as the row of v_{i-1} in its registers has been used,
+  // so the loads run under this pass's arithmetic and exchange.
   auto pass = [&](auto first, int i2, VT (&vp)[RPT][C], const VT (&vc)[RPT][C]) -> bool {
+    const bool pre = i2 + 1 <= j;
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.V + (int64_t)(pre ? i2 + 1 : 0) * p.vstride, nbytes);
     double part[C];
 #pragma unroll
     for (int c = 0; c < C; c++) part[c] = 0.0;
@@ -1702,6 +1717,14 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
         for (int c = 0; c < C; c++) zr[c] = (VT)fma(-h[c], (double)vp[r][c], (double)zr[c]);
         zput(r, zr);
       }
+      if (pre) {
+        if (r < RPT - 1 || last_ok) {
+          load_row16<VT, C>(rs, b0, (unsigned)r * bs, vp[r]);
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; c++) vp[r][c] = (VT)0;
+        }
+      }
 #pragma unroll
       for (int c = 0; c < C; c++) {
         const double w = i2 <= j ? (double)vc[r][c] : (double)zr[c];
@@ -1709,7 +1732,6 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
       }
     }
     mgs_post<C>(p.grid, rtag, part, wpart[i2 & 1]);
-    if (i2 + 1 <= j) load_rows(p.V + (int64_t)(i2 + 1) * p.vstride, vp);
     if (!mgs_collect<C>(p.grid, rtag, part, res[i2 & 1])) return false;
     if (i2 <= j) {
 #pragma unroll
@@ -1756,7 +1778,7 @@ size_t mgs_persist_ws_bytes() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMg
 
 template <typename VT, int RPT>
 static int launch_mgs_rpt(BMgsParams<VT> &p, int G, hipStream_t s) {
-  constexpr bool ZL = RPT >= 16;
+  constexpr bool ZL = RPT >= 8;
   const unsigned lds = ZL ? (unsigned)(RPT * kSolveThreads * 16) : 0u;
   void *fn = (void *)k_b_mgs_persist<VT, RPT, ZL>;
   if (ZL) BSPAI_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1766,12 +1788,13 @@ static int launch_mgs_rpt(BMgsParams<VT> &p, int G, hipStream_t s) {
 }
 
 // One Arnoldi step's MGS (see k_b_mgs_persist) for the n x (16 / sizeof(VT))
-// block z, basis V (v_i at V + i * vstride), H columns of step j; ws:
-// mgs_persist_ws_bytes() of device memory (exchange words and the abort flag,
-// cleared here).  Enqueued on s.
+// block z, basis V (v_i at V + i * vstride), H columns of step j; gma: the
+// columns' GMRES-active flags (the launch returns at once when none is set),
+// or null; ws: mgs_persist_ws_bytes() of device memory (exchange words and
+// the abort flag, cleared here).  Enqueued on s.
 template <typename VT>
-int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn, void *ws,
-                       hipStream_t s) {
+int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn,
+                       const int *gma, void *ws, hipStream_t s) {
   const int rpt = mgs_persist_rpt(n);
   if (!rpt) return fail(BSPAI_EINVAL, "batched MGS: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
   const int G = (int)(((int64_t)n + (int64_t)kSolveThreads * rpt - 1) / ((int64_t)kSolveThreads * rpt));
@@ -1790,6 +1813,7 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
   p.vstride = vstride;
   p.H = H;
   p.hn = hn;
+  p.gma = gma;
   p.grid.slots = static_cast<unsigned long long *>(ws);
   p.grid.abortf = reinterpret_cast<unsigned *>(static_cast<char *>(ws) + slot_bytes);
   switch (rpt) {
@@ -1804,10 +1828,10 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
 // the abort flag's offset in the batched MGS workspace
 size_t mgs_persist_abort_offset() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols; }
 
-template int launch_mgs_persist<float>(int, int, int, const float *, float *, int64_t, double *, double *, void *,
-                                       hipStream_t);
-template int launch_mgs_persist<double>(int, int, int, const double *, double *, int64_t, double *, double *, void *,
-                                        hipStream_t);
+template int launch_mgs_persist<float>(int, int, int, const float *, float *, int64_t, double *, double *,
+                                       const int *, void *, hipStream_t);
+template int launch_mgs_persist<double>(int, int, int, const double *, double *, int64_t, double *, double *,
+                                        const int *, void *, hipStream_t);
 
 }  // namespace bspai
 

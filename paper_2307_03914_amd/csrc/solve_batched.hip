@@ -304,47 +304,112 @@ __global__ void k_b_scale4(int R, int64_t nr, const VT *z, const double *h, VT *
   Vec4<VT>::store(v + e, o);
 }
 
-// Givens step j for every column (one thread per column).  H column j holds
-// h_{0..j+1, j} on entry; rotated in place.  Writes res[c] = |g_{j+1}|.
-__global__ void k_b_givens(int R, int m, int j, double *H, double *cs, double *sn, double *g, const int *gm_active,
-                           double *res) {
-  int c = threadIdx.x;
+// Givens step j, one block of 64 threads per column (grid R; dynamic LDS
+// (3 m + 1) doubles).  H column j holds h_{0..j+1, j} on entry; rotated in
+// place.  Writes res[c] = |g_{j+1}|.  The column and the earlier rotations
+// are staged in LDS by the whole block; lane 0 then applies rotations
+// 0..j-1 carrying the rotated entry in a register (the chain of dependent
+// products never goes through global memory) and forms rotation j.
+// hn non-null: the column's GMRES stops here (gm_active[c] = 0) when
+// |g_{j+1}| <= tau beta[c], h_{j+1,j} = hn[c] = 0 or j + 1 = m, the test the
+// host repeats on the same values, so that steps queued ahead see it.
+__global__ void __launch_bounds__(64) k_b_givens(int R, int m, int j, double *H, double *cs, double *sn, double *g,
+                                                 int *gm_active, double *res, const double *hn, const double *beta,
+                                                 double tau) {
+  extern __shared__ double gsh[];
+  const int c = blockIdx.x;
   if (c >= R) return;
   double *h = H + ((int64_t)c * m + j) * (m + 1);
   double *cc = cs + (int64_t)c * m, *ss = sn + (int64_t)c * m, *gg = g + (int64_t)c * (m + 1);
   if (!gm_active[c]) {
-    res[c] = 0.0;
+    if (threadIdx.x == 0) res[c] = 0.0;
     return;
   }
-  for (int i = 0; i < j; i++) {
-    double a = h[i], b = h[i + 1];
-    h[i] = cc[i] * a + ss[i] * b;
-    h[i + 1] = -ss[i] * a + cc[i] * b;
+  double *lh = gsh, *lc = gsh + (m + 1), *ls = lc + m;
+  for (int i = threadIdx.x; i <= j + 1; i += 64) lh[i] = h[i];
+  for (int i = threadIdx.x; i < j; i += 64) {
+    lc[i] = cc[i];
+    ls[i] = ss[i];
   }
-  double a = h[j], b = h[j + 1];
-  double rho = hypot(a, b);
-  cc[j] = rho == 0.0 ? 1.0 : a / rho;
-  ss[j] = rho == 0.0 ? 0.0 : b / rho;
-  h[j] = rho;
-  h[j + 1] = 0.0;
-  gg[j + 1] = -ss[j] * gg[j];
-  gg[j] = cc[j] * gg[j];
-  res[c] = fabs(gg[j + 1]);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = lh[0];
+#pragma unroll 4
+    for (int i = 0; i < j; i++) {
+      const double b = lh[i + 1], ci = lc[i], si = ls[i];
+      lh[i] = ci * a + si * b;
+      a = -si * a + ci * b;
+    }
+    const double b = lh[j + 1];
+    const double rho = hypot(a, b);
+    const double cj = rho == 0.0 ? 1.0 : a / rho;
+    const double sj = rho == 0.0 ? 0.0 : b / rho;
+    cc[j] = cj;
+    ss[j] = sj;
+    lh[j] = rho;
+    lh[j + 1] = 0.0;
+    const double gj = gg[j];
+    gg[j + 1] = -sj * gj;
+    gg[j] = cj * gj;
+    const double hres = fabs(-sj * gj);
+    res[c] = hres;
+    if (hn && (hres <= tau * beta[c] || hn[c] == 0.0 || j + 1 == m)) gm_active[c] = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 64) h[i] = lh[i];
 }
 
-// y = R^{-1} g for every column (k[c] iterations)
-__global__ void k_b_backsub(int R, int m, const double *H, const double *g, const int *kc, double *y) {
-  int c = threadIdx.x;
+// y = R^{-1} g for every column (k[c] iterations): one 64-thread block per
+// column (grid R, dynamic LDS 3 m doubles, m <= kBacksubMaxM).  For row i the
+// lanes form the rounded products h_{i,j} y_j (j > i) in parallel and lane 0
+// subtracts them from g_i in increasing j, the order of the row recurrence;
+// the entries of row i - 1 are loaded while lane 0 works on row i.
+constexpr int kBacksubMaxM = 192;
+// Arnoldi steps of the column-group path queued ahead of the host's
+// stopping decisions
+constexpr int kStepLag = 4;
+__global__ void __launch_bounds__(64) k_b_backsub(int R, int m, const double *H, const double *g, const int *kc,
+                                                  double *y) {
+  constexpr int Q = kBacksubMaxM / 64;
+  extern __shared__ double bsh[];
+  const int c = blockIdx.x;
   if (c >= R) return;
-  int k = kc[c];
+  const int k = kc[c], lane = threadIdx.x;
+  if (k <= 0) return;
   const double *Hc = H + (int64_t)c * m * (m + 1);
-  const double *gg = g + (int64_t)c * (m + 1);
-  double *yy = y + (int64_t)c * m;
+  double *ly = bsh, *lp = bsh + m, *lh = bsh + 2 * m;  // y, products, row i (entries j >= i)
+  double r[Q];
+  auto load_row = [&](int i) {
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const int j = i + lane + 64 * q;
+      r[q] = j < k ? Hc[(int64_t)j * (m + 1) + i] : 0.0;
+    }
+  };
+  auto store_row = [&](int i) {
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const int j = i + lane + 64 * q;
+      if (j < k) lh[j] = r[q];
+    }
+  };
+  load_row(k - 1);
+  store_row(k - 1);
+  __syncthreads();
   for (int i = k - 1; i >= 0; i--) {
-    double t = gg[i];
-    for (int j = i + 1; j < k; j++) t -= Hc[(int64_t)j * (m + 1) + i] * yy[j];
-    yy[i] = t / Hc[(int64_t)i * (m + 1) + i];
+    for (int j = i + 1 + lane; j < k; j += 64) lp[j] = lh[j] * ly[j];
+    const double diag = lh[i];
+    __syncthreads();
+    if (i > 0) load_row(i - 1);
+    if (lane == 0) {
+      double t = g[(int64_t)c * (m + 1) + i];
+      for (int j = i + 1; j < k; j++) t -= lp[j];
+      ly[i] = t / diag;
+    }
+    if (i > 0) store_row(i - 1);
+    __syncthreads();
   }
+  for (int i = lane; i < k; i += 64) y[(int64_t)c * m + i] = ly[i];
 }
 
 // d = V y per column (FP64); add mode: x += d, else out = d; max|d|, max|x|
@@ -417,6 +482,7 @@ template <typename VT>
 int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
                   const gmres_ir_tol *tol, double *x, int R, int m, gmres_ir_stats *st_host, hipStream_t s,
                   bool mgs1) {
+  if (m > kBacksubMaxM) return fail(BSPAI_EINVAL, "gmres_ir_solve: gmres_max %d above %d", m, kBacksubMaxM);
   if (mgs1 && (R * (int)sizeof(VT) != 16 || !mgs_persist_rpt(A->n)))
     return fail(BSPAI_EINVAL, "gmres_ir_solve: the one-launch MGS needs %d columns and at most %d rows",
                 16 / (int)sizeof(VT), 256 * 512 * 16);
@@ -440,20 +506,37 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb, mgsws;
   int rc;
   if (mgs1 && (rc = dalloc(&mgsws.p, mgs_persist_ws_bytes()))) return rc;
-  // optional timing of the one-launch MGS kernel (HIP events on s)
+  // per queued step: pinned copies of h_{j+1,j}, |g_{j+1}| and the MGS abort
+  // flag, the step's completion event, and (when profiling) HIP events
+  // around its MGS launch
   const bool prof = mgs1 && profiling_on();
-  struct Events {
-    hipEvent_t e[2] = {nullptr, nullptr};
-    ~Events() {
-      for (auto &q : e)
+  struct StepRing {
+    void *pin = nullptr;
+    int R = 0;
+    hipStream_t st = nullptr;
+    hipEvent_t done[kStepLag] = {};
+    hipEvent_t prof[2 * kStepLag] = {};
+    double *hq(int k) { return static_cast<double *>(pin) + (size_t)k * (2 * R + 1); }
+    unsigned *abort(int k) { return reinterpret_cast<unsigned *>(hq(k) + 2 * R); }
+    ~StepRing() {
+      if (pin) (void)hipStreamSynchronize(st);  // copies into pin may still be queued on an error return
+      for (auto q : done)
         if (q) (void)hipEventDestroy(q);
+      for (auto q : prof)
+        if (q) (void)hipEventDestroy(q);
+      if (pin) (void)hipHostFree(pin);
     }
-  } pev;
-  if (prof) {
-    BSPAI_HIP(hipEventCreate(&pev.e[0]));
-    BSPAI_HIP(hipEventCreate(&pev.e[1]));
+  } ring;
+  ring.R = R;
+  ring.st = s;
+  BSPAI_HIP(hipHostMalloc(&ring.pin, sizeof(double) * (size_t)kStepLag * (2 * R + 1), hipHostMallocDefault));
+  for (int k = 0; k < kStepLag; k++) {
+    BSPAI_HIP(hipEventCreateWithFlags(&ring.done[k], hipEventDisableTiming));
+    if (prof) {
+      BSPAI_HIP(hipEventCreate(&ring.prof[2 * k]));
+      BSPAI_HIP(hipEventCreate(&ring.prof[2 * k + 1]));
+    }
   }
-  unsigned mgs_abort = 0;
   const int32_t *arp = A->row_ptr, *acol = A->col;
   const double *aval = A->val;
   if (tr) {
@@ -491,6 +574,27 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   Apm.rp[0] = arp;
   Apm.col[0] = acol;
   Apm.val[0] = Ap;
+  // A's ELL copy (byte or int16 column codes where they fit) for the
+  // many-column products: 5 instead of 8 bytes per FP32 entry
+  DevBuf aecol, aeval, aecode, aedict;
+  if (!Ab && nnz > 0 && R % 4 == 0) {
+    int32_t w = 0, cw = 0, *ecol = nullptr, *edict = nullptr;
+    void *eval = nullptr, *ecode = nullptr;
+    rc = csr_to_ell(n, arp, acol, Ap, (int)sizeof(VT), &ecol, &eval, &w, s);
+    aecol.p = ecol, aeval.p = eval;
+    if (rc) return rc;
+    if (w) {
+      rc = ell_codes(n, w, ecol, &ecode, &edict, &cw, s);
+      aecode.p = ecode, aedict.p = edict;
+      if (rc) return rc;
+      Apm.ell_w[0] = w;
+      Apm.ell_cw[0] = cw;
+      Apm.ell_col[0] = cw ? nullptr : ecol;
+      Apm.ell_val[0] = eval;
+      Apm.ell_code[0] = ecode;
+      Apm.ell_dict[0] = edict;
+    }
+  }
   if (Ab) Apm = tr ? Ab->matT : Ab->mat;
   const BMat &Mb = tr ? M->matT : M->mat;
   const int fp64 = sizeof(VT) == 8;
@@ -600,73 +704,92 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
     BSPAI_HIP(hipMemcpyAsync(GMA, gm_active.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
     int nrun = 0;
     for (int c = 0; c < R; c++) nrun += gm_active[c];
-    for (int j = 0; j < m && nrun > 0; j++) {
-      VT *vj = V + (int64_t)j * nr;
-      if (!tr) {
-        if ((rc = launch_bspmv(Apm, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Mb, W, Z, R, R, fp64, s))) return rc;
-      } else {
-        if ((rc = launch_bspmv(Mb, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Apm, W, Z, R, R, fp64, s))) return rc;
-      }
-      if (mgs1) {
-        // the whole step's MGS in one cooperative launch (h_{i,j} to H, the
-        // norms to S row 5, v_{j+1} written)
-        if (prof) BSPAI_HIP(hipEventRecord(pev.e[0], s));
-        if ((rc = launch_mgs_persist<VT>(n, j, m, Z, V, nr, H, S + 5 * R, mgsws.p, s))) return rc;
-        if (prof) BSPAI_HIP(hipEventRecord(pev.e[1], s));
-        BSPAI_HIP(hipMemcpyAsync(&mgs_abort, static_cast<char *>(mgsws.p) + mgs_persist_abort_offset(), 4,
-                                 hipMemcpyDeviceToHost, s));
-      }
-      // MGS: pass i removes v_{i-1}, measures v_i; h_{i,j} lands in H column j
-      for (int i = 0; !mgs1 && i <= j + 1; i++) {
-        const VT *vprev = i > 0 ? V + (int64_t)(i - 1) * nr : nullptr;
-        const VT *vcur = i <= j ? V + (int64_t)i * nr : nullptr;
-        const double *hprev = S + 5 * R;
-        if (vec4)
-          hipLaunchKernelGGL(k_b_mgs4<VT>, dim3(nblk4), dim3(kBT), 0, s, R, n, Z, vprev, hprev, vcur, P1);
+    // Steps are queued up to `lag` ahead of the host.  On the column-group
+    // path the Givens kernel applies each column's stopping test on the
+    // device (a step queued after every column stopped finds no active
+    // column: its MGS launch returns at once and its rotations are skipped),
+    // and the host repeats the test on the same values when the step's event
+    // completes.  The per-pass path decides on the host after every step.
+    const int lag = mgs1 ? kStepLag : 1;
+    int jq = 0;  // steps queued
+    for (int jd = 0; jd < m && nrun > 0; jd++) {
+      for (; jq < m && jq < jd + lag; jq++) {
+        const int j = jq, slot = j % lag;
+        VT *vj = V + (int64_t)j * nr;
+        if (!tr) {
+          if ((rc = launch_bspmv(Apm, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Mb, W, Z, R, R, fp64, s)))
+            return rc;
+        } else {
+          if ((rc = launch_bspmv(Mb, vj, W, R, R, fp64, s)) || (rc = launch_bspmv(Apm, W, Z, R, R, fp64, s)))
+            return rc;
+        }
+        if (mgs1) {
+          // the whole step's MGS in one cooperative launch (h_{i,j} to H, the
+          // norms to S row 5, v_{j+1} written)
+          if (prof) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot], s));
+          if ((rc = launch_mgs_persist<VT>(n, j, m, Z, V, nr, H, S + 5 * R, GMA, mgsws.p, s))) return rc;
+          if (prof) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot + 1], s));
+          BSPAI_HIP(hipMemcpyAsync(ring.abort(slot), static_cast<char *>(mgsws.p) + mgs_persist_abort_offset(), 4,
+                                   hipMemcpyDeviceToHost, s));
+        }
+        // MGS: pass i removes v_{i-1}, measures v_i; h_{i,j} lands in H column j
+        for (int i = 0; !mgs1 && i <= j + 1; i++) {
+          const VT *vprev = i > 0 ? V + (int64_t)(i - 1) * nr : nullptr;
+          const VT *vcur = i <= j ? V + (int64_t)i * nr : nullptr;
+          const double *hprev = S + 5 * R;
+          if (vec4)
+            hipLaunchKernelGGL(k_b_mgs4<VT>, dim3(nblk4), dim3(kBT), 0, s, R, n, Z, vprev, hprev, vcur, P1);
+          else
+            hipLaunchKernelGGL(k_b_mgs<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, Z, vprev, hprev, vcur, P1);
+          BSPAI_CHECK_LAUNCH();
+          // the finished scalar goes to S row 5 (next pass) and into H column j
+          if ((rc = finish(false, P1, S + 5 * R, i > j, H + (int64_t)j * (m + 1) + i, (int64_t)m * (m + 1),
+                           vec4 ? nblk4 : nblk)))
+            return rc;
+        }
+        // v_{j+1} = z / h_{j+1,j} (written by the one-launch MGS itself)
+        if (mgs1) {
+        } else if (vec4)
+          hipLaunchKernelGGL(k_b_scale4<VT>, dim3((unsigned)((nr / 4 + 255) / 256)), dim3(256), 0, s, R, nr, Z,
+                             S + 5 * R, V + (int64_t)(j + 1) * nr);
         else
-          hipLaunchKernelGGL(k_b_mgs<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, Z, vprev, hprev, vcur, P1);
+          hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, Z, S + 5 * R,
+                             V + (int64_t)(j + 1) * nr);
         BSPAI_CHECK_LAUNCH();
-        // the finished scalar goes to S row 5 (next pass) and into H column j
-        if ((rc = finish(false, P1, S + 5 * R, i > j, H + (int64_t)j * (m + 1) + i, (int64_t)m * (m + 1),
-                         vec4 ? nblk4 : nblk)))
-          return rc;
+        hipLaunchKernelGGL(k_b_givens, dim3(R), dim3(64), (size_t)(3 * m + 1) * sizeof(double), s, R, m, j, H, CS,
+                           SN, G, GMA, S + 6 * R, mgs1 ? S + 5 * R : nullptr, S + 4 * R, tol->tau);
+        BSPAI_CHECK_LAUNCH();
+        // row 0: h_{j+1,j}, row 1: |g_{j+1}|
+        BSPAI_HIP(hipMemcpyAsync(ring.hq(slot), S + 5 * R, 2 * 8 * (size_t)R, hipMemcpyDeviceToHost, s));
+        BSPAI_HIP(hipEventRecord(ring.done[slot], s));
       }
-      // v_{j+1} = z / h_{j+1,j} (written by the one-launch MGS itself)
-      if (mgs1) {
-      } else if (vec4)
-        hipLaunchKernelGGL(k_b_scale4<VT>, dim3((unsigned)((nr / 4 + 255) / 256)), dim3(256), 0, s, R, nr, Z,
-                           S + 5 * R, V + (int64_t)(j + 1) * nr);
-      else
-        hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, Z, S + 5 * R, V + (int64_t)(j + 1) * nr);
-      BSPAI_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_b_givens, dim3(1), dim3(64), 0, s, R, m, j, H, CS, SN, G, GMA, S + 6 * R);
-      BSPAI_CHECK_LAUNCH();
-      std::vector<double> hq;  // row 0: h_{j+1,j}, row 1: |g_{j+1}|
-      if ((rc = to_host(S + 5 * R, hq, 2))) return rc;
-      if (mgs_abort) return fail(BSPAI_EHIP, "gmres_ir_solve: a grid exchange of the MGS kernel timed out");
+      const int slot = jd % lag;
+      BSPAI_HIP(hipEventSynchronize(ring.done[slot]));
+      if (mgs1 && *ring.abort(slot))
+        return fail(BSPAI_EHIP, "gmres_ir_solve: a grid exchange of the MGS kernel timed out");
       if (prof) {
         float ms = 0.f;
-        BSPAI_HIP(hipEventElapsedTime(&ms, pev.e[0], pev.e[1]));
+        BSPAI_HIP(hipEventElapsedTime(&ms, ring.prof[2 * slot], ring.prof[2 * slot + 1]));
         // algorithmic bytes of MGS step j: v_0..v_j read and v_{j+1} written,
         // (j + 2) vectors of u_g per column (z, read once more by the kernel,
         // is not counted)
-        add_mgs_profile(ms, (double)(j + 2) * (double)nr * sizeof(VT));
+        add_mgs_profile(ms, (double)(jd + 2) * (double)nr * sizeof(VT));
       }
-      const double *hn = hq.data(), *hres = hq.data() + R;
+      const double *hn = ring.hq(slot), *hres = hn + R;
       bool changed = false;
       for (int c = 0; c < R; c++) {
         if (!gm_active[c]) continue;
-        kc[c] = j + 1;
-        if (hres[c] <= tol->tau * hbeta[c] || hn[c] == 0.0 || j + 1 == m) {
+        kc[c] = jd + 1;
+        if (hres[c] <= tol->tau * hbeta[c] || hn[c] == 0.0 || jd + 1 == m) {
           gm_active[c] = 0;
           nrun--;
           changed = true;
         }
       }
-      if (changed) BSPAI_HIP(hipMemcpyAsync(GMA, gm_active.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
+      if (changed && !mgs1) BSPAI_HIP(hipMemcpyAsync(GMA, gm_active.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
     }
     BSPAI_HIP(hipMemcpyAsync(KC, kc.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_b_backsub, dim3(1), dim3(64), 0, s, R, m, H, G, KC, Y);
+    hipLaunchKernelGGL(k_b_backsub, dim3(R), dim3(64), (size_t)3 * m * sizeof(double), s, R, m, H, G, KC, Y);
     BSPAI_CHECK_LAUNCH();
     if (!tr) {
       hipLaunchKernelGGL(k_b_update<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, m, V, nr, Y, KC, x, nullptr, P1, P2);
