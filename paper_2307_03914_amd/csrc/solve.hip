@@ -1645,24 +1645,18 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
   __shared__ double wpart[2][kWaves * C];
   __shared__ double res[2][2 * C];
   // rows t0 + r T, 16 bytes each (byte offsets fit 32 bits: n <= 2^21).
-  // Rows r < RPT - 1 exist for every thread (the launcher checks
-  // (RPT - 1) T <= n), so they are loaded unconditionally, all in flight
-  // together; only the last slot can lie past row n - 1, where it is zero.
+  // Every access goes through a buffer resource of n rows, whose range check
+  // (on the thread offset plus the uniform row offset) reads rows past n - 1
+  // as zero and drops stores to them: no load or store sits behind a branch,
+  // so the wait counts stay exact and loads issued early stay in flight.
   const unsigned T = gridDim.x * kSolveThreads;
   const unsigned t0 = blockIdx.x * kSolveThreads + threadIdx.x;
   const int n = p.n, j = p.j;
-  const bool last_ok = (int64_t)t0 + (int64_t)(RPT - 1) * T < n;
   const unsigned b0 = t0 * 16u, bs = T * 16u, nbytes = (unsigned)n * 16u;
   auto load_rows = [&](const VT *base, VT (&dst)[RPT][C]) {
     const __amdgpu_buffer_rsrc_t rs = rows_rsrc(base, nbytes);
 #pragma unroll
-    for (int r = 0; r < RPT - 1; r++) load_row16<VT, C>(rs, b0, (unsigned)r * bs, dst[r]);
-    if (last_ok) {
-      load_row16<VT, C>(rs, b0, (unsigned)(RPT - 1) * bs, dst[RPT - 1]);
-    } else {
-#pragma unroll
-      for (int c = 0; c < C; c++) dst[RPT - 1][c] = (VT)0;
-    }
+    for (int r = 0; r < RPT; r++) load_row16<VT, C>(rs, b0, (unsigned)r * bs, dst[r]);
   };
   VT va[RPT][C], vb[RPT][C];
   VT zreg[ZL ? 1 : RPT][C];
@@ -1701,10 +1695,12 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
   // one pass; vp holds v_{i-1} (refilled with v_{i+1}), vc holds v_i.  The
   // first pass (no update) is a separate instance.  Each row of v_{i+1} is
   // requested as soon as the row of v_{i-1} in its registers has been used,
-  // so the loads run under this pass's arithmetic and exchange.
+  // so the loads run under this pass's arithmetic and exchange (the last two
+  // passes have no v_{i+1}: an empty resource, whose loads return zero
+  // without touching memory).
   auto pass = [&](auto first, int i2, VT (&vp)[RPT][C], const VT (&vc)[RPT][C]) -> bool {
     const bool pre = i2 + 1 <= j;
-    const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.V + (int64_t)(pre ? i2 + 1 : 0) * p.vstride, nbytes);
+    const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.V + (int64_t)(pre ? i2 + 1 : 0) * p.vstride, pre ? nbytes : 0u);
     double part[C];
 #pragma unroll
     for (int c = 0; c < C; c++) part[c] = 0.0;
@@ -1717,14 +1713,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
         for (int c = 0; c < C; c++) zr[c] = (VT)fma(-h[c], (double)vp[r][c], (double)zr[c]);
         zput(r, zr);
       }
-      if (pre) {
-        if (r < RPT - 1 || last_ok) {
-          load_row16<VT, C>(rs, b0, (unsigned)r * bs, vp[r]);
-        } else {
-#pragma unroll
-          for (int c = 0; c < C; c++) vp[r][c] = (VT)0;
-        }
-      }
+      load_row16<VT, C>(rs, b0, (unsigned)r * bs, vp[r]);
 #pragma unroll
       for (int c = 0; c < C; c++) {
         const double w = i2 <= j ? (double)vc[r][c] : (double)zr[c];
@@ -1748,13 +1737,11 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
       const __amdgpu_buffer_rsrc_t rs = rows_rsrc(p.V + (int64_t)(j + 1) * p.vstride, nbytes);
 #pragma unroll
       for (int r = 0; r < RPT; r++) {
-        if (r < RPT - 1 || last_ok) {
-          VT zr[C], o[C];
-          zget(r, zr);
+        VT zr[C], o[C];
+        zget(r, zr);
 #pragma unroll
-          for (int c = 0; c < C; c++) o[c] = hn[c] > 0.0 ? (VT)((double)zr[c] / hn[c]) : (VT)0;
-          store_row16<VT, C>(rs, b0, (unsigned)r * bs, o);
-        }
+        for (int c = 0; c < C; c++) o[c] = hn[c] > 0.0 ? (VT)((double)zr[c] / hn[c]) : (VT)0;
+        store_row16<VT, C>(rs, b0, (unsigned)r * bs, o);
       }
     }
     return true;
@@ -1798,8 +1785,8 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
   const int rpt = mgs_persist_rpt(n);
   if (!rpt) return fail(BSPAI_EINVAL, "batched MGS: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
   const int G = (int)(((int64_t)n + (int64_t)kSolveThreads * rpt - 1) / ((int64_t)kSolveThreads * rpt));
-  // the kernel loads rows t + r T, r < rpt - 1, of every grid thread t
-  // without a bounds test: they must all lie below n
+  // layout check: every grid thread t owns rows t + r T, r < rpt - 1, below n
+  // (the kernel's range-checked accesses would also cover rows past n)
   if ((int64_t)(rpt - 1) * G * kSolveThreads > n)
     return fail(BSPAI_EINVAL, "batched MGS: %d rows per thread on %d blocks overrun n = %d", rpt, G, n);
   const size_t slot_bytes = 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols;
