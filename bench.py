@@ -495,20 +495,31 @@ def powerlaw_bench(B, W, torch, np, kw, reps=50):
     h = B.build(Ad, Pd, eps=c["eps"][0], precs=c["precs"])
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    h.tune_apply()
-    st = h.stats()
     x = torch.randn(n, device="cuda", dtype=torch.float32)
     y = torch.empty_like(x)
-    for _ in range(3):
-        B.apply(h, x, out=y)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        B.apply(h, x, out=y)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def time_apply():
+        for _ in range(3):
+            B.apply(h, x, out=y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            B.apply(h, x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    by_kind = {}
+    for kind, name in ((2, "lds_tiles"), (4, "lanes_per_row"), (5, "entry_balanced_tiles")):
+        try:
+            h.set_apply_kind(kind)
+        except B.BSPAIError:
+            continue
+        by_kind[name] = time_apply() * 1e3
+    h.tune_apply()
+    st = h.stats()
+    ms = time_apply()
     nb = sum(1 for cc, p in zip(st["count"], st["precs"]) if cc > 0 and p != 5)
     alg = sum(cc * (VALUE_BYTES[p] + 4) for cc, p in zip(st["count"], st["precs"]) if p != 5)
     alg += 4 * (n + 1) * nb + 8 * n
@@ -548,7 +559,8 @@ def powerlaw_bench(B, W, torch, np, kw, reps=50):
     res = {"workload": f"random n={n}, power-law rows (mean 13, max 401), lognormal(4) values, diagonal 1.1x "
                        f"dominant; SPAI pattern(A), buckets fp64/fp32/fp16/fp8 eps=1e-3; stop on eta <= 2^-51",
            "build_s": build_s, "bucket_counts": st["count"], "storage_pct": st["storage_pct"],
-           "apply_kind": st["apply_kind"], "apply_us": ms * 1e3, "apply_algorithmic_bytes": alg,
+           "apply_kind": st["apply_kind"], "apply_us": ms * 1e3, "apply_us_by_kernel": by_kind,
+           "apply_algorithmic_bytes": alg,
            "apply_GBs": alg / (ms * 1e-3) / 1e9, "apply_frac_of_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
            "solve_at_eps_1e-3": {k: head[k] for k in ("its", "eta", "relres", "status", "stop_reason", "converged",
                                                       "solves_per_s")},

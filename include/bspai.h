@@ -327,7 +327,11 @@ int bspai_export_pattern(const bspai_handle *M, int32_t *row_ptr_host, int32_t *
  *   0 automatic: ELL/SELL copies when every bucket has one, else LDS tiles;
  *   1 the padded copies (ELL with byte or int16 column codes, else SELL-64);
  *   2 LDS tiles of contiguous rows (balanced for rows of any length);
- *   3 two rows per thread;  4 a group of lanes per row.
+ *   3 two rows per thread;  4 a group of lanes per row;
+ *   5 entry-balanced tiles of whole rows (about 4096 entries per block, a
+ *     plan built with the handle; rows of more than 32 entries are added by
+ *     a whole wavefront), for rows of very different lengths with scattered
+ *     columns; not available when a row has more than 4096 entries.
  * bspai_set_apply_kind -- use kernel `kind` for M_b (trans = 0) or M_b^T
  *   (trans = 1); EINVAL when the handle lacks what the kernel needs (kind 1:
  *   a copy for every bucket; padded copies are not built where padding would
@@ -357,7 +361,7 @@ typedef struct {
     int32_t ell_width[6];    /* width W of the bucket's row-major padded copy used by bspai_apply (0: none) */
     int32_t col_bytes[6];    /* bytes per column index that bspai_apply reads for the bucket: 1 (index
                                 into 256 offsets col - row), 2 (int16 offset) or 4 */
-    int32_t apply_kind[2];   /* kernel bspai_apply / bspai_apply_T use (1..4, see bspai_set_apply_kind;
+    int32_t apply_kind[2];   /* kernel bspai_apply / bspai_apply_T use (1..5, see bspai_set_apply_kind;
                                 0 for apply_T without build_T) */
 } bspai_bucket_stats;
 

@@ -305,7 +305,8 @@ class Handle:
 
     def set_apply_kind(self, kind: int, trans: bool = False) -> None:
         """Kernel of apply (trans False) or apply_T: 0 automatic, 1 padded
-        copies, 2 LDS tiles, 3 two rows per thread, 4 lanes per row."""
+        copies, 2 LDS tiles, 3 two rows per thread, 4 lanes per row,
+        5 entry-balanced tiles (long rows summed by a wavefront)."""
         _check(_lib.bspai_set_apply_kind(self.ptr, int(trans), int(kind)))
 
     def tune_apply(self, stream=None) -> None:

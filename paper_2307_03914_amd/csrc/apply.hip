@@ -417,6 +417,319 @@ static int launch_vec(const BMat &M, const XT *x, XT *y, int lanes, hipStream_t 
   return BSPAI_OK;
 }
 
+// ------------------------------------------------------------------ segmented tiles
+//
+// For rows of very different lengths with scattered columns (a power-law
+// matrix): the rows are cut into tiles of whole rows holding about
+// kSegTile entries over all buckets (a plan built with the handle), one
+// block per tile.  Phase 1 streams every bucket's entries of the tile with
+// 8-wide aligned non-temporal loads (each thread keeps 8 gathers of x in
+// flight) and writes the products to LDS; phase 2 adds each row's products
+// in CSR order, one thread per row, except rows of more than kSegLong
+// entries, which a whole wavefront adds (lane l takes products l, l + 64,
+// ..., then a fixed butterfly), so a long row does not hold its block.
+// Per-bucket sums in FP32 (FP64 for wide products), scaled and added in FP64
+// from the least to the most precise bucket, as in the other kernels; the
+// order of additions inside a row is fixed by the plan, so repeated products
+// give identical bits.
+constexpr int kSegTile = 4096;
+constexpr int kSegLong = 32;
+constexpr int kSegMaxLong = 2 * kSegTile / (kSegLong + 1) + 1;
+
+template <typename T>
+__device__ __forceinline__ T wave_butterfly_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// one bucket's entries [b0, b1) of a tile into LDS products (pk indexed by
+// entry), the value format fixed at compile time: each thread takes up to
+// kSegChunks aligned 8-entry chunks, issues all their column and value loads,
+// then all their gathers, then writes the products of the entries inside
+// [b0, b1).  Loads go through buffer resources whose extent is the 16-byte
+// granule holding entry b1 - 1 (a 16-byte load that crosses the extent
+// returns zero as a whole; the granule never crosses a page), so chunks past
+// the tile read zero without a branch around a load; entries at or past b1
+// gather x[t] of their lane (coalesced, never written).  The chunk loop runs
+// the same number of times in every thread of the block.
+constexpr int kSegChunks = 2;  // 8-entry chunks per thread in flight
+template <int FMT, typename XT, typename PT>
+__device__ __forceinline__ void seg_stream(const BMat &M, int k, int b0, int b1, const XT *__restrict__ x,
+                                           PT *pk) {
+  constexpr int VB = FMT == BSPAI_FP64 ? 8 : FMT == BSPAI_FP32 ? 4 : (FMT == BSPAI_FP8_E4M3 ? 1 : 2);
+  const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t *>(M.col[k]), (short)0,
+                                                                      (4 * b1 + 15) & ~15, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(M.val[k]), (short)0,
+                                                                      (VB * b1 + 15) & ~15, 0x00020000);
+  const int a0 = b0 & ~(kTileVec - 1), first = a0 + threadIdx.x * kTileVec;
+  constexpr int kStride = kApplyThreads * kTileVec;
+  const int groups = (b1 - a0 + kSegChunks * kStride - 1) / (kSegChunks * kStride);
+  const int spare = min((int)threadIdx.x, M.n - 1);
+  for (int g = 0, base0 = first; g < groups; g++, base0 += kSegChunks * kStride) {
+    int cc[kSegChunks][kTileVec];
+    PT vv[kSegChunks][kTileVec];
+#pragma unroll
+    for (int u = 0; u < kSegChunks; u++) {
+      const unsigned base = (unsigned)(base0 + u * kStride);
+      const auto c0 = __builtin_amdgcn_raw_buffer_load_b128(rc, 4u * base, 0u, 2);
+      const auto c1 = __builtin_amdgcn_raw_buffer_load_b128(rc, 4u * base + 16u, 0u, 2);
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        cc[u][t] = (int)base + t < b1 ? (int)c0[t] : spare;
+        cc[u][4 + t] = (int)base + 4 + t < b1 ? (int)c1[t] : spare;
+      }
+      if constexpr (FMT == BSPAI_FP8_E4M3) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b64(rv, base, 0u, 2);
+#pragma unroll
+        for (int t = 0; t < 8; t++) vv[u][t] = (PT)decode_e4m3((uint8_t)((w[t >> 2] >> (8 * (t & 3))) & 0xFFu));
+      } else if constexpr (FMT == BSPAI_FP16 || FMT == BSPAI_BF16) {
+        const auto w = __builtin_amdgcn_raw_buffer_load_b128(rv, 2u * base, 0u, 2);
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          const uint16_t h = (uint16_t)((w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu);
+          vv[u][t] = (PT)(FMT == BSPAI_FP16 ? decode_f16(h) : decode_bf16(h));
+        }
+      } else if constexpr (FMT == BSPAI_FP32) {
+        const auto w0 = __builtin_amdgcn_raw_buffer_load_b128(rv, 4u * base, 0u, 2);
+        const auto w1 = __builtin_amdgcn_raw_buffer_load_b128(rv, 4u * base + 16u, 0u, 2);
+#pragma unroll
+        for (int t = 0; t < 4; t++) vv[u][t] = (PT)__uint_as_float(w0[t]), vv[u][4 + t] = (PT)__uint_as_float(w1[t]);
+      } else {
+#pragma unroll
+        for (int h2 = 0; h2 < 4; h2++) {
+          const auto w = __builtin_amdgcn_raw_buffer_load_b128(rv, 8u * base + 16u * h2, 0u, 2);
+          vv[u][2 * h2] = (PT)__longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+          vv[u][2 * h2 + 1] = (PT)__longlong_as_double((long long)(((unsigned long long)w[3] << 32) | w[2]));
+        }
+      }
+    }
+    PT xv[kSegChunks][kTileVec];
+#pragma unroll
+    for (int u = 0; u < kSegChunks; u++)
+#pragma unroll
+      for (int t = 0; t < kTileVec; t++) xv[u][t] = (PT)x[cc[u][t]];
+#pragma unroll
+    for (int u = 0; u < kSegChunks; u++)
+#pragma unroll
+      for (int t = 0; t < kTileVec; t++) {
+        const int e = base0 + u * kStride + t;
+        if (e >= b0 && e < b1) pk[e] = vv[u][t] * xv[u][t];
+      }
+  }
+}
+
+template <typename XT, typename PT>
+__global__ void __launch_bounds__(kApplyThreads) k_bspmv_seg(BMat M, const XT *__restrict__ x, XT *__restrict__ y) {
+  extern __shared__ double seg_lds[];
+  PT *prod = reinterpret_cast<PT *>(seg_lds);
+  __shared__ int nlong;
+  __shared__ int longrow[kSegMaxLong];
+  const int tile = xcd_block(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x, nb = M.nb;
+  // the tile's rows and each bucket's entry range, from the plan in one round
+  const int r0 = M.seg_rows[tile], r1 = M.seg_rows[tile + 1];
+  int e0[kMaxBuckets], off[kMaxBuckets + 1];
+  off[0] = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxBuckets; k++) {
+    if (k < nb) {
+      e0[k] = M.seg_off[tile * nb + k];
+      off[k + 1] = off[k] + (M.seg_off[(tile + 1) * nb + k] - e0[k]);
+    } else {
+      e0[k] = 0;
+      off[k + 1] = off[k];
+    }
+  }
+  // row pointers of the thread's first two rows, loaded under the gathers
+  constexpr int RR = 2;
+  int ra[RR][kMaxBuckets], rb[RR][kMaxBuckets];
+#pragma unroll
+  for (int r = 0; r < RR; r++) {
+    const int i = r0 + tid + r * kApplyThreads;
+#pragma unroll
+    for (int k = 0; k < kMaxBuckets; k++) {
+      const bool ok = k < nb && i < r1;
+      ra[r][k] = ok ? M.rp[k][i] : 0;
+      rb[r][k] = ok ? M.rp[k][i + 1] : 0;
+    }
+  }
+  if (tid == 0) nlong = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxBuckets; k++) {
+    if (k >= nb) break;
+    const int b0 = e0[k], b1 = b0 + (off[k + 1] - off[k]);
+    PT *pk = prod + off[k] - b0;
+    switch (M.prec[k]) {
+      case BSPAI_FP64: seg_stream<BSPAI_FP64, XT, PT>(M, k, b0, b1, x, pk); break;
+      case BSPAI_FP32: seg_stream<BSPAI_FP32, XT, PT>(M, k, b0, b1, x, pk); break;
+      case BSPAI_FP16: seg_stream<BSPAI_FP16, XT, PT>(M, k, b0, b1, x, pk); break;
+      case BSPAI_BF16: seg_stream<BSPAI_BF16, XT, PT>(M, k, b0, b1, x, pk); break;
+      default: seg_stream<BSPAI_FP8_E4M3, XT, PT>(M, k, b0, b1, x, pk); break;
+    }
+  }
+  __syncthreads();
+  for (int r = 0, i = r0 + tid; i < r1; r++, i += kApplyThreads) {
+    int a[kMaxBuckets], b[kMaxBuckets], len = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxBuckets; k++) {
+      if (r < RR) {
+        a[k] = r == 0 ? ra[0][k] : ra[1][k];
+        b[k] = r == 0 ? rb[0][k] : rb[1][k];
+      } else {
+        a[k] = k < nb ? M.rp[k][i] : 0;
+        b[k] = k < nb ? M.rp[k][i + 1] : 0;
+      }
+      len += b[k] - a[k];
+    }
+    if (len > kSegLong) {
+      longrow[atomicAdd(&nlong, 1)] = i;
+      continue;
+    }
+    double total = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxBuckets; k++) {
+      if (k >= nb) break;
+      const PT *pk = prod + off[k] - e0[k];
+      if (M.prec[k] == BSPAI_FP64 || sizeof(PT) == 8) {
+        double sum = 0.0;
+        for (int q = a[k]; q < b[k]; q++) sum += (double)pk[q];
+        total += sum * M.scale[k];
+      } else {
+        float sum = 0.f;
+        for (int q = a[k]; q < b[k]; q++) sum += (float)pk[q];
+        total += (double)sum * M.scale[k];
+      }
+    }
+    y[i] = (XT)total;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int q = wv; q < nlong; q += kApplyThreads / 64) {
+    const int i = longrow[q];
+    double total = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxBuckets; k++) {
+      if (k >= nb) break;
+      const int a = M.rp[k][i], b = M.rp[k][i + 1];
+      const PT *pk = prod + off[k] - e0[k];
+      if (M.prec[k] == BSPAI_FP64 || sizeof(PT) == 8) {
+        double sum = 0.0;
+        for (int p = a + lane; p < b; p += 64) sum += (double)pk[p];
+        total += wave_butterfly_sum(sum) * M.scale[k];
+      } else {
+        float sum = 0.f;
+        for (int p = a + lane; p < b; p += 64) sum += (float)pk[p];
+        total += (double)wave_butterfly_sum(sum) * M.scale[k];
+      }
+    }
+    if (lane == 0) y[i] = (XT)total;
+  }
+}
+
+template <typename XT, typename PT>
+static int launch_seg(const BMat &M, const XT *x, XT *y, hipStream_t s) {
+  if (M.seg_ntiles == 0) return BSPAI_OK;
+  const size_t lds = (size_t)M.seg_cap * sizeof(PT);
+  static bool attr = false;  // raise the dynamic LDS limit once per instantiation
+  if (!attr) {
+    BSPAI_HIP(hipFuncSetAttribute((const void *)k_bspmv_seg<XT, PT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_bspmv_seg<XT, PT>), dim3((unsigned)M.seg_ntiles), dim3(kApplyThreads), lds, s, M, x, y);
+  BSPAI_CHECK_LAUNCH();
+  return BSPAI_OK;
+}
+
+// entries of row i over all buckets, and the longest row
+__global__ void k_seg_len(BMat M, int32_t *len, int32_t *mx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.n) return;
+  int l = 0;
+  for (int k = 0; k < M.nb; k++) l += M.rp[k][i + 1] - M.rp[k][i];
+  len[i] = l;
+  atomicMax(mx, l);
+}
+
+// rows[t] = the first row whose entries start at or after t kSegTile
+// (pre: exclusive prefix of the row lengths, n + 1 entries); rows[nt] = n;
+// off[t nb + k] = the first entry of bucket k in tile t
+__global__ void k_seg_bounds(BMat M, const int32_t *pre, int nt, int32_t *rows, int32_t *off) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > nt) return;
+  const int n = M.n;
+  int lo = n;
+  if (t < nt) {
+    const int64_t target = (int64_t)t * kSegTile;
+    int hi = n;  // smallest r in [0, n] with pre[r] >= target
+    lo = 0;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      if (pre[mid] >= target)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+  }
+  rows[t] = lo;
+  for (int k = 0; k < M.nb; k++) off[(int64_t)t * M.nb + k] = M.rp[k][lo];
+}
+
+int build_seg_plan(BMat &M, int32_t **rows, hipStream_t s) {
+  *rows = nullptr;
+  M.seg_rows = nullptr;
+  M.seg_off = nullptr;
+  M.seg_ntiles = 0;
+  M.seg_cap = 0;
+  if (M.n == 0 || M.nb == 0) return BSPAI_OK;
+  const int n = M.n;
+  int32_t *len = nullptr, *pre = nullptr, *mx = nullptr;
+  void *tmp = nullptr;
+  int rc;
+  if ((rc = dalloc_t(&len, (size_t)n)) || (rc = dalloc_t(&pre, (size_t)n + 1)) || (rc = dalloc_t(&mx, 1)) ||
+      (rc = dalloc(&tmp, scan_tmp_bytes(n)))) {
+    dfree(len), dfree(pre), dfree(mx), dfree(tmp);
+    return rc;
+  }
+  int32_t hmx = 0, total = 0;
+  auto body = [&]() -> int {
+    BSPAI_HIP(hipMemsetAsync(mx, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_seg_len, dim3((n + 255) / 256), dim3(256), 0, s, M, len, mx);
+    BSPAI_CHECK_LAUNCH();
+    int r = exclusive_scan(len, pre, n, tmp, s);
+    if (r) return r;
+    BSPAI_HIP(hipMemcpyAsync(&hmx, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipMemcpyAsync(&total, pre + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSPAI_HIP(hipStreamSynchronize(s));
+    // no plan for a row longer than a tile, or for byte offsets of the
+    // buffer loads (8 per FP64 entry) that would not fit 31 bits
+    if (hmx > kSegTile || total > (1 << 28)) return BSPAI_OK;
+    const int nt = std::max(1, (total + kSegTile - 1) / kSegTile);
+    // one allocation: nt + 1 tile rows, then (nt + 1) nb bucket offsets
+    if ((r = dalloc_t(rows, (size_t)(nt + 1) * (1 + M.nb)))) return r;
+    int32_t *off = *rows + nt + 1;
+    hipLaunchKernelGGL(k_seg_bounds, dim3((nt + 1 + 255) / 256), dim3(256), 0, s, M, pre, nt, *rows, off);
+    BSPAI_CHECK_LAUNCH();
+    BSPAI_HIP(hipStreamSynchronize(s));
+    M.seg_rows = *rows;
+    M.seg_off = off;
+    M.seg_ntiles = nt;
+    M.seg_cap = 2 * kSegTile;  // a tile holds fewer than kSegTile + (longest row) entries
+    return BSPAI_OK;
+  };
+  rc = body();
+  dfree(len), dfree(pre), dfree(mx), dfree(tmp);
+  if (rc) {
+    dfree(*rows);
+    *rows = nullptr;
+    M.seg_rows = nullptr;
+    M.seg_off = nullptr;
+    M.seg_ntiles = 0;
+  }
+  return rc;
+}
+
 // every stored bucket has an ELL or a SELL copy
 static bool sell_ok(const BMat &M) {
   for (int k = 0; k < M.nb; k++)
@@ -431,6 +744,7 @@ bool apply_kind_ok(const BMat &M, int kind) {
     case kApplyTile: return M.aligned != 0;
     case kApplyRows:
     case kApplyLanes: return true;
+    case kApplySeg: return M.seg_rows != nullptr && M.aligned != 0;
   }
   return false;
 }
@@ -450,6 +764,7 @@ static int launch_one(const BMat &M, const XT *x, XT *y, int kind, hipStream_t s
     case kApplySell: return launch_sell<XT, PT>(M, x, y, s);
     case kApplyTile: return launch_tile<XT, PT>(M, x, y, s);
     case kApplyRows: return launch_rowthread<XT, PT>(M, x, y, s);
+    case kApplySeg: return launch_seg<XT, PT>(M, x, y, s);
     default: return launch_vec<XT>(M, x, y, M.lanes > 0 ? M.lanes : pick_lanes(M, M.nnz), s);
   }
 }
@@ -631,7 +946,7 @@ static int time_kind(const BMat &M, int kind, const float *x, float *y, hipStrea
 static int tune_one(BMat &M, const float *x, float *y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   int best = kApplyAuto;
   float best_ms = 0.f;
-  for (int kind : {kApplySell, kApplyTile, kApplyRows, kApplyLanes}) {
+  for (int kind : {kApplySell, kApplyTile, kApplyRows, kApplyLanes, kApplySeg}) {
     if (!apply_kind_ok(M, kind)) continue;
     float ms = 0.f;
     int rc = time_kind(M, kind, x, y, s, e0, e1, &ms);
@@ -649,7 +964,7 @@ extern "C" int bspai_set_apply_kind(bspai_handle *M, int trans, int kind) {
   if (!M) return fail(BSPAI_EINVAL, "bspai_set_apply_kind: null handle");
   if (trans && !M->has_T) return fail(BSPAI_EINVAL, "bspai_set_apply_kind: handle built without build_T");
   BMat &B = trans ? M->matT : M->mat;
-  if (kind < kApplyAuto || kind > kApplyLanes || !apply_kind_ok(B, kind))
+  if (kind < kApplyAuto || kind > kApplySeg || !apply_kind_ok(B, kind))
     return fail(BSPAI_EINVAL, "bspai_set_apply_kind: kernel %d is not available for this matrix", kind);
   B.apply_kind = kind;
   return BSPAI_OK;

@@ -964,6 +964,7 @@ static void free_handle_memory(bspai_handle *h) {
   dfree(h->m_rp), dfree(h->m_col), dfree(h->m_val);
   dfree(h->mT_rp), dfree(h->mT_col), dfree(h->mT_val);
   dfree(h->bucket_id), dfree(h->stored);
+  dfree(h->seg_rows), dfree(h->seg_rowsT);
 }
 
 // Buckets, packing and (optionally) transposed packing of h->m_* (FP64 M).
@@ -1142,6 +1143,11 @@ static int bucketize(bspai_handle *h, const bspai_prec *precs, int q, double eps
       if ((r = csr_transpose(n, nnz, h->m_rp, h->m_col, h->m_val, 8, h->mT_rp, h->mT_col, h->mT_val, s))) return r;
     }
     h->has_T = 1;
+  }
+  {  // entry-balanced tile plans for the segmented product (after matT copied mat)
+    int r;
+    if ((r = build_seg_plan(h->mat, &h->seg_rows, s))) return r;
+    if (h->has_T && (r = build_seg_plan(h->matT, &h->seg_rowsT, s))) return r;
   }
   return BSPAI_OK;
 }

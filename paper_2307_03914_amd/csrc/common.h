@@ -74,10 +74,18 @@ struct BMat {
   // kernel of the single-vector product: 0 chosen from the layout, else one
   // of the ApplyKind values (set by bspai_set_apply_kind / bspai_tune_apply)
   int32_t apply_kind;
+  // entry-balanced tiles of whole rows for the segmented product: tile t
+  // holds rows seg_rows[t] .. seg_rows[t + 1] - 1, with fewer than seg_cap
+  // entries over all buckets, whose entries of bucket k start at
+  // seg_off[t nb + k]; seg_rows null: no plan
+  const int32_t *seg_rows;
+  const int32_t *seg_off;
+  int32_t seg_ntiles;
+  int32_t seg_cap;
 };
 
 // kernels of the single-vector bucketed product
-enum ApplyKind { kApplyAuto = 0, kApplySell = 1, kApplyTile = 2, kApplyRows = 3, kApplyLanes = 4 };
+enum ApplyKind { kApplyAuto = 0, kApplySell = 1, kApplyTile = 2, kApplyRows = 3, kApplyLanes = 4, kApplySeg = 5 };
 
 constexpr int kSlice = 64;
 
@@ -116,6 +124,7 @@ struct bspai_handle {
   double *stored = nullptr;     // decoded stored value per entry (FP64), CSR order
   int has_T = 0, has_fp64 = 0;
   bspai::BMat mat, matT;
+  int32_t *seg_rows = nullptr, *seg_rowsT = nullptr;  // tile plans of mat and matT
   int device = 0;
 };
 
@@ -187,6 +196,10 @@ int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, in
 // whether M has what kernel `kind` needs, and the kernel used when none is set
 bool apply_kind_ok(const BMat &M, int kind);
 int apply_kind_resolved(const BMat &M);
+// Entry-balanced tile plan of M for the segmented product (sets M.seg_*);
+// *rows is allocated here and owned by the caller.  No plan (and BSPAI_OK)
+// when some row has more entries than a tile holds.
+int build_seg_plan(BMat &M, int32_t **rows, hipStream_t s);
 
 // One Arnoldi step's MGS over an n x (16 / sizeof(VT)) row-major column
 // group as one cooperative kernel (solve.hip).  mgs_persist_rpt(n) is 0 when

@@ -385,8 +385,9 @@ def test_apply_narrow_column_codes(B, kind, col_bytes, width):
 @pytest.mark.parametrize("key", ["2s", "3s", "4as", "5s"])
 def test_apply_every_kernel_and_tuning(B, key):
     """Every single-vector apply kernel the handle supports (padded copies,
-    LDS tiles, two rows per thread, lanes per row), both orientations,
-    against the oracle; then the tuner's choice."""
+    LDS tiles, two rows per thread, lanes per row, entry-balanced tiles with
+    wavefront sums of long rows), both orientations, against the oracle;
+    then the tuner's choice."""
     import torch
 
     c = W.config(key[:-1], small=True)
@@ -401,7 +402,7 @@ def test_apply_every_kernel_and_tuning(B, key):
     refs = {t: (O.apply_T if t else O.apply)(Mb, x, O.FP64) for t in (False, True)}
     bounds = {t: _apply_bound(Mb, x, U32, transpose=t) + U32 * np.abs(refs[t]) for t in (False, True)}
     ran = 0
-    for kind in (1, 2, 3, 4, 0):
+    for kind in (1, 2, 3, 4, 5, 0):
         for t in (False, True):
             try:
                 h.set_apply_kind(kind, trans=t)
@@ -411,15 +412,46 @@ def test_apply_every_kernel_and_tuning(B, key):
             y = (B.apply_T if t else B.apply)(h, xd).double().cpu().numpy()
             assert np.all(np.abs(y - refs[t]) <= bounds[t] + 1e-300), (key, kind, t)
             ran += 1
-    assert ran >= 8
+    assert ran >= 10
     h.tune_apply()
     st = h.stats()
-    assert all(1 <= k <= 4 for k in st["apply_kind"]), st["apply_kind"]
+    assert all(1 <= k <= 5 for k in st["apply_kind"]), st["apply_kind"]
     for t in (False, True):
         y = (B.apply_T if t else B.apply)(h, xd).double().cpu().numpy()
         assert np.all(np.abs(y - refs[t]) <= bounds[t] + 1e-300)
     with pytest.raises(B.BSPAIError):
         h.set_apply_kind(7)
+    h.free()
+
+
+def test_apply_segmented_tiles_power_law(B):
+    """The entry-balanced tile kernel on power-law rows (up to 121 entries:
+    529 rows take the wavefront path) with scattered columns: both
+    orientations against the oracle, identical bits on a repeat, and the
+    same results from FP64 vectors."""
+    import torch
+
+    c = W.config("3", small=True)
+    A, P = c["A"], c["P"]
+    assert np.diff(P.row_ptr).max() > 32
+    _say("apply segmented tiles", A.n)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, c["eps"][0], c["precs"])
+    h = B.import_m(B.CSRMatrix.from_host(M), c["eps"][0], c["precs"])
+    x = np.random.default_rng(12).standard_normal(A.n).astype(np.float32).astype(np.float64)
+    for t in (False, True):
+        h.set_apply_kind(5, trans=t)
+        ref = (O.apply_T if t else O.apply)(Mb, x, O.FP64)
+        bound = _apply_bound(Mb, x, U32, transpose=t) + U32 * np.abs(ref)
+        f = B.apply_T if t else B.apply
+        y1 = f(h, _dev(x, torch.float32)).double().cpu().numpy()
+        y2 = f(h, _dev(x, torch.float32)).double().cpu().numpy()
+        assert np.all(np.abs(y1 - ref) <= bound + 1e-300), t
+        assert np.array_equal(y1, y2)
+        y64 = f(h, _dev(x, torch.float64)).cpu().numpy()
+        b64 = _apply_bound(Mb, x, U64, transpose=t) + U64 * np.abs(ref)
+        assert np.all(np.abs(y64 - ref) <= b64 + 1e-300), t
+    assert h.stats()["apply_kind"] == [5, 5]
     h.free()
 
 
