@@ -203,14 +203,13 @@ int build_seg_plan(BMat &M, int32_t **rows, hipStream_t s);
 
 // One Arnoldi step's MGS over an n x (16 / sizeof(VT)) row-major column
 // group as one cooperative kernel (solve.hip).  mgs_persist_rpt(n) is 0 when
-// n is too large for it; ws needs mgs_persist_ws_bytes() bytes, the abort
-// flag sits at mgs_persist_abort_offset().
+// n is too large for it; ws needs mgs_persist_ws_bytes() bytes of exchange
+// words, zeroed once before the first launch (see launch_mgs_persist).
 int mgs_persist_rpt(int n);
 size_t mgs_persist_ws_bytes();
-size_t mgs_persist_abort_offset();
 template <typename VT>
 int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn,
-                       const int *gma, void *ws, hipStream_t s);
+                       const int *gma, void *ws, unsigned rtag0, unsigned *abortf, hipStream_t s);
 
 // Instrumentation shared by the solvers (solve.hip): the profiling switch
 // (bspai_set_profiling) and the totals of the one-launch MGS kernel.

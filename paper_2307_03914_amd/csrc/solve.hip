@@ -1463,7 +1463,7 @@ static int multi_plan_typed(const bspai_system *sys, int nsys, const gmres_ir_to
 constexpr int kMgsCols = 4;  // column sums per exchange (FP32: 4, FP64: 2 used)
 
 struct MgsGrid {
-  // [kNumSlots][kMaxBlocks][kMgsCols][2] tagged words, cleared per launch:
+  // [kNumSlots][kMaxBlocks][kMgsCols][2] tagged words, cleared once per solve:
   // each block's words share one 64-byte line, written by one instruction
   // (column-major slots, whose polls coalesce, measured 4% slower per pass:
   // four blocks then write into every line)
@@ -1480,6 +1480,7 @@ struct BMgsParams {
   double *H;         // h_{i,j} of column c at H + (c * m + j) * (m + 1) + i, i <= j + 1
   double *hn;        // [C]: h_{j+1,j}
   const int *gma;    // [C] GMRES-active flags, or null: with none set the launch does nothing
+  unsigned rtag0;    // exchange rounds before this launch (its first round is rtag0 + 1)
   MgsGrid grid;
 };
 
@@ -1688,7 +1689,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_b_mgs_persist(BMgsParams<VT> 
   }
 #pragma unroll
   for (int r = 0; r < RPT; r++) zput(r, va[r]);
-  unsigned rtag = 0;
+  unsigned rtag = p.rtag0;
   double h[C];
 #pragma unroll
   for (int c = 0; c < C; c++) h[c] = 0.0;
@@ -1761,7 +1762,7 @@ int mgs_persist_rpt(int n) {
   return 0;
 }
 
-size_t mgs_persist_ws_bytes() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols + 256; }
+size_t mgs_persist_ws_bytes() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols; }
 
 template <typename VT, int RPT>
 static int launch_mgs_rpt(BMgsParams<VT> &p, int G, hipStream_t s) {
@@ -1777,11 +1778,14 @@ static int launch_mgs_rpt(BMgsParams<VT> &p, int G, hipStream_t s) {
 // One Arnoldi step's MGS (see k_b_mgs_persist) for the n x (16 / sizeof(VT))
 // block z, basis V (v_i at V + i * vstride), H columns of step j; gma: the
 // columns' GMRES-active flags (the launch returns at once when none is set),
-// or null; ws: mgs_persist_ws_bytes() of device memory (exchange words and
-// the abort flag, cleared here).  Enqueued on s.
+// or null; ws: mgs_persist_ws_bytes() of device memory holding the exchange
+// words, zeroed by the caller before the first launch on it; rtag0: the
+// exchange rounds of all earlier launches on ws (j + 2 per launch), so that
+// words left by them never carry a current tag; abortf: a zeroed word that a
+// timed-out exchange sets.  Enqueued on s.
 template <typename VT>
 int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride, double *H, double *hn,
-                       const int *gma, void *ws, hipStream_t s) {
+                       const int *gma, void *ws, unsigned rtag0, unsigned *abortf, hipStream_t s) {
   const int rpt = mgs_persist_rpt(n);
   if (!rpt) return fail(BSPAI_EINVAL, "batched MGS: n = %d exceeds %d rows", n, kMaxBlocks * kSolveThreads * 16);
   const int G = (int)(((int64_t)n + (int64_t)kSolveThreads * rpt - 1) / ((int64_t)kSolveThreads * rpt));
@@ -1789,8 +1793,6 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
   // (the kernel's range-checked accesses would also cover rows past n)
   if ((int64_t)(rpt - 1) * G * kSolveThreads > n)
     return fail(BSPAI_EINVAL, "batched MGS: %d rows per thread on %d blocks overrun n = %d", rpt, G, n);
-  const size_t slot_bytes = 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols;
-  BSPAI_HIP(hipMemsetAsync(ws, 0, mgs_persist_ws_bytes(), s));
   BMgsParams<VT> p;
   p.n = n;
   p.j = j;
@@ -1801,8 +1803,9 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
   p.H = H;
   p.hn = hn;
   p.gma = gma;
+  p.rtag0 = rtag0;
   p.grid.slots = static_cast<unsigned long long *>(ws);
-  p.grid.abortf = reinterpret_cast<unsigned *>(static_cast<char *>(ws) + slot_bytes);
+  p.grid.abortf = abortf;
   switch (rpt) {
     case 1: return launch_mgs_rpt<VT, 1>(p, G, s);
     case 2: return launch_mgs_rpt<VT, 2>(p, G, s);
@@ -1812,13 +1815,10 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
   }
 }
 
-// the abort flag's offset in the batched MGS workspace
-size_t mgs_persist_abort_offset() { return 16 * (size_t)kNumSlots * kMaxBlocks * kMgsCols; }
-
 template int launch_mgs_persist<float>(int, int, int, const float *, float *, int64_t, double *, double *,
-                                       const int *, void *, hipStream_t);
+                                       const int *, void *, unsigned, unsigned *, hipStream_t);
 template int launch_mgs_persist<double>(int, int, int, const double *, double *, int64_t, double *, double *,
-                                        const int *, void *, hipStream_t);
+                                        const int *, void *, unsigned, unsigned *, hipStream_t);
 
 }  // namespace bspai
 

@@ -505,10 +505,14 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   // or A_b^T), M_b (or M_b^T), FP64 M for x_0
   DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb, mgsws;
   int rc;
-  if (mgs1 && (rc = dalloc(&mgsws.p, mgs_persist_ws_bytes()))) return rc;
-  // per queued step: pinned copies of h_{j+1,j}, |g_{j+1}| and the MGS abort
-  // flag, the step's completion event, and (when profiling) HIP events
-  // around its MGS launch
+  if (mgs1) {
+    if ((rc = dalloc(&mgsws.p, mgs_persist_ws_bytes()))) return rc;
+    BSPAI_HIP(hipMemsetAsync(mgsws.p, 0, mgs_persist_ws_bytes(), s));
+  }
+  unsigned mgs_rounds = 0;  // exchange rounds of the MGS launches so far
+  // per queued step: a pinned copy of S rows 5-7 (h_{j+1,j}, |g_{j+1}|) and
+  // the MGS abort word, the step's completion event, and (when profiling)
+  // HIP events around its MGS launch
   const bool prof = mgs1 && profiling_on();
   struct StepRing {
     void *pin = nullptr;
@@ -516,8 +520,8 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
     hipStream_t st = nullptr;
     hipEvent_t done[kStepLag] = {};
     hipEvent_t prof[2 * kStepLag] = {};
-    double *hq(int k) { return static_cast<double *>(pin) + (size_t)k * (2 * R + 1); }
-    unsigned *abort(int k) { return reinterpret_cast<unsigned *>(hq(k) + 2 * R); }
+    double *hq(int k) { return static_cast<double *>(pin) + (size_t)k * (3 * R + 1); }
+    unsigned *abort(int k) { return reinterpret_cast<unsigned *>(hq(k) + 3 * R); }
     ~StepRing() {
       if (pin) (void)hipStreamSynchronize(st);  // copies into pin may still be queued on an error return
       for (auto q : done)
@@ -529,7 +533,7 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   } ring;
   ring.R = R;
   ring.st = s;
-  BSPAI_HIP(hipHostMalloc(&ring.pin, sizeof(double) * (size_t)kStepLag * (2 * R + 1), hipHostMallocDefault));
+  BSPAI_HIP(hipHostMalloc(&ring.pin, sizeof(double) * (size_t)kStepLag * (3 * R + 1), hipHostMallocDefault));
   for (int k = 0; k < kStepLag; k++) {
     BSPAI_HIP(hipEventCreateWithFlags(&ring.done[k], hipEventDisableTiming));
     if (prof) {
@@ -550,14 +554,16 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
       (rc = dalloc(&rv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&wv.p, sizeof(VT) * (size_t)nr)) ||
       (rc = dalloc(&zv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&Vb.p, sizeof(VT) * (size_t)nr * (m + 1))) ||
       (rc = dalloc(&dtmp.p, 8 * (size_t)nr)) || (rc = dalloc(&parts.p, 2 * 8 * (size_t)kBGrid * R)) ||
-      (rc = dalloc(&scal.p, 8 * 8 * (size_t)R)) || (rc = dalloc(&Hb.p, 8 * (size_t)R * m * (m + 1))) ||
+      (rc = dalloc(&scal.p, 8 * (8 * (size_t)R + 1))) || (rc = dalloc(&Hb.p, 8 * (size_t)R * m * (m + 1))) ||
       (rc = dalloc(&csb.p, 8 * (size_t)R * m)) || (rc = dalloc(&snb.p, 8 * (size_t)R * m)) ||
       (rc = dalloc(&gb.p, 8 * (size_t)R * (m + 1))) || (rc = dalloc(&yb.p, 8 * (size_t)R * m)) ||
       (rc = dalloc(&kcb.p, 4 * (size_t)R)) || (rc = dalloc(&actb.p, 4 * (size_t)R)))
     return rc;
   VT *Ap = (VT *)apv.p, *RV = (VT *)rv.p, *W = (VT *)wv.p, *Z = (VT *)zv.p, *V = (VT *)Vb.p;
   double *r64 = (double *)rbuf.p, *D = (double *)dtmp.p, *P1 = (double *)parts.p, *P2 = P1 + (int64_t)kBGrid * R;
-  double *S = (double *)scal.p;  // 8 rows of R scalars
+  double *S = (double *)scal.p;  // 8 rows of R scalars, then the MGS abort word
+  unsigned *mgs_abortf = reinterpret_cast<unsigned *>(S + 8 * R);
+  BSPAI_HIP(hipMemsetAsync(mgs_abortf, 0, sizeof(double), s));
   double *H = (double *)Hb.p, *CS = (double *)csb.p, *SN = (double *)snb.p, *G = (double *)gb.p, *Y = (double *)yb.p;
   int *KC = (int *)kcb.p, *ACT = (int *)actb.p;
   if (nnz > 0 && !Ab) {
@@ -727,10 +733,11 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
           // the whole step's MGS in one cooperative launch (h_{i,j} to H, the
           // norms to S row 5, v_{j+1} written)
           if (prof) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot], s));
-          if ((rc = launch_mgs_persist<VT>(n, j, m, Z, V, nr, H, S + 5 * R, GMA, mgsws.p, s))) return rc;
+          if ((rc = launch_mgs_persist<VT>(n, j, m, Z, V, nr, H, S + 5 * R, GMA, mgsws.p, mgs_rounds, mgs_abortf,
+                                           s)))
+            return rc;
+          mgs_rounds += (unsigned)(j + 2);
           if (prof) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot + 1], s));
-          BSPAI_HIP(hipMemcpyAsync(ring.abort(slot), static_cast<char *>(mgsws.p) + mgs_persist_abort_offset(), 4,
-                                   hipMemcpyDeviceToHost, s));
         }
         // MGS: pass i removes v_{i-1}, measures v_i; h_{i,j} lands in H column j
         for (int i = 0; !mgs1 && i <= j + 1; i++) {
@@ -759,8 +766,8 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
         hipLaunchKernelGGL(k_b_givens, dim3(R), dim3(64), (size_t)(3 * m + 1) * sizeof(double), s, R, m, j, H, CS,
                            SN, G, GMA, S + 6 * R, mgs1 ? S + 5 * R : nullptr, S + 4 * R, tol->tau);
         BSPAI_CHECK_LAUNCH();
-        // row 0: h_{j+1,j}, row 1: |g_{j+1}|
-        BSPAI_HIP(hipMemcpyAsync(ring.hq(slot), S + 5 * R, 2 * 8 * (size_t)R, hipMemcpyDeviceToHost, s));
+        // S rows 5 (h_{j+1,j}), 6 (|g_{j+1}|) and 7, then the MGS abort word
+        BSPAI_HIP(hipMemcpyAsync(ring.hq(slot), S + 5 * R, 8 * (3 * (size_t)R + 1), hipMemcpyDeviceToHost, s));
         BSPAI_HIP(hipEventRecord(ring.done[slot], s));
       }
       const int slot = jd % lag;
