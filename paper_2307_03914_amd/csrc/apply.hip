@@ -1,6 +1,7 @@
 // Public bucketed products: bspai_apply (M_b X) and bspai_apply_T (M_b^T X).
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "common.h"
 #include "spmv_dev.h"
@@ -846,6 +847,148 @@ __global__ void __launch_bounds__(kApplyThreads) k_bspmm4_ell(BMat M, const XT *
   }
 }
 
+// One stored bucket in ELL form (the common case of a stencil operator):
+// k_bspmm4_ell with the value format fixed at compile time, so the kernel
+// keeps few registers and many waves in flight; codes and values are read
+// once, with non-temporal loads.  Same order of operations.
+template <int U, int FMT, typename PT>
+__device__ __forceinline__ void ell1_vals(const void *val, int64_t e, PT (&v)[U]) {
+  if constexpr (FMT == BSPAI_FP64) {
+#pragma unroll
+    for (int t = 0; t < U; t += 2) {
+      const f64x2 a = ld_stream<true, f64x2>(static_cast<const double *>(val) + e + t);
+      v[t] = (PT)a.x, v[t + 1] = (PT)a.y;
+    }
+  } else if constexpr (FMT == BSPAI_FP32) {
+#pragma unroll
+    for (int t = 0; t < U; t += 4) {
+      const f32x4 a = ld_stream<true, f32x4>(static_cast<const float *>(val) + e + t);
+      v[t] = a.x, v[t + 1] = a.y, v[t + 2] = a.z, v[t + 3] = a.w;
+    }
+  } else if constexpr (FMT == BSPAI_FP16 || FMT == BSPAI_BF16) {
+    uint32_t w[U / 2];
+    if constexpr (U == 8) {
+      const u32x4 a = ld_stream<true, u32x4>(static_cast<const uint16_t *>(val) + e);
+      w[0] = a.x, w[1] = a.y, w[2] = a.z, w[3] = a.w;
+    } else {
+      const u32x2 a = ld_stream<true, u32x2>(static_cast<const uint16_t *>(val) + e);
+      w[0] = a.x, w[1] = a.y;
+    }
+#pragma unroll
+    for (int t = 0; t < U; t++) {
+      const uint16_t h = (uint16_t)((w[t >> 1] >> (16 * (t & 1))) & 0xFFFFu);
+      v[t] = (PT)(FMT == BSPAI_FP16 ? decode_f16(h) : decode_bf16(h));
+    }
+  } else {
+    uint32_t w[2] = {0u, 0u};
+    if constexpr (U == 8) {
+      const u32x2 a = ld_stream<true, u32x2>(static_cast<const uint8_t *>(val) + e);
+      w[0] = a.x, w[1] = a.y;
+    } else {
+      w[0] = ld_stream<true, uint32_t>(static_cast<const uint8_t *>(val) + e);
+    }
+#pragma unroll
+    for (int t = 0; t < U; t++) v[t] = (PT)decode_e4m3((uint8_t)((w[t >> 2] >> (8 * (t & 3))) & 0xFFu));
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void ell1_cols(const BMat &M, int cw, int64_t e, int row, const int32_t *dict,
+                                          int (&c)[U]) {
+  if (cw == 1) {
+    uint32_t q[2] = {0u, 0u};
+    if constexpr (U == 8) {
+      const u32x2 a = ld_stream<true, u32x2>(static_cast<const uint8_t *>(M.ell_code[0]) + e);
+      q[0] = a.x, q[1] = a.y;
+    } else {
+      q[0] = ld_stream<true, uint32_t>(static_cast<const uint8_t *>(M.ell_code[0]) + e);
+    }
+#pragma unroll
+    for (int t = 0; t < U; t++) c[t] = row + dict[(q[t >> 2] >> (8 * (t & 3))) & 0xFFu];
+  } else if (cw == 2) {
+    uint32_t q[4] = {0u, 0u, 0u, 0u};
+    if constexpr (U == 8) {
+      const u32x4 a = ld_stream<true, u32x4>(static_cast<const int16_t *>(M.ell_code[0]) + e);
+      q[0] = a.x, q[1] = a.y, q[2] = a.z, q[3] = a.w;
+    } else {
+      const u32x2 a = ld_stream<true, u32x2>(static_cast<const int16_t *>(M.ell_code[0]) + e);
+      q[0] = a.x, q[1] = a.y;
+    }
+#pragma unroll
+    for (int t = 0; t < U; t++) c[t] = row + (int32_t)(int16_t)((q[t >> 1] >> (16 * (t & 1))) & 0xFFFFu);
+  } else {
+#pragma unroll
+    for (int t = 0; t < U; t += 4) {
+      const i32x4 a = ld_stream<true, i32x4>(M.ell_col[0] + e + t);
+      c[t] = a.x, c[t + 1] = a.y, c[t + 2] = a.z, c[t + 3] = a.w;
+    }
+  }
+}
+
+template <int U, int FMT, typename XT, typename PT>
+__device__ __forceinline__ void bspmm4_ell1_chunk(const BMat &M, int cw, int64_t e, int row, const int32_t *dict,
+                                                  const XT *__restrict__ x, int64_t ld, int c0, PT (&acc)[4]) {
+  int cc[U];
+  PT vv[U];
+  ell1_cols<U>(M, cw, e, row, dict, cc);
+  ell1_vals<U, FMT, PT>(M.ell_val[0], e, vv);
+  double xv[U][4];
+#pragma unroll
+  for (int t = 0; t < U; t++) ld4<XT>(x + (int64_t)cc[t] * ld + c0, xv[t]);
+#pragma unroll
+  for (int t = 0; t < U; t++)
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      if constexpr (sizeof(PT) == 8)
+        acc[u] = fma(vv[t], xv[t][u], acc[u]);
+      else
+        acc[u] = fmaf(vv[t], (float)xv[t][u], acc[u]);
+    }
+}
+
+template <typename XT, int FMT>
+__global__ void __launch_bounds__(kApplyThreads) k_bspmm4_ell1(BMat M, const XT *__restrict__ x, XT *__restrict__ y,
+                                                               int64_t ld, int nrhs) {
+  using PT = typename std::conditional<FMT == BSPAI_FP64 || sizeof(XT) == 8, double, float>::type;
+  __shared__ int32_t sdict[256];
+  const int cw = M.ell_cw[0], ew = M.ell_w[0];
+  if (cw == 1) {
+    sdict[threadIdx.x] = M.ell_dict[0][threadIdx.x];  // kApplyThreads == 256
+    __syncthreads();
+  }
+  const int tpr = nrhs / 4, rpb = kApplyThreads / tpr;
+  const int g = threadIdx.x / tpr, c0 = 4 * (threadIdx.x % tpr);
+  const int i = xcd_block(blockIdx.x, gridDim.x) * rpb + g;
+  if (g >= rpb || i >= M.n) return;
+  PT acc[4] = {(PT)0, (PT)0, (PT)0, (PT)0};
+  const int64_t e0 = (int64_t)i * ew;
+  if (ew == 4)
+    bspmm4_ell1_chunk<4, FMT, XT, PT>(M, cw, e0, i, sdict, x, ld, c0, acc);
+  else
+    for (int q = 0; q < ew; q += 8) bspmm4_ell1_chunk<8, FMT, XT, PT>(M, cw, e0 + q, i, sdict, x, ld, c0, acc);
+  double total[4];
+#pragma unroll
+  for (int u = 0; u < 4; u++) total[u] = (double)acc[u] * M.scale[0];
+  XT *yp = y + (int64_t)i * ld + c0;
+  if (sizeof(XT) == 4) {
+    *reinterpret_cast<float4 *>(yp) = make_float4((float)total[0], (float)total[1], (float)total[2], (float)total[3]);
+  } else {
+    reinterpret_cast<double2 *>(yp)[0] = make_double2(total[0], total[1]);
+    reinterpret_cast<double2 *>(yp)[1] = make_double2(total[2], total[3]);
+  }
+}
+
+template <typename XT>
+static void *bspmm4_ell1_kernel(int fmt) {
+  switch (fmt) {
+    case BSPAI_FP64: return (void *)k_bspmm4_ell1<XT, BSPAI_FP64>;
+    case BSPAI_FP32: return (void *)k_bspmm4_ell1<XT, BSPAI_FP32>;
+    case BSPAI_FP16: return (void *)k_bspmm4_ell1<XT, BSPAI_FP16>;
+    case BSPAI_BF16: return (void *)k_bspmm4_ell1<XT, BSPAI_BF16>;
+    default: return (void *)k_bspmm4_ell1<XT, BSPAI_FP8_E4M3>;
+  }
+}
+
 int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, int fp64, hipStream_t s) {
   if (M.n == 0) return BSPAI_OK;
   if (nrhs == 1) {
@@ -860,7 +1003,13 @@ int launch_bspmv(const BMat &M, const void *x, void *y, int nrhs, int64_t ld, in
     const int rpb = kApplyThreads / (nrhs / 4);
     const int64_t nblk = (M.n + rpb - 1) / rpb;
     const bool ell = all_ell(M);
-    if (fp64)
+    if (ell && M.nb == 1) {  // one ELL bucket: the format-specialised kernel
+      BMat Mc = M;
+      int nr = nrhs;
+      void *args[] = {&Mc, const_cast<void **>(&x), &y, &ld, &nr};
+      void *fn = fp64 ? bspmm4_ell1_kernel<double>(M.prec[0]) : bspmm4_ell1_kernel<float>(M.prec[0]);
+      BSPAI_HIP(hipLaunchKernel(fn, dim3((unsigned)nblk), dim3(kApplyThreads), args, 0, s));
+    } else if (fp64)
       hipLaunchKernelGGL(ell ? k_bspmm4_ell<double> : k_bspmm4<double>, dim3((unsigned)nblk), dim3(kApplyThreads),
                          0, s, M, static_cast<const double *>(x), static_cast<double *>(y), ld, nrhs);
     else
