@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--only-convdiff", action="store_true", help="run only the 256^2 convection-diffusion block")
     ap.add_argument("--only-multi", action="store_true", help="run only the 32-system measurement")
     ap.add_argument("--only-powerlaw", action="store_true", help="run only the power-law matrix measurement")
+    ap.add_argument("--only-powerlaw-apply", action="store_true",
+                    help="run only the power-law matrix's build and apply timings (no solves)")
     ap.add_argument("--only-gradient", action="store_true", help="run only the 512^2 gradient measurement")
     ap.add_argument("--only-adaptive", action="store_true", help="run only the adaptive-SPAI measurement")
     ap.add_argument("--only-bucketed-a", action="store_true", help="run only the bucketed-A measurement")
@@ -172,6 +174,9 @@ def main():
         return
     if args.only_powerlaw:
         _emit(B, torch, {"powerlaw": powerlaw_bench(B, W, torch, np, kw0)})
+        return
+    if args.only_powerlaw_apply:
+        _emit(B, torch, {"powerlaw": powerlaw_bench(B, W, torch, np, kw0, reps=20, apply_only=True)})
         return
     if args.only_gradient:
         _emit(B, torch, {"gradient": gradient_bench(B, W, torch, np)})
@@ -472,7 +477,7 @@ def _bucket_damage(P, ex, q):
     return flushed, zero_diag
 
 
-def powerlaw_bench(B, W, torch, np, kw, reps=50):
+def powerlaw_bench(B, W, torch, np, kw, reps=50, apply_only=False):
     """The 2^20-row random matrix with power-law rows (mean 13, up to 401,
     lognormal(4) values): SPAI build (rows past the wavefront path go to the
     block path), the bucketed apply with the tuned kernel, and the solve.
@@ -523,6 +528,14 @@ def powerlaw_bench(B, W, torch, np, kw, reps=50):
     nb = sum(1 for cc, p in zip(st["count"], st["precs"]) if cc > 0 and p != 5)
     alg = sum(cc * (VALUE_BYTES[p] + 4) for cc, p in zip(st["count"], st["precs"]) if p != 5)
     alg += 4 * (n + 1) * nb + 8 * n
+    if apply_only:
+        h.free()
+        return {"workload": "random n=%d, power-law rows, SPAI pattern(A), buckets eps=1e-3" % n,
+                "bucket_counts": st["count"], "apply_kind": st["apply_kind"], "apply_us": ms * 1e3,
+                "apply_us_by_kernel": by_kind, "apply_algorithmic_bytes": alg,
+                "apply_GBs": alg / (ms * 1e-3) / 1e9,
+                "traffic_bytes_per_launch": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "apply.hip"),
+                                                     "powerlaw_apply_traffic.json")}
     ex = h.export()
     h.free()
     del x, y
@@ -561,6 +574,8 @@ def powerlaw_bench(B, W, torch, np, kw, reps=50):
            "build_s": build_s, "bucket_counts": st["count"], "storage_pct": st["storage_pct"],
            "apply_kind": st["apply_kind"], "apply_us": ms * 1e3, "apply_us_by_kernel": by_kind,
            "apply_algorithmic_bytes": alg,
+           "apply_traffic_bytes_per_launch": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "apply.hip"),
+                                                      "powerlaw_apply_traffic.json"),
            "apply_GBs": alg / (ms * 1e-3) / 1e9, "apply_frac_of_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
            "solve_at_eps_1e-3": {k: head[k] for k in ("its", "eta", "relres", "status", "stop_reason", "converged",
                                                       "solves_per_s")},
