@@ -475,6 +475,32 @@ def test_apply_multi_rhs_matches_columns(B, nrhs):
     h.free()
 
 
+@pytest.mark.parametrize("nrhs", [4, 8])
+def test_apply_multi_rhs_single_ell_bucket(B, nrhs):
+    """Many right-hand sides through the format-specialised one-bucket ELL
+    kernel (every entry bf16, byte column codes: the batched solve's M and
+    A products), both orientations, each column against the oracle."""
+    import torch
+
+    c = W.config("4a", small=True)
+    A, P = c["A"], c["P"]
+    _say("spmm one ELL bucket", A.n, nrhs)
+    M = _spai_oracle(A, P)
+    Mb = O.Bucketed(M, 1e-2, c["precs"])
+    h = B.import_m(B.CSRMatrix.from_host(M), 1e-2, c["precs"])
+    st = h.stats()
+    stored = [k for k in range(st["q"]) if st["count"][k] > 0]
+    assert len(stored) == 1 and st["ell_width"][stored[0]] > 0 and st["col_bytes"][stored[0]] == 1, st
+    X = np.random.default_rng(19).standard_normal((M.n, nrhs)).astype(np.float32).astype(np.float64)
+    for t in (False, True):
+        Y = (B.apply_T if t else B.apply)(h, _dev(X, torch.float32)).double().cpu().numpy()
+        for j in range(nrhs):
+            ref = (O.apply_T if t else O.apply)(Mb, X[:, j])
+            bound = _apply_bound(Mb, X[:, j], U32, transpose=t) + U32 * np.abs(ref)
+            assert np.all(np.abs(Y[:, j] - ref) <= bound + 1e-300), (t, j)
+    h.free()
+
+
 def test_apply_full_size_sampled_rows(B):
     """Config 4a's operator at full size (n = 2,097,152, all entries bf16 at
     eps = 1e-2): the HIP product checked on 2000 sampled rows against the
