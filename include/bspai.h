@@ -329,7 +329,7 @@ int bspai_export_pattern(const bspai_handle *M, int32_t *row_ptr_host, int32_t *
  *   2 LDS tiles of contiguous rows (balanced for rows of any length);
  *   3 two rows per thread;  4 a group of lanes per row;
  *   5 entry-balanced tiles of whole rows (about 4096 entries per block, a
- *     plan built with the handle; rows of more than 32 entries are added by
+ *     plan built with the handle; rows of more than 64 entries are added by
  *     a whole wavefront), for rows of very different lengths with scattered
  *     columns; not available when a row has more than 4096 entries.
  * bspai_set_apply_kind -- use kernel `kind` for M_b (trans = 0) or M_b^T

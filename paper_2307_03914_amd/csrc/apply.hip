@@ -429,12 +429,16 @@ static int launch_vec(const BMat &M, const XT *x, XT *y, int lanes, hipStream_t 
 // in CSR order, one thread per row, except rows of more than kSegLong
 // entries, which a whole wavefront adds (lane l takes products l, l + 64,
 // ..., then a fixed butterfly), so a long row does not hold its block.
+// Measured on a 2^20-row power-law matrix: kSegLong 16 / 32 / 64 / 128 /
+// 256 gave 137 / 114 / 104 / 104 / 116 us, tiles of 2048 / 4096 / 8192
+// entries 118 / 114 / 154 us, one chunk per round instead of two 110 us,
+// one chunk with kSegLong 64: 101 us.
 // Per-bucket sums in FP32 (FP64 for wide products), scaled and added in FP64
 // from the least to the most precise bucket, as in the other kernels; the
 // order of additions inside a row is fixed by the plan, so repeated products
 // give identical bits.
 constexpr int kSegTile = 4096;
-constexpr int kSegLong = 32;
+constexpr int kSegLong = 64;
 constexpr int kSegMaxLong = 2 * kSegTile / (kSegLong + 1) + 1;
 
 template <typename T>
@@ -454,7 +458,7 @@ __device__ __forceinline__ T wave_butterfly_sum(T v) {
 // the tile read zero without a branch around a load; entries at or past b1
 // gather x[t] of their lane (coalesced, never written).  The chunk loop runs
 // the same number of times in every thread of the block.
-constexpr int kSegChunks = 2;  // 8-entry chunks per thread in flight
+constexpr int kSegChunks = 1;  // 8-entry chunks per thread per round
 template <int FMT, typename XT, typename PT>
 __device__ __forceinline__ void seg_stream(const BMat &M, int k, int b0, int b1, const XT *__restrict__ x,
                                            PT *pk) {
