@@ -1614,4 +1614,37 @@ def test_build_powerlaw_full_size_sampled_rows(B):
     # power-law rows would pad 64-row slices many times over: no padded
     # copies, the products default to LDS tiles
     assert st["apply_kind"] == [2, 2], st["apply_kind"]
+    # the entry-balanced tile product at full size (3,300 tiles, the longest
+    # rows on the wavefront path): sampled rows of M_b x and M_b^T x against
+    # the stored values, and the whole vector against the LDS tiles' result
+    import torch
+
+    ex = h.export()
+    stored = ex["stored"]
+    x = np.random.default_rng(8).standard_normal(A.n).astype(np.float32)
+    xd = torch.as_tensor(x, device="cuda")
+    xs = x.astype(np.float64)
+    ys = {}
+    for kind in (2, 5):
+        h.set_apply_kind(kind)
+        h.set_apply_kind(kind, trans=True)
+        ys[kind] = (B.apply(h, xd).double().cpu().numpy(), B.apply_T(h, xd).double().cpu().numpy())
+    y5, y5t = ys[5]
+    for i in rows:
+        s = slice(P.row_ptr[i], P.row_ptr[i + 1])
+        ref = float(np.dot(stored[s], xs[P.col[s]]))
+        tol = (lens[i] + 2) * U32 * float(np.abs(stored[s]) @ np.abs(xs[P.col[s]]))
+        assert abs(y5[i] - ref) <= tol + U32 * abs(ref), (i, lens[i])
+    # transposed: column j of M_b is the entries with col == j
+    cols = rows[:20]
+    sel = np.isin(P.col, cols)
+    rix = np.repeat(np.arange(A.n), lens)[sel]
+    for j in cols:
+        e = np.flatnonzero(sel)[P.col[sel] == j]
+        ref = float(np.dot(stored[e], xs[rix[P.col[sel] == j]]))
+        tol = (len(e) + 2) * U32 * float(np.abs(stored[e]) @ np.abs(xs[rix[P.col[sel] == j]]))
+        assert abs(y5t[j] - ref) <= tol + U32 * abs(ref), j
+    for a5, a2 in zip(ys[5], ys[2]):
+        scale = np.abs(a2).max()
+        assert np.abs(a5 - a2).max() <= 1e-4 * scale
     h.free()
