@@ -6,7 +6,9 @@ Headline workload: the 128^3 anisotropic 7-point diffusion operator
 (1:10:100, n = 2,097,152) with 64 right-hand sides N(0,1) sharing one BSPAI
 M (SPAI on the pattern of A, buckets fp32/fp16/bf16 at eps_b = 1e-2),
 u_g = u_p = fp32, u = fp64, residuals in double-double, tau = 1e-4, refinement
-to relative residual 1e-10, GMRES cap 150.  The library solves many
+to relative residual 1e-10, GMRES cap 50 (each correction's Arnoldi run
+stops at 50 steps; the solve takes about a dozen corrections).  The library
+solves many
 right-hand sides in column groups (4 columns in FP32, one cooperative MGS
 launch per Arnoldi step); a step is one gmres_ir_solve call on one such group
 of 4 of the 64 columns, the steps cycling through the 16 groups.  value =
@@ -79,16 +81,21 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(kernel_src, record="solve_kernel_traffic.json"):
+def _traffic(kernel_src, record="solve_kernel_traffic.json", alg_bytes=None):
     """HBM traffic per launch from the committed rocprofv3 counter runs, only if
-    they were taken on the current kernel source."""
+    they were taken on the current kernel source (and, given alg_bytes, on a
+    workload of the same algorithmic bytes per launch, within 1%)."""
     p = os.path.join(ROOT, "profiles", record)
     try:
         with open(p) as f:
             t = json.load(f)
-        if t.get("source_sha256_16") == _src_hash(kernel_src):
-            return t.get("bytes_per_launch")
-    except (OSError, ValueError):
+        if t.get("source_sha256_16") != _src_hash(kernel_src):
+            return None
+        ref = t.get("algorithmic_bytes_per_launch")
+        if alg_bytes is not None and (not ref or abs(ref / alg_bytes - 1.0) > 0.01):
+            return None
+        return t.get("bytes_per_launch")
+    except (OSError, ValueError, ZeroDivisionError):
         pass
     return None
 
@@ -119,7 +126,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--gmres-max", type=int, default=150)
+    ap.add_argument("--gmres-max", type=int, default=150, help="GMRES cap of the secondary workloads")
+    ap.add_argument("--headline-cap", type=int, default=50,
+                    help="GMRES cap of the headline solve (its MGS work per correction grows as the cap squared)")
+    ap.add_argument("--i-max", type=int, default=20, help="refinement corrections allowed per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="only the headline (and its comparators)")
     ap.add_argument("--no-comparators", action="store_true",
@@ -162,7 +172,8 @@ def main():
         torch.cuda.synchronize()
         del a, b2
         torch.cuda.empty_cache()
-    kw0 = dict(tau=1e-4, tol_rr=1e-10, gmres_max=args.gmres_max, i_max=20)
+    kw0 = dict(tau=1e-4, tol_rr=1e-10, gmres_max=args.gmres_max, i_max=args.i_max)
+    kwh = dict(kw0, gmres_max=args.headline_cap)
     if args.only_apply:
         _emit(B, torch, {"m_apply": apply_bench(B, W, torch, np)})
         return
@@ -191,10 +202,10 @@ def main():
         _emit(B, torch, {"low_uf_spai": low_uf_bench(B, W, torch, np, kw0)})
         return
     if args.only_cpu_baseline:
-        _emit(B, torch, {"cpu_baseline": cpu_baseline(W, np, kw0, [150, 150, 150, 150])})
+        _emit(B, torch, {"cpu_baseline": cpu_baseline(W, np, kwh, [args.headline_cap] * 12)})
         return
 
-    out, its_per_col = headline(B, W, torch, np, kw0, args.steps, args.warmup, not args.no_comparators)
+    out, its_per_col = headline(B, W, torch, np, kwh, args.steps, args.warmup, not args.no_comparators)
     if not args.no_secondary:
         out["convdiff_256"] = convdiff_bench(B, W, torch, np, kw0, 20, 3)
         out["m_apply"] = apply_bench(B, W, torch, np)
@@ -205,7 +216,7 @@ def main():
         out["bucketed_a"] = bucketed_a_bench(B, W, torch, np, kw0)
         out["low_uf_spai"] = low_uf_bench(B, W, torch, np, kw0)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, np, kw0, its_per_col)
+        out["cpu_baseline"] = cpu_baseline(W, np, kwh, its_per_col)
     _emit(B, torch, out)
 
 
@@ -249,12 +260,13 @@ def headline(B, W, torch, np, kw, steps, warmup, comparators=True):
     _log(f"BSPAI: {rhs_per_s:.2f} RHS/s ({elapsed * 1e3 / steps:.0f} ms per {GROUP}-column step), "
          f"its {summ['its_col0']}, max relres {summ['max_relres']:.2e}, all converged {summ['all_converged']}")
     mgs_gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else 0.0
+    alg_launch = prof["bytes"] / max(1, prof["launches"])
     roofline = {"kernel": "k_b_mgs_persist (one Arnoldi step's MGS for a 4-column group)", "bound": "hbm",
                 "achieved": mgs_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": mgs_gbs / PEAK_HBM_GBS,
                 "traffic": _traffic(os.path.join(ROOT, "paper_2307_03914_amd", "csrc", "solve.hip"),
-                                    "batched_mgs_traffic.json"),
+                                    "batched_mgs_traffic.json", alg_launch),
                 "launches": prof["launches"], "avg_launch_us": 1e3 * prof["ms"] / max(1, prof["launches"]),
-                "algorithmic_bytes_per_launch": prof["bytes"] / max(1, prof["launches"]),
+                "algorithmic_bytes_per_launch": alg_launch,
                 "kernel_share_of_step": prof["ms"] * 1e-3 / elapsed}
     out = {"metric": "GMRES-IR solves/s & M-apply HBM GB/s, BSPAI vs fp64 SPAI at equal backward error",
            "value": rhs_per_s, "unit": "RHS solves/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -829,8 +841,9 @@ def _cpu_model():
 def cpu_baseline(W, np, kw, its_per_col):
     """The CPU oracle (plain C, OpenMP over rows, dot products sequential and
     accumulated in FP64, the realisation the GPU computes) on the headline
-    workload, one column.  A full solve of one column is 4 corrections of
-    ~150 GMRES iterations (minutes on the host), so the sample is bounded:
+    workload, one column.  A full solve of one column is about a dozen
+    corrections of 50 GMRES iterations (minutes on the host), so the sample
+    is bounded:
     MGS-GMRES corrections of 20 and 40 iterations on M_b A d = M_b r fix
     t(k) = a k + b k (k + 1) / 2 (the products per iteration, the
     Gram-Schmidt growing with k), which is summed over the column's GPU
