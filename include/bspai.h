@@ -392,12 +392,15 @@ int bspai_grad_vals(const bspai_pattern *A, const double *lam, const double *x, 
 void bspai_set_profiling(int on);
 double bspai_last_solve_kernel_ms(void);
 /* bspai_batched_mgs_profile -- with profiling on, gmres_ir_solve with several
- * right-hand sides times each launch of its one-launch MGS kernel (see
- * bspai_set_batch_mode) with HIP events on its stream; this returns the
- * totals since the last reset: milliseconds, launches and algorithmic bytes
+ * right-hand sides times one launch in seven of its one-launch MGS kernel (see
+ * bspai_set_batch_mode; the count runs across solves) with HIP events on its
+ * stream; this returns the totals of the timed launches since the last reset:
+ * milliseconds, launches and algorithmic bytes
  * ((j + 2) n c values of u_g for step j of a c-column group: v_0..v_j read,
- * v_{j+1} written).  Any pointer may be NULL; reset clears them. */
-void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes);
+ * v_{j+1} written), and every launch made while profiling was on, timed or
+ * not.  Any pointer may be NULL; reset clears them. */
+void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes,
+                               long long *all_launches);
 
 /*
  * bspai_set_batch_mode -- how gmres_ir_solve runs nrhs > 1 columns.

@@ -171,18 +171,19 @@ def last_solve_kernel_ms() -> float:
 
 
 _lib.bspai_batched_mgs_profile.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
-                                           C.POINTER(C.c_double)]
+                                           C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
 _lib.bspai_batched_mgs_profile.restype = None
 _lib.bspai_set_batch_mode.argtypes = [C.c_int]
 _lib.bspai_set_batch_mode.restype = C.c_int
 
 
 def batched_mgs_profile(reset: bool = False) -> Dict:
-    """Totals of the one-launch MGS kernel timed while profiling is on
-    (bspai_batched_mgs_profile): ms, launches, algorithmic bytes."""
-    ms, n, by = C.c_double(0), C.c_longlong(0), C.c_double(0)
-    _lib.bspai_batched_mgs_profile(int(reset), C.byref(ms), C.byref(n), C.byref(by))
-    return dict(ms=ms.value, launches=n.value, bytes=by.value)
+    """Totals of the one-launch MGS kernel while profiling is on
+    (bspai_batched_mgs_profile): ms, launches and algorithmic bytes of the
+    timed launches (one in seven), and all_launches."""
+    ms, n, by, al = C.c_double(0), C.c_longlong(0), C.c_double(0), C.c_longlong(0)
+    _lib.bspai_batched_mgs_profile(int(reset), C.byref(ms), C.byref(n), C.byref(by), C.byref(al))
+    return dict(ms=ms.value, launches=n.value, bytes=by.value, all_launches=al.value)
 
 
 BATCH_AUTO, BATCH_ALL_COLUMNS, BATCH_GROUPS = 0, 1, 2

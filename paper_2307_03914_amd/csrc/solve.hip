@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -2000,10 +2001,23 @@ extern "C" void bspai_set_profiling(int on) { g_profile = on ? 1 : 0; }
 
 static std::mutex g_mgs_mu;
 static double g_mgs_ms = 0.0, g_mgs_bytes = 0.0;
-static long long g_mgs_launches = 0;
+static long long g_mgs_launches = 0, g_mgs_all = 0;
 static int g_batch_mode = 0;
 namespace bspai {
 bool profiling_on() { return g_profile != 0; }
+// One launch in kMgsProfEvery is timed: the two events around a launch delay
+// the next dispatch by several microseconds each.  The counter runs across
+// launches and solves, so with correction lengths prime to 7 the sample
+// covers every step index j evenly.
+constexpr unsigned kMgsProfEvery = 7;
+static std::atomic<unsigned> g_mgs_seq{0};
+bool mgs_profile_sample() {
+  {
+    std::lock_guard<std::mutex> lock(g_mgs_mu);
+    g_mgs_all++;
+  }
+  return g_mgs_seq.fetch_add(1, std::memory_order_relaxed) % kMgsProfEvery == 0;
+}
 void add_mgs_profile(double ms, double bytes) {
   std::lock_guard<std::mutex> lock(g_mgs_mu);
   g_mgs_ms += ms;
@@ -2013,14 +2027,16 @@ void add_mgs_profile(double ms, double bytes) {
 int batch_mode() { return g_batch_mode; }
 }  // namespace bspai
 
-extern "C" void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes) {
+extern "C" void bspai_batched_mgs_profile(int reset, double *ms_total, long long *launches, double *bytes,
+                                          long long *all_launches) {
   std::lock_guard<std::mutex> lock(g_mgs_mu);
   if (ms_total) *ms_total = g_mgs_ms;
   if (launches) *launches = g_mgs_launches;
   if (bytes) *bytes = g_mgs_bytes;
+  if (all_launches) *all_launches = g_mgs_all;
   if (reset) {
     g_mgs_ms = g_mgs_bytes = 0.0;
-    g_mgs_launches = 0;
+    g_mgs_launches = g_mgs_all = 0;
   }
 }
 

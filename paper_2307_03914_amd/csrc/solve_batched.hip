@@ -313,16 +313,29 @@ __global__ void k_b_scale4(int R, int64_t nr, const VT *z, const double *h, VT *
 // hn non-null: the column's GMRES stops here (gm_active[c] = 0) when
 // |g_{j+1}| <= tau beta[c], h_{j+1,j} = hn[c] = 0 or j + 1 = m, the test the
 // host repeats on the same values, so that steps queued ahead see it.
+// The host's copy of the step (pinned host memory hq, read once a later
+// event has completed): hq[c] = hrow[c] (h_{j+1,j}), hq[R + c] = |g_{j+1}|
+// and, from block 0, the MGS abort word *abortf at hq + 3 R (an unsigned).
 __global__ void __launch_bounds__(64) k_b_givens(int R, int m, int j, double *H, double *cs, double *sn, double *g,
                                                  int *gm_active, double *res, const double *hn, const double *beta,
-                                                 double tau) {
+                                                 double tau, const double *hrow, const unsigned *abortf,
+                                                 double *hq) {
   extern __shared__ double gsh[];
   const int c = blockIdx.x;
   if (c >= R) return;
   double *h = H + ((int64_t)c * m + j) * (m + 1);
   double *cc = cs + (int64_t)c * m, *ss = sn + (int64_t)c * m, *gg = g + (int64_t)c * (m + 1);
+  auto to_host = [&](double r) {
+    hq[c] = hrow[c];
+    hq[R + c] = r;
+    if (c == 0) *reinterpret_cast<unsigned *>(hq + 3 * R) = *abortf;
+    __threadfence_system();
+  };
   if (!gm_active[c]) {
-    if (threadIdx.x == 0) res[c] = 0.0;
+    if (threadIdx.x == 0) {
+      res[c] = 0.0;
+      to_host(0.0);
+    }
     return;
   }
   double *lh = gsh, *lc = gsh + (m + 1), *ls = lc + m;
@@ -354,6 +367,7 @@ __global__ void __launch_bounds__(64) k_b_givens(int R, int m, int j, double *H,
     const double hres = fabs(-sj * gj);
     res[c] = hres;
     if (hn && (hres <= tau * beta[c] || hn[c] == 0.0 || j + 1 == m)) gm_active[c] = 0;
+    to_host(hres);
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j + 1; i += 64) h[i] = lh[i];
@@ -366,8 +380,12 @@ __global__ void __launch_bounds__(64) k_b_givens(int R, int m, int j, double *H,
 // the entries of row i - 1 are loaded while lane 0 works on row i.
 constexpr int kBacksubMaxM = 192;
 // Arnoldi steps of the column-group path queued ahead of the host's
-// stopping decisions
-constexpr int kStepLag = 4;
+// stopping decisions, and the steps per completion event the host waits on
+// (each event recorded on the stream delays the next dispatch by a few
+// microseconds; twice as many steps queued as one event covers keep the
+// stream busy while the host reads them)
+constexpr int kStepLag = 8;
+constexpr int kStepsPerEvent = 4;
 __global__ void __launch_bounds__(64) k_b_backsub(int R, int m, const double *H, const double *g, const int *kc,
                                                   double *y) {
   constexpr int Q = kBacksubMaxM / 64;
@@ -510,20 +528,23 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
     BSPAI_HIP(hipMemsetAsync(mgsws.p, 0, mgs_persist_ws_bytes(), s));
   }
   unsigned mgs_rounds = 0;  // exchange rounds of the MGS launches so far
-  // per queued step: a pinned copy of S rows 5-7 (h_{j+1,j}, |g_{j+1}|) and
-  // the MGS abort word, the step's completion event, and (when profiling)
-  // HIP events around its MGS launch
+  // per queued step: pinned host memory that the step's rotation kernel
+  // fills with h_{j+1,j} and |g_{j+1}| of every column and the MGS abort
+  // word, a completion event (recorded after every kStepsPerEvent-th step),
+  // and (when profiling) HIP events around its MGS launch
   const bool prof = mgs1 && profiling_on();
   struct StepRing {
-    void *pin = nullptr;
+    void *pin = nullptr, *dpin = nullptr;  // host and device addresses
     int R = 0;
     hipStream_t st = nullptr;
     hipEvent_t done[kStepLag] = {};
     hipEvent_t prof[2 * kStepLag] = {};
+    bool timed[kStepLag] = {};  // the slot's MGS launch has events around it
     double *hq(int k) { return static_cast<double *>(pin) + (size_t)k * (3 * R + 1); }
     unsigned *abort(int k) { return reinterpret_cast<unsigned *>(hq(k) + 3 * R); }
+    double *dhq(int k) { return static_cast<double *>(dpin) + (size_t)k * (3 * R + 1); }
     ~StepRing() {
-      if (pin) (void)hipStreamSynchronize(st);  // copies into pin may still be queued on an error return
+      if (pin) (void)hipStreamSynchronize(st);  // kernels writing into pin may still be queued on an error return
       for (auto q : done)
         if (q) (void)hipEventDestroy(q);
       for (auto q : prof)
@@ -533,7 +554,9 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   } ring;
   ring.R = R;
   ring.st = s;
-  BSPAI_HIP(hipHostMalloc(&ring.pin, sizeof(double) * (size_t)kStepLag * (3 * R + 1), hipHostMallocDefault));
+  BSPAI_HIP(hipHostMalloc(&ring.pin, sizeof(double) * (size_t)kStepLag * (3 * R + 1),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+  BSPAI_HIP(hipHostGetDevicePointer(&ring.dpin, ring.pin, 0));
   for (int k = 0; k < kStepLag; k++) {
     BSPAI_HIP(hipEventCreateWithFlags(&ring.done[k], hipEventDisableTiming));
     if (prof) {
@@ -716,7 +739,7 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
     // column: its MGS launch returns at once and its rotations are skipped),
     // and the host repeats the test on the same values when the step's event
     // completes.  The per-pass path decides on the host after every step.
-    const int lag = mgs1 ? kStepLag : 1;
+    const int lag = mgs1 ? kStepLag : 1, every = mgs1 ? kStepsPerEvent : 1;
     int jq = 0;  // steps queued
     for (int jd = 0; jd < m && nrun > 0; jd++) {
       for (; jq < m && jq < jd + lag; jq++) {
@@ -732,12 +755,13 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
         if (mgs1) {
           // the whole step's MGS in one cooperative launch (h_{i,j} to H, the
           // norms to S row 5, v_{j+1} written)
-          if (prof) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot], s));
+          ring.timed[slot] = prof && mgs_profile_sample();
+          if (ring.timed[slot]) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot], s));
           if ((rc = launch_mgs_persist<VT>(n, j, m, Z, V, nr, H, S + 5 * R, GMA, mgsws.p, mgs_rounds, mgs_abortf,
                                            s)))
             return rc;
           mgs_rounds += (unsigned)(j + 2);
-          if (prof) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot + 1], s));
+          if (ring.timed[slot]) BSPAI_HIP(hipEventRecord(ring.prof[2 * slot + 1], s));
         }
         // MGS: pass i removes v_{i-1}, measures v_i; h_{i,j} lands in H column j
         for (int i = 0; !mgs1 && i <= j + 1; i++) {
@@ -763,18 +787,22 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
           hipLaunchKernelGGL(k_b_scale<VT>, dim3(eg), dim3(256), 0, s, R, nr, Z, S + 5 * R,
                              V + (int64_t)(j + 1) * nr);
         BSPAI_CHECK_LAUNCH();
+        // the rotations; h_{j+1,j}, |g_{j+1}| and the MGS abort word go
+        // straight to the step's pinned slot
         hipLaunchKernelGGL(k_b_givens, dim3(R), dim3(64), (size_t)(3 * m + 1) * sizeof(double), s, R, m, j, H, CS,
-                           SN, G, GMA, S + 6 * R, mgs1 ? S + 5 * R : nullptr, S + 4 * R, tol->tau);
+                           SN, G, GMA, S + 6 * R, mgs1 ? S + 5 * R : nullptr, S + 4 * R, tol->tau, S + 5 * R,
+                           mgs_abortf, ring.dhq(slot));
         BSPAI_CHECK_LAUNCH();
-        // S rows 5 (h_{j+1,j}), 6 (|g_{j+1}|) and 7, then the MGS abort word
-        BSPAI_HIP(hipMemcpyAsync(ring.hq(slot), S + 5 * R, 8 * (3 * (size_t)R + 1), hipMemcpyDeviceToHost, s));
-        BSPAI_HIP(hipEventRecord(ring.done[slot], s));
+        if (j % every == every - 1 || j == m - 1) BSPAI_HIP(hipEventRecord(ring.done[slot], s));
       }
       const int slot = jd % lag;
-      BSPAI_HIP(hipEventSynchronize(ring.done[slot]));
+      // the first event recorded at or after step jd (queued: it is less
+      // than jd + lag)
+      const int je = std::min(m - 1, jd - jd % every + every - 1);
+      BSPAI_HIP(hipEventSynchronize(ring.done[je % lag]));
       if (mgs1 && *ring.abort(slot))
         return fail(BSPAI_EHIP, "gmres_ir_solve: a grid exchange of the MGS kernel timed out");
-      if (prof) {
+      if (prof && ring.timed[slot]) {
         float ms = 0.f;
         BSPAI_HIP(hipEventElapsedTime(&ms, ring.prof[2 * slot], ring.prof[2 * slot + 1]));
         // algorithmic bytes of MGS step j: v_0..v_j read and v_{j+1} written,
