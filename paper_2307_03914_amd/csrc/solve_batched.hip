@@ -233,7 +233,9 @@ struct Vec4<double> {
   }
 };
 
-// the per-column partials of a block of 4-column threads, fixed order
+// the per-column partials (sums, or maxima with MAX) of a block of 4-column
+// threads, fixed order
+template <bool MAX = false>
 __device__ __forceinline__ void block_cols4(int R, int tpr, int rpp, const double (&acc)[4], double *sh, double *part) {
   const int t = threadIdx.x;
 #pragma unroll
@@ -242,7 +244,10 @@ __device__ __forceinline__ void block_cols4(int R, int tpr, int rpp, const doubl
   if (t < R) {
     const int cg = t / 4, u = t % 4;
     double a = sh[4 * cg + u];
-    for (int g = 1; g < rpp; g++) a += sh[4 * (g * tpr + cg) + u];
+    for (int g = 1; g < rpp; g++) {
+      const double v = sh[4 * (g * tpr + cg) + u];
+      a = MAX ? fmax(a, v) : a + v;
+    }
     part[(int64_t)blockIdx.x * R + t] = a;
   }
 }
@@ -462,6 +467,56 @@ __global__ void __launch_bounds__(kBT) k_b_update(Cols cc, int n, int m, const V
   block_cols<true>(cc, mx, sh, part_x);
 }
 
+// k_b_update with four adjacent columns per thread (R % 4 == 0): one 16-byte
+// load of V per basis vector instead of four.  Each column's sum runs over t
+// in the order of k_b_update and the maxima are exact, so the results are
+// the same bits.
+template <typename VT>
+__global__ void __launch_bounds__(kBT) k_b_update4(int R, int n, int m, const VT *V, int64_t vstride,
+                                                   const double *y, const int *kc, double *x, double *dout,
+                                                   double *part_d, double *part_x) {
+  __shared__ double sh[4 * kBT];
+  const int tpr = R / 4, rpp = kBT / tpr;
+  const int g = threadIdx.x / tpr, c0 = 4 * (threadIdx.x % tpr);
+  double md[4] = {0.0, 0.0, 0.0, 0.0}, mx[4] = {0.0, 0.0, 0.0, 0.0};
+  if (g < rpp) {
+    int k[4], kmax = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      k[u] = kc[c0 + u];
+      kmax = max(kmax, k[u]);
+    }
+    const double *yy = y + (int64_t)c0 * m;  // column c0 + u at yy + u m
+    for (int64_t i = (int64_t)blockIdx.x * rpp + g; i < n; i += (int64_t)gridDim.x * rpp) {
+      const int64_t e = i * R + c0;
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t < kmax; t++) {
+        double v[4];
+        Vec4<VT>::load(V + (int64_t)t * vstride + e, v);
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          if (t < k[u]) d[u] = fma(v[u], yy[(int64_t)u * m + t], d[u]);
+      }
+      if (dout) {
+        Vec4<double>::store(dout + e, d);
+      } else {
+        double xv[4];
+        Vec4<double>::load(x + e, xv);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          xv[u] = xv[u] + d[u];
+          md[u] = fmax(md[u], fabs(d[u]));
+          mx[u] = fmax(mx[u], fabs(xv[u]));
+        }
+        Vec4<double>::store(x + e, xv);
+      }
+    }
+  }
+  block_cols4<true>(R, tpr, rpp, md, sh, part_d);
+  __syncthreads();
+  block_cols4<true>(R, tpr, rpp, mx, sh, part_x);
+}
+
 // x += d (d FP64, computed by the transposed apply) with max|d|, max|x|
 __global__ void __launch_bounds__(kBT) k_b_add(Cols cc, int n, const double *d, double *x, double *part_d,
                                                double *part_x) {
@@ -666,7 +721,7 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   std::vector<gmres_ir_stats> st(R);
   for (auto &q : st) memset(&q, 0, sizeof(q));
   std::vector<int> active(R, 1), stag(R, 0), status(R, BSPAI_OK);
-  std::vector<double> dx_prev(R, 0.0), hr, hx, hbeta;
+  std::vector<double> dx_prev(R, 0.0), hr, hbeta;
   int it = 0;
   for (;;) {
     // residuals and stopping tests per column
@@ -674,11 +729,11 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
                        P2);
     BSPAI_CHECK_LAUNCH();
     if ((rc = finish(true, P1, S + 2 * R, 0)) || (rc = finish(true, P2, S + 3 * R, 0))) return rc;
-    if ((rc = to_host(S + 2 * R, hr)) || (rc = to_host(S + 3 * R, hx))) return rc;
+    if ((rc = to_host(S + 2 * R, hr, 2))) return rc;  // rows 2 and 3: ||r||, ||x|| per column
     int nact = 0;
     for (int c = 0; c < R; c++) {
       if (!active[c]) continue;
-      double nr_ = hr[c], nx = hx[c], nb_ = hnb[c];
+      double nr_ = hr[c], nx = hr[R + c], nb_ = hnb[c];
       double eta = nr_ / (normA * nx + nb_);
       double rho = nb_ > 0 ? nr_ / nb_ : nr_;
       if (it <= 64) {
@@ -826,19 +881,22 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
     BSPAI_HIP(hipMemcpyAsync(KC, kc.data(), 4 * (size_t)R, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_b_backsub, dim3(R), dim3(64), (size_t)3 * m * sizeof(double), s, R, m, H, G, KC, Y);
     BSPAI_CHECK_LAUNCH();
-    if (!tr) {
-      hipLaunchKernelGGL(k_b_update<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, m, V, nr, Y, KC, x, nullptr, P1, P2);
-      BSPAI_CHECK_LAUNCH();
-    } else {
-      hipLaunchKernelGGL(k_b_update<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, m, V, nr, Y, KC, x, r64, P1, P2);
-      BSPAI_CHECK_LAUNCH();
+    if (vec4)
+      hipLaunchKernelGGL(k_b_update4<VT>, dim3(nblk), dim3(kBT), 0, s, R, n, m, V, nr, Y, KC, x, tr ? r64 : nullptr,
+                         P1, P2);
+    else
+      hipLaunchKernelGGL(k_b_update<VT>, dim3(nblk), dim3(kBT), 0, s, cc, n, m, V, nr, Y, KC, x, tr ? r64 : nullptr,
+                         P1, P2);
+    BSPAI_CHECK_LAUNCH();
+    if (tr) {
       if ((rc = launch_bspmv(Mb, r64, D, R, R, 1, s))) return rc;  // d = M_b^T (V y) in FP64
       hipLaunchKernelGGL(k_b_add, dim3(nblk), dim3(kBT), 0, s, cc, n, D, x, P1, P2);
       BSPAI_CHECK_LAUNCH();
     }
     if ((rc = finish(true, P1, S + 6 * R, 0)) || (rc = finish(true, P2, S + 7 * R, 0))) return rc;
-    std::vector<double> hdn, hxn;
-    if ((rc = to_host(S + 6 * R, hdn)) || (rc = to_host(S + 7 * R, hxn))) return rc;
+    std::vector<double> hdx;
+    if ((rc = to_host(S + 6 * R, hdx, 2))) return rc;  // rows 6 and 7: max|d|, max|x|
+    const double *hdn = hdx.data(), *hxn = hdx.data() + R;
     for (int c = 0; c < R; c++) {
       if (!active[c]) continue;
       if (it < 64) st[c].its[it] = kc[c];
