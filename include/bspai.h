@@ -439,11 +439,12 @@ int bspai_exchange_latency(int G, int iters, double *us_out, void *stream);
 int bspai_exchange_latency_placed(int G, int iters, int one_xcd, double *us_out, int *xcd_out, void *stream);
 int bspai_solve_blocks(int n);
 
-/* bspai_release_workspace -- free the single-system solver's grow-only
- * device workspace (the Krylov basis and vectors that gmres_ir_solve with
- * nrhs = 1 keeps between calls); the next solve allocates it again.  Waits
- * for the workspace's device.  For callers that tear down the HIP runtime
- * themselves: call it before the runtime goes away. */
+/* bspai_release_workspace -- free the solvers' grow-only device workspaces
+ * (the Krylov bases and vectors that gmres_ir_solve keeps between calls: one
+ * for nrhs = 1, one for the column groups of nrhs > 1); the next solve
+ * allocates them again.  Waits for the workspaces' devices.  For callers that
+ * tear down the HIP runtime themselves: call it before the runtime goes
+ * away. */
 int bspai_release_workspace(void);
 
 /* bspai_free -- release a handle (NULL is ignored).  Waits for the device. */

@@ -214,6 +214,7 @@ int launch_mgs_persist(int n, int j, int m, const VT *z, VT *V, int64_t vstride,
 // Instrumentation shared by the solvers (solve.hip): the profiling switch
 // (bspai_set_profiling) and the totals of the one-launch MGS kernel.
 bool profiling_on();
+int release_batched_workspace();  // frees the column-group solve's kept device block
 bool mgs_profile_sample();  // whether to time the next one-launch MGS (one in seven)
 void add_mgs_profile(double ms, double bytes);
 // How the many-right-hand-side solve runs its columns (bspai_set_batch_mode):

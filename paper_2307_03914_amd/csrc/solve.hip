@@ -2213,6 +2213,7 @@ extern "C" int bspai_multi_wait(bspai_multi *plan, gmres_ir_stats *st_host, void
 extern "C" void bspai_multi_free(bspai_multi *plan) { multi_release(plan); }
 
 extern "C" int bspai_release_workspace(void) {
+  if (int rc = release_batched_workspace()) return rc;
   std::lock_guard<std::mutex> lock(g_ws.mu);
   if (!g_ws.ptr) return BSPAI_OK;
   int cur = 0;

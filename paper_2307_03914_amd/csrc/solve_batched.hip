@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -548,8 +550,39 @@ __global__ void k_to_vt_vals(int64_t nnz, const double *a, VT *o) {
 
 struct DevBuf {
   void *p = nullptr;
-  ~DevBuf() { dfree(p); }
+  bool own = true;  // false: carved from the grow-only block below
+  ~DevBuf() {
+    if (own) dfree(p);
+  }
 };
+
+// The column-group solve's per-call buffers come from one grow-only device
+// block that the library keeps between calls (bspai_release_workspace frees
+// it); a call that finds the block in use by another thread allocates its
+// own.  The holder's stream is idle whenever the lock is free.
+static struct {
+  std::mutex mu;
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+} g_bws;
+
+int release_batched_workspace() {
+  std::lock_guard<std::mutex> lock(g_bws.mu);
+  if (!g_bws.ptr) return BSPAI_OK;
+  int cur = 0;
+  BSPAI_HIP(hipGetDevice(&cur));
+  const int dev = g_bws.device;
+  if (cur != dev) BSPAI_HIP(hipSetDevice(dev));
+  const hipError_t e = hipDeviceSynchronize();
+  dfree(g_bws.ptr);
+  g_bws.ptr = nullptr;
+  g_bws.bytes = 0;
+  g_bws.device = -1;
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return fail(BSPAI_EHIP, "bspai_release_workspace: %s", hipGetErrorString(e));
+  return BSPAI_OK;
+}
 
 template <typename VT>
 int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, const bspai_handle *M,
@@ -576,12 +609,74 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
 
   // operators: A (or A^T) in FP64 and, inside GMRES, in u_g or bucketed (A_b
   // or A_b^T), M_b (or M_b^T), FP64 M for x_0
+  // the grow-only block's lock while this call uses the block; the stream
+  // drains before it is released (drain is destroyed first)
+  std::unique_lock<std::mutex> bws_lock;
+  struct Drain {
+    hipStream_t s;
+    const std::unique_lock<std::mutex> *l;
+    ~Drain() {
+      if (l->owns_lock()) (void)hipStreamSynchronize(s);
+    }
+  } drain{s, &bws_lock};
   DevBuf trp, tcol, tval, apv, rbuf, rv, wv, zv, Vb, dtmp, parts, scal, Hb, csb, snb, gb, yb, kcb, actb, mgsws;
   int rc;
-  if (mgs1) {
-    if ((rc = dalloc(&mgsws.p, mgs_persist_ws_bytes()))) return rc;
-    BSPAI_HIP(hipMemsetAsync(mgsws.p, 0, mgs_persist_ws_bytes(), s));
+  {
+    const std::pair<DevBuf *, size_t> want[] = {
+        {&mgsws, mgs1 ? mgs_persist_ws_bytes() : 0},
+        {&trp, tr ? 4 * ((size_t)n + 1) : 0},
+        {&tcol, tr ? 4 * (size_t)(nnz + 1) : 0},
+        {&tval, tr ? 8 * (size_t)(nnz + 1) : 0},
+        {&apv, !Ab ? sizeof(VT) * (size_t)(nnz + 1) : 0},
+        {&rbuf, 8 * (size_t)nr},
+        {&rv, sizeof(VT) * (size_t)nr},
+        {&wv, sizeof(VT) * (size_t)nr},
+        {&zv, sizeof(VT) * (size_t)nr},
+        {&Vb, sizeof(VT) * (size_t)nr * (m + 1)},
+        {&dtmp, 8 * (size_t)nr},
+        {&parts, 2 * 8 * (size_t)kBGrid * R},
+        {&scal, 8 * (8 * (size_t)R + 1)},
+        {&Hb, 8 * (size_t)R * m * (m + 1)},
+        {&csb, 8 * (size_t)R * m},
+        {&snb, 8 * (size_t)R * m},
+        {&gb, 8 * (size_t)R * (m + 1)},
+        {&yb, 8 * (size_t)R * m},
+        {&kcb, 4 * (size_t)R},
+        {&actb, 4 * (size_t)R}};
+    auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t total = 0;
+    for (const auto &w : want) total += a256(w.second);
+    std::unique_lock<std::mutex> wl(g_bws.mu, std::try_to_lock);
+    char *base = nullptr;
+    if (wl.owns_lock()) {
+      int dev = 0;
+      BSPAI_HIP(hipGetDevice(&dev));
+      if (g_bws.bytes < total || g_bws.device != dev) {
+        if (g_bws.ptr) {
+          (void)hipDeviceSynchronize();
+          dfree(g_bws.ptr);
+          g_bws.ptr = nullptr;
+          g_bws.bytes = 0;
+        }
+        if ((rc = dalloc(&g_bws.ptr, total))) return rc;
+        g_bws.bytes = total;
+        g_bws.device = dev;
+      }
+      base = static_cast<char *>(g_bws.ptr);
+    }
+    for (const auto &w : want) {
+      if (!w.second) continue;
+      if (base) {
+        w.first->p = base;
+        w.first->own = false;
+        base += a256(w.second);
+      } else if ((rc = dalloc(&w.first->p, w.second))) {
+        return rc;
+      }
+    }
+    if (wl.owns_lock()) bws_lock = std::move(wl);
   }
+  if (mgs1) BSPAI_HIP(hipMemsetAsync(mgsws.p, 0, mgs_persist_ws_bytes(), s));
   unsigned mgs_rounds = 0;  // exchange rounds of the MGS launches so far
   // per queued step: pinned host memory that the step's rotation kernel
   // fills with h_{j+1,j} and |g_{j+1}| of every column and the MGS abort
@@ -622,21 +717,9 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
   const int32_t *arp = A->row_ptr, *acol = A->col;
   const double *aval = A->val;
   if (tr) {
-    if ((rc = dalloc(&trp.p, 4 * ((size_t)n + 1))) || (rc = dalloc(&tcol.p, 4 * (size_t)(nnz + 1))) ||
-        (rc = dalloc(&tval.p, 8 * (size_t)(nnz + 1))))
-      return rc;
     if ((rc = csr_transpose(n, nnz, arp, acol, aval, 8, (int32_t *)trp.p, (int32_t *)tcol.p, tval.p, s))) return rc;
     arp = (const int32_t *)trp.p, acol = (const int32_t *)tcol.p, aval = (const double *)tval.p;
   }
-  if ((!Ab && (rc = dalloc(&apv.p, sizeof(VT) * (size_t)(nnz + 1)))) || (rc = dalloc(&rbuf.p, 8 * (size_t)nr)) ||
-      (rc = dalloc(&rv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&wv.p, sizeof(VT) * (size_t)nr)) ||
-      (rc = dalloc(&zv.p, sizeof(VT) * (size_t)nr)) || (rc = dalloc(&Vb.p, sizeof(VT) * (size_t)nr * (m + 1))) ||
-      (rc = dalloc(&dtmp.p, 8 * (size_t)nr)) || (rc = dalloc(&parts.p, 2 * 8 * (size_t)kBGrid * R)) ||
-      (rc = dalloc(&scal.p, 8 * (8 * (size_t)R + 1))) || (rc = dalloc(&Hb.p, 8 * (size_t)R * m * (m + 1))) ||
-      (rc = dalloc(&csb.p, 8 * (size_t)R * m)) || (rc = dalloc(&snb.p, 8 * (size_t)R * m)) ||
-      (rc = dalloc(&gb.p, 8 * (size_t)R * (m + 1))) || (rc = dalloc(&yb.p, 8 * (size_t)R * m)) ||
-      (rc = dalloc(&kcb.p, 4 * (size_t)R)) || (rc = dalloc(&actb.p, 4 * (size_t)R)))
-    return rc;
   VT *Ap = (VT *)apv.p, *RV = (VT *)rv.p, *W = (VT *)wv.p, *Z = (VT *)zv.p, *V = (VT *)Vb.p;
   double *r64 = (double *)rbuf.p, *D = (double *)dtmp.p, *P1 = (double *)parts.p, *P2 = P1 + (int64_t)kBGrid * R;
   double *S = (double *)scal.p;  // 8 rows of R scalars, then the MGS abort word
