@@ -322,25 +322,41 @@ int csr_to_sell(int n, const int32_t *rp, const int32_t *col, const void *val, i
 
 // ------------------------------------------------------------------ ELL
 
-__global__ void k_row_len_max(int n, const int32_t *rp, int32_t *mx) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicMax(mx, rp[i + 1] - rp[i]);
+// the longest row: a grid-stride maximum, one atomic per block
+__global__ void __launch_bounds__(256) k_row_len_max(int n, const int32_t *rp, int32_t *mx) {
+  int v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = max(v, rp[i + 1] - rp[i]);
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  __shared__ int32_t sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) v = max(v, sh[k]);
+    atomicMax(mx, v);
+  }
 }
 
+// one thread per ELL entry (row i = dst / w, slot u = dst % w), so that the
+// stores of a wave are contiguous; values move as whole 2-, 4- or 8-byte words.
+// Slots past the row's length hold column i and value 0.
 __global__ void k_ell_fill(int n, const int32_t *rp, const int32_t *col, const uint8_t *val, int vbytes, int w,
                            int32_t *ecol, uint8_t *eval) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int s = rp[i], e = rp[i + 1];
-  for (int u = 0; u < w; u++) {
-    int64_t dst = (int64_t)i * w + u;
-    if (s + u < e) {
-      ecol[dst] = col[s + u];
-      for (int b = 0; b < vbytes; b++) eval[dst * vbytes + b] = val[(int64_t)(s + u) * vbytes + b];
-    } else {
-      ecol[dst] = i;
-      for (int b = 0; b < vbytes; b++) eval[dst * vbytes + b] = 0;
-    }
+  const int64_t dst = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dst >= (int64_t)n * w) return;
+  const int i = (int)(dst / w), u = (int)(dst % w);
+  const int s = rp[i], e = rp[i + 1];
+  const bool in = s + u < e;
+  const int64_t src = (int64_t)s + u;
+  ecol[dst] = in ? col[src] : i;
+  if (vbytes == 8) {
+    reinterpret_cast<uint64_t *>(eval)[dst] = in ? reinterpret_cast<const uint64_t *>(val)[src] : 0ull;
+  } else if (vbytes == 4) {
+    reinterpret_cast<uint32_t *>(eval)[dst] = in ? reinterpret_cast<const uint32_t *>(val)[src] : 0u;
+  } else if (vbytes == 2) {
+    reinterpret_cast<uint16_t *>(eval)[dst] = in ? reinterpret_cast<const uint16_t *>(val)[src] : (uint16_t)0;
+  } else {
+    for (int b = 0; b < vbytes; b++) eval[dst * vbytes + b] = in ? val[src * vbytes + b] : (uint8_t)0;
   }
 }
 
@@ -354,7 +370,7 @@ int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, in
   int32_t hmx = 0, nnz = 0;
   auto body = [&]() -> int {
     BSPAI_HIP(hipMemsetAsync(mx, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_row_len_max, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, mx);
+    hipLaunchKernelGGL(k_row_len_max, dim3((unsigned)std::min(1024, (n + 255) / 256)), dim3(256), 0, s, n, rp, mx);
     BSPAI_CHECK_LAUNCH();
     BSPAI_HIP(hipMemcpyAsync(&hmx, mx, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BSPAI_HIP(hipMemcpyAsync(&nnz, rp + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -371,8 +387,8 @@ int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, in
     *ecol = nullptr, *evalp = nullptr;
     return rc;
   }
-  hipLaunchKernelGGL(k_ell_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, rp, col, static_cast<const uint8_t *>(val),
-                     vbytes, w, *ecol, static_cast<uint8_t *>(*evalp));
+  hipLaunchKernelGGL(k_ell_fill, dim3((unsigned)(((int64_t)n * w + 255) / 256)), dim3(256), 0, s, n, rp, col,
+                     static_cast<const uint8_t *>(val), vbytes, w, *ecol, static_cast<uint8_t *>(*evalp));
   BSPAI_CHECK_LAUNCH();
   BSPAI_HIP(hipStreamSynchronize(s));
   *width = w;
@@ -387,7 +403,8 @@ int csr_to_ell(int n, const int32_t *rp, const int32_t *col, const void *val, in
 // byte each, an index into a per-bucket table of offsets; otherwise, when every
 // offset fits 16 bits, two bytes each.
 
-__global__ void k_delta_range(int64_t ne, int w, const int32_t *ecol, int32_t *mm) {
+constexpr int kDeltaWaves = 4;  // waves per block of k_delta_range (256 threads)
+__global__ void __launch_bounds__(256) k_delta_range(int64_t ne, int w, const int32_t *ecol, int32_t *mm) {
   int32_t lo = INT32_MAX, hi = INT32_MIN;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
     int32_t d = ecol[e] - (int32_t)(e / w);
@@ -398,7 +415,18 @@ __global__ void k_delta_range(int64_t ne, int w, const int32_t *ecol, int32_t *m
     lo = min(lo, __shfl_xor(lo, o));
     hi = max(hi, __shfl_xor(hi, o));
   }
+  // one pair of atomics per block (every wave's would queue on two words)
+  __shared__ int32_t sh[2][kDeltaWaves];
   if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = lo;
+    sh[1][threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
+      lo = min(lo, sh[0][k]);
+      hi = max(hi, sh[1][k]);
+    }
     atomicMin(&mm[0], lo);
     atomicMax(&mm[1], hi);
   }
@@ -438,7 +466,7 @@ int ell_codes(int n, int w, const int32_t *ecol, void **code, int32_t **dict, in
     const int32_t init[2] = {INT32_MAX, INT32_MIN};
     int32_t hm[2];
     BSPAI_HIP(hipMemcpyAsync(mm, init, sizeof(init), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_delta_range, dim3(grid), dim3(256), 0, s, ne, w, ecol, mm);
+    hipLaunchKernelGGL(k_delta_range, dim3(std::min(grid, 1024u)), dim3(256), 0, s, ne, w, ecol, mm);
     BSPAI_CHECK_LAUNCH();
     BSPAI_HIP(hipMemcpyAsync(hm, mm, sizeof(hm), hipMemcpyDeviceToHost, s));
     BSPAI_HIP(hipStreamSynchronize(s));
