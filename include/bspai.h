@@ -181,7 +181,12 @@ typedef struct {
  *   own tests (a finished column takes no further corrections).  Needs
  *   device workspace of about (gmres_max + 5) n nrhs values of u_g.
  *   M: handle from bspai_build / bspai_import (keep_fp64_M for x0_mode 0,
- *   build_T for trans).  Synchronises `stream`.  Returns BSPAI_OK only when
+ *   build_T for trans).  Synchronises `stream`.  A solve's kernels keep every
+ *   compute unit of its GPU in grid-wide exchanges, so solves on one GPU run
+ *   one at a time: calls of the same kind (nrhs = 1, or nrhs > 1) from
+ *   several threads of a process wait for each other; a solve that overlaps
+ *   one of the other kind, or another process's, may end with BSPAI_EHIP
+ *   (an exchange timeout) rather than wait.  Returns BSPAI_OK only when
  *   every right-hand side met tol_rr or tol_be; otherwise the worst of ENAN,
  *   ENOCONV (i_max reached) and ESTAG (stagnated first), in that order, with
  *   x and the stats still written.

@@ -577,8 +577,8 @@ class MultiPlan:
 
 
 def release_workspace() -> None:
-    """Free the single-system solver's cached device workspace
-    (bspai_release_workspace); the next solve allocates it again."""
+    """Free the solvers' cached device workspaces, single-system and column
+    groups (bspai_release_workspace); the next solve allocates them again."""
     _check(_lib.bspai_release_workspace())
 
 

@@ -558,8 +558,9 @@ struct DevBuf {
 
 // The column-group solve's per-call buffers come from one grow-only device
 // block that the library keeps between calls (bspai_release_workspace frees
-// it); a call that finds the block in use by another thread allocates its
-// own.  The holder's stream is idle whenever the lock is free.
+// it).  A call holds the block's lock from start to end, so such solves from
+// several threads run one after another (their MGS kernels each need every
+// compute unit); the holder's stream is idle whenever the lock is free.
 static struct {
   std::mutex mu;
   void *ptr = nullptr;
@@ -646,35 +647,27 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
     auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
     size_t total = 0;
     for (const auto &w : want) total += a256(w.second);
-    std::unique_lock<std::mutex> wl(g_bws.mu, std::try_to_lock);
-    char *base = nullptr;
-    if (wl.owns_lock()) {
-      int dev = 0;
-      BSPAI_HIP(hipGetDevice(&dev));
-      if (g_bws.bytes < total || g_bws.device != dev) {
-        if (g_bws.ptr) {
-          (void)hipDeviceSynchronize();
-          dfree(g_bws.ptr);
-          g_bws.ptr = nullptr;
-          g_bws.bytes = 0;
-        }
-        if ((rc = dalloc(&g_bws.ptr, total))) return rc;
-        g_bws.bytes = total;
-        g_bws.device = dev;
+    bws_lock = std::unique_lock<std::mutex>(g_bws.mu);
+    int dev = 0;
+    BSPAI_HIP(hipGetDevice(&dev));
+    if (g_bws.bytes < total || g_bws.device != dev) {
+      if (g_bws.ptr) {
+        (void)hipDeviceSynchronize();
+        dfree(g_bws.ptr);
+        g_bws.ptr = nullptr;
+        g_bws.bytes = 0;
       }
-      base = static_cast<char *>(g_bws.ptr);
+      if ((rc = dalloc(&g_bws.ptr, total))) return rc;
+      g_bws.bytes = total;
+      g_bws.device = dev;
     }
+    char *base = static_cast<char *>(g_bws.ptr);
     for (const auto &w : want) {
       if (!w.second) continue;
-      if (base) {
-        w.first->p = base;
-        w.first->own = false;
-        base += a256(w.second);
-      } else if ((rc = dalloc(&w.first->p, w.second))) {
-        return rc;
-      }
+      w.first->p = base;
+      w.first->own = false;
+      base += a256(w.second);
     }
-    if (wl.owns_lock()) bws_lock = std::move(wl);
   }
   if (mgs1) BSPAI_HIP(hipMemsetAsync(mgsws.p, 0, mgs_persist_ws_bytes(), s));
   unsigned mgs_rounds = 0;  // exchange rounds of the MGS launches so far

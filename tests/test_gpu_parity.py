@@ -1202,6 +1202,41 @@ def test_solve_column_groups_match_oracle(B, u_g, ncols):
     h.free()
 
 
+def test_column_group_workspace_kept_and_released(B):
+    """The column-group solve keeps its device block between calls: a second
+    call reuses it, a larger one grows it, and after release_workspace the
+    next call allocates it again; every call gives the bits of the first."""
+    import torch
+
+    c = W.config("4a", small=True)
+    A, P = c["A"], c["P"]
+    rng = np.random.default_rng(47)
+    Bm = rng.standard_normal((A.n, 8))
+    kw = dict(tau=1e-4, tol_rr=1e-10, gmres_max=40, i_max=20)
+    B.set_batch_mode(2)
+    try:
+        Ad = B.CSRMatrix.from_host(A)
+        h = B.build(Ad, B.CSRMatrix.from_host(P), eps=c["eps"][0], precs=c["precs"])
+        b4 = _dev(Bm[:, :4])
+        runs = []
+        x, _ = B.solve(Ad, b4, h, **kw)
+        runs.append(x.cpu().numpy())
+        x, _ = B.solve(Ad, b4, h, **kw)  # the kept block
+        runs.append(x.cpu().numpy())
+        x8, _ = B.solve(Ad, _dev(Bm), h, **dict(kw, gmres_max=60))  # a larger block
+        B.release_workspace()
+        x, _ = B.solve(Ad, b4, h, **kw)  # allocated again
+        runs.append(x.cpu().numpy())
+        torch.cuda.synchronize()
+    finally:
+        B.set_batch_mode(0)
+    _say("workspace runs", len(runs))
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    assert np.isfinite(x8.cpu().numpy()).all()
+    h.free()
+
+
 def test_solve_batched_full_size(B):
     """128^3 anisotropic operator (n = 2,097,152) with all 64 right-hand sides
     in one call, as the benchmark runs it: each column meets the relative
