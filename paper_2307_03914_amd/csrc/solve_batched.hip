@@ -805,7 +805,7 @@ int solve_batched(const bspai_csr *A, const bspai_handle *Ab, const double *b, c
                        P2);
     BSPAI_CHECK_LAUNCH();
     if ((rc = finish(true, P1, S + 2 * R, 0)) || (rc = finish(true, P2, S + 3 * R, 0))) return rc;
-    if ((rc = to_host(S + 2 * R, hr, 2))) return rc;  // rows 2 and 3: ||r||, ||x|| per column
+    if ((rc = to_host(S + 2 * R, hr, 2))) return rc;  // rows 2 and 3: max|r|, max|x| per column
     int nact = 0;
     for (int c = 0; c < R; c++) {
       if (!active[c]) continue;
